@@ -1,0 +1,524 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: brute
+force numerical line integrals, closed-form Gaussian integrals and Fourier
+transforms, library routines (scipy rotations, naive DFT), symmetries and
+finite differences.  A plausible slip in the oracle (dropped normalisation,
+wrong sign of the shift, transposed pose, half-pixel origin, missing
+y-flip) fails at least one of them.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+from scipy.spatial.transform import Rotation
+
+from oracle import adam, ctf, model, objective
+from paper_2508_04929_amd import inputs
+
+
+def _mixture(rng, n, radius, sd_lo, sd_hi, iso=False):
+    sd = rng.uniform(sd_lo, sd_hi, size=(n, 1 if iso else 3))
+    sd = np.repeat(sd, 3, axis=1) if iso else sd
+    return inputs.Mixture(
+        means=rng.uniform(-radius, radius, size=(n, 3)).astype(np.float32),
+        log_scales=np.log(sd).astype(np.float32),
+        quats=(1.7 * inputs.haar_quaternions(rng, n)).astype(np.float32),
+        amps=rng.uniform(0.5, 2.0, size=n).astype(np.float32))
+
+
+def _views(rng, b, D, p, shift_px=0.0, defocus=(1e4, 2e4), astig=False):
+    v = inputs.views(rng, b, D, p, defocus_um=(defocus[0] / 1e4, defocus[1] / 1e4),
+                     shift_px_sd=shift_px)
+    if astig:
+        v.defocus_v = (v.defocus_u * rng.uniform(0.7, 1.3, size=b)).astype(np.float32)
+        v.astig = rng.uniform(-np.pi, np.pi, size=b).astype(np.float32)
+    # FP64 rotations orthogonal to rounding, so that closed forms that assume
+    # W^T = W^-1 hold to FP64 accuracy.
+    U, _, Vt = np.linalg.svd(v.rot.astype(np.float64))
+    v.rot = U @ Vt
+    return v
+
+
+# ---------------------------------------------------------------- rotations
+
+def test_quaternion_convention_matches_scipy():
+    rng = np.random.default_rng(0)
+    q = rng.standard_normal((50, 4)) * 2.0
+    R = model.rotation_from_quaternion(q)
+    # scipy stores quaternions scalar-last and normalises them.
+    R_ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+    np.testing.assert_allclose(R, R_ref, atol=1e-14)
+
+
+def test_covariance_is_R_S2_Rt():
+    rng = np.random.default_rng(1)
+    g = _mixture(rng, 20, 5.0, 0.5, 3.0)
+    S = model.covariance(g.log_scales, g.quats)
+    R = Rotation.from_quat(g.quats.astype(np.float64)[:, [1, 2, 3, 0]]).as_matrix()
+    s = np.exp(g.log_scales.astype(np.float64))
+    ref = np.einsum("nij,nj,nkj->nik", R, s ** 2, R)
+    np.testing.assert_allclose(S, ref, rtol=1e-13, atol=1e-13)
+    # eigenvalues are the squared scales
+    ev = np.sort(np.linalg.eigvalsh(S), axis=1)
+    np.testing.assert_allclose(ev, np.sort(s ** 2, axis=1), rtol=1e-12)
+
+
+# ---------------------------------------------------- PIN-1 line integrals
+
+def _brute_force_image(g, v, b):
+    """Eq. 1/3 from the definition: integrate the 3-D density along z.
+
+    The image at in-plane point r is the integral over z of
+    sum_n A_n N3(W^T([r, z] - [t, 0]); mu_n, Sigma_n) (W is a rotation, so
+    no Jacobian), evaluated by the composite trapezoid rule over +-12
+    standard deviations of each Gaussian's view-frame z extent.
+    """
+    D, p = v.D, v.pixel
+    c = D // 2
+    W = v.rot[b].astype(np.float64)
+    t = np.array([v.shift[b, 0], v.shift[b, 1], 0.0], dtype=np.float64)
+    R = Rotation.from_quat(g.quats.astype(np.float64)[:, [1, 2, 3, 0]]).as_matrix()
+    s = np.exp(g.log_scales.astype(np.float64))
+    img = np.zeros((D, D))
+    for n in range(g.n):
+        Sig = R[n] @ np.diag(s[n] ** 2) @ R[n].T
+        Sinv = np.linalg.inv(Sig)
+        norm = 1.0 / ((2 * np.pi) ** 1.5 * np.sqrt(np.linalg.det(Sig)))
+        mu = g.means[n].astype(np.float64)
+        zc = (W @ mu + t)[2]
+        zs = np.sqrt((W @ Sig @ W.T)[2, 2])
+        z = np.linspace(zc - 12 * zs, zc + 12 * zs, 4001)
+        for i in range(D):
+            for j in range(D):
+                r = np.stack([np.full_like(z, (j - c) * p), np.full_like(z, -(i - c) * p), z], 1)
+                x = (r - t) @ W - mu          # rows: W^T (r - t) - mu
+                f = np.exp(-0.5 * np.einsum("ki,ij,kj->k", x, Sinv, x))
+                img[i, j] += g.amps[n] * norm * integrate.trapezoid(f, z)
+    return img
+
+
+@pytest.mark.parametrize("D", [7, 8, 9, 16])
+def test_pin1_line_integral(D):
+    rng = np.random.default_rng(100 + D)
+    p = 1.0
+    g = _mixture(rng, 2, D * 0.25, 0.8, 2.0)
+    v = _views(rng, 2, D, p, shift_px=1.0)
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)
+    for b in range(2):
+        ref = _brute_force_image(g, v, b)
+        err = np.abs(Q[b] - ref).max() / np.abs(ref).max()
+        assert err < 1e-10, err
+
+
+# ---------------------------------------------------------- PIN-2 mass
+
+def test_pin2_mass_well_sampled():
+    rng = np.random.default_rng(2)
+    D, p = 96, 1.0
+    g = _mixture(rng, 40, 12.0, 1.5, 3.0)
+    v = _views(rng, 4, D, p)
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)
+    mass = p * p * Q.reshape(4, -1).sum(1)
+    np.testing.assert_allclose(mass, g.amps.astype(np.float64).sum(), rtol=1e-12)
+
+
+def test_pin2_mass_undersampled_lattice_sum():
+    """p^2 sum_ij G(r_ij) equals the Poisson lattice sum of its transform."""
+    rng = np.random.default_rng(3)
+    D, p = 48, 3.0
+    g = _mixture(rng, 1, 6.0, 1.0, 3.0)
+    v = _views(rng, 3, D, p, shift_px=0.3)
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)
+    R = Rotation.from_quat(g.quats.astype(np.float64)[:, [1, 2, 3, 0]]).as_matrix()[0]
+    Sig = R @ np.diag(np.exp(2 * g.log_scales[0].astype(np.float64))) @ R.T
+    c = D // 2
+    for b in range(3):
+        W = v.rot[b].astype(np.float64)
+        P = W[:2]
+        mu2 = P @ g.means[0] + v.shift[b]
+        S2 = P @ Sig @ P.T
+        # lattice: x = (j - c) p, y = -(i - c) p, i.e. spacing p through 0
+        ks = np.arange(-6, 7)
+        kx, ky = np.meshgrid(ks, ks, indexing="ij")
+        xi = np.stack([kx.ravel(), ky.ravel()], 1) / p
+        ref = np.sum(np.exp(-2 * np.pi ** 2 * np.einsum("ki,ij,kj->k", xi, S2, xi))
+                     * np.cos(2 * np.pi * xi @ mu2)) * g.amps[0]
+        assert abs(p * p * Q[b].sum() - ref) < 1e-12 * abs(ref)
+
+
+def test_pin2b_view_dependent_normalisation():
+    """Mass is view-invariant only with the 1/(2 pi |S~|^1/2) factor (Sec. 3.3.3)."""
+    rng = np.random.default_rng(4)
+    D, p = 128, 1.0
+    g = inputs.Mixture(means=np.zeros((1, 3), np.float32),
+                       log_scales=np.log(np.array([[1.5, 1.5, 8.0]], np.float32)),
+                       quats=np.array([[1, 0, 0, 0]], np.float32),
+                       amps=np.ones(1, np.float32))
+    v = _views(rng, 100, D, p)
+    cov = model.covariance(g.log_scales, g.quats)
+    mu2, cov2 = model.project(g.means, cov, v.rot, v.shift)
+    masses, unnorm = [], []
+    for b in range(100):
+        Q = model.splat_image(mu2[b], cov2[b], np.ones(1), D, p, model.Q_FAITHFUL)
+        masses.append(Q.sum())
+        det = np.linalg.det(cov2[b, 0])
+        unnorm.append(Q.sum() * 2 * np.pi * np.sqrt(det))    # 3DGS-style splat
+    np.testing.assert_allclose(masses, 1.0, rtol=1e-12)
+    assert np.std(unnorm) / np.mean(unnorm) > 0.2
+
+
+def test_pin2_ctf_dc_term():
+    rng = np.random.default_rng(5)
+    g = _mixture(rng, 30, 10.0, 1.5, 3.0)
+    v = _views(rng, 2, 64, 1.0)
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, 64, 1.0)
+    X = ctf.apply_ctf(Q, ctf.ctf_grid_for(v))
+    np.testing.assert_allclose(X.reshape(2, -1).sum(1), -v.amp_contrast * Q.reshape(2, -1).sum(1),
+                               rtol=1e-12)
+
+
+# ------------------------------------------------ PIN-3 FFT-centred origin
+
+@pytest.mark.parametrize("D", [4, 5, 8, 9])
+def test_pin3_centred_delta(D):
+    c = D // 2
+    delta = np.zeros((D, D))
+    delta[c, c] = 1.0
+    F = np.fft.fft2(np.fft.ifftshift(delta))
+    np.testing.assert_allclose(F, np.ones((D, D)), atol=1e-15)
+
+
+def test_pin3_four_by_four_example():
+    """A narrow Gaussian at the origin peaks at pixel (2, 2) when D = 4."""
+    g = inputs.Mixture(means=np.zeros((1, 3), np.float32),
+                       log_scales=np.full((1, 3), np.log(0.3), np.float32),
+                       quats=np.array([[1, 0, 0, 0]], np.float32), amps=np.ones(1, np.float32))
+    v = _views(np.random.default_rng(6), 1, 4, 1.0)
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, 4, 1.0)[0]
+    assert np.unravel_index(np.argmax(Q), Q.shape) == (2, 2)
+    s = np.exp(np.float64(g.log_scales[0, 0]))
+    np.testing.assert_allclose(Q[2, 2], 1.0 / (2 * np.pi * s * s), rtol=1e-12)
+
+
+def test_pin3_psf_centred_and_symmetric():
+    D, p = 64, 1.0
+    rng = np.random.default_rng(7)
+    v = _views(rng, 1, D, p)
+    H = ctf.ctf_grid_for(v)
+    delta = np.zeros((1, D, D))
+    c = D // 2
+    delta[0, c, c] = 1.0
+    psf = ctf.apply_ctf(delta, H)[0]
+    # point symmetric about (c, c) on the periodic grid
+    idx = (2 * c - np.arange(D)) % D
+    np.testing.assert_allclose(psf, psf[np.ix_(idx, idx)], atol=1e-15)
+    assert abs(psf.sum() - (-v.amp_contrast)) < 1e-13
+
+
+def test_pin3_half_pixel_origin_phase_error():
+    """The image-centred origin ((D-1)/2) shifts the DFT phase by -pi k/D."""
+    D, p = 32, 1.0
+    g = inputs.Mixture(means=np.array([[1.3, -0.7, 0.4]], np.float32),
+                       log_scales=np.full((1, 3), np.log(2.0), np.float32),
+                       quats=np.array([[1, 0, 0, 0]], np.float32), amps=np.ones(1, np.float32))
+    v = _views(np.random.default_rng(8), 1, D, p)
+    v.rot = np.eye(3)[None]
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)[0]
+    # image-centred rendering = origin half a pixel up-left = shift by (-1/2, +1/2) A
+    shift = np.array([[-0.5 * p, 0.5 * p]], np.float32)
+    Qc = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, shift, D, p)[0]
+    F, Fc = np.fft.fft(Q.sum(0)), np.fft.fft(Qc.sum(0))
+    k = np.fft.fftfreq(D) * D
+    ratio = Fc / F
+    # below D/4 the aliased copies of a 2-px Gaussian are below 1e-17
+    low = np.abs(k) <= D // 4
+    np.testing.assert_allclose(np.angle(ratio[low]), (np.pi * k / D)[low], atol=1e-9)
+    np.testing.assert_allclose(np.abs(ratio[low]), 1.0, atol=1e-9)
+
+
+# ----------------------------------------------------------- PIN-4 CTF
+
+def test_pin4_wavelength():
+    assert abs(ctf.electron_wavelength(300.0) - 0.0196875) < 1e-6
+    assert abs(ctf.electron_wavelength(200.0) - 0.0250793) < 1e-6
+
+
+def test_pin4_ctf_closed_form_cartesian():
+    """Grid values equal an independent Cartesian statement of the CTF."""
+    rng = np.random.default_rng(9)
+    D, p = 48, 1.3
+    v = _views(rng, 3, D, p, astig=True)
+    v.phase = rng.uniform(0, 0.5, 3).astype(np.float32)
+    v.bfactor = 40.0
+    H = ctf.ctf_grid_for(v)
+    lam = ctf.electron_wavelength(300.0)   # pinned by test_pin4_wavelength
+    f = np.fft.fftfreq(D, d=p)
+    for b in range(3):
+        du, dv_, a = float(v.defocus_u[b]), float(v.defocus_v[b]), float(v.astig[b])
+        for ky in range(1, D):
+            for kx in range(1, D):
+                if ky == D // 2 or kx == D // 2:
+                    continue
+                sx, sy = f[kx], -f[ky]
+                s2 = sx * sx + sy * sy
+                # cos 2(alpha - a) from Cartesian components
+                c2 = ((sx * sx - sy * sy) * np.cos(2 * a) + 2 * sx * sy * np.sin(2 * a)) / s2
+                df = 0.5 * (du + dv_) + 0.5 * (du - dv_) * c2
+                chi = np.pi * lam * df * s2 - 0.5 * np.pi * 2.7e7 * lam ** 3 * s2 ** 2 - v.phase[b]
+                ref = -(np.sqrt(0.99) * np.sin(chi) + 0.1 * np.cos(chi)) * np.exp(-10.0 * s2)
+                assert abs(H[b, ky, kx] - ref) < 1e-12
+
+
+def test_pin4_ctf_special_values():
+    s = np.linspace(0, 0.3, 2001)
+    h0 = ctf.ctf_polar(0.0, 0.0, 1e4, 1e4, 0.0, 0.0, 300.0, 2.7, 0.1)
+    assert abs(h0 + 0.1) < 1e-15
+    # Cs = 0, w = 0: zeros exactly at s^2 = n / (lam df)
+    lam = ctf.electron_wavelength(300.0)
+    df = 1.5e4
+    for n in range(1, 6):
+        sn = np.sqrt(n / (lam * df))
+        assert abs(ctf.ctf_polar(sn, 0.3, df, df, 0.0, 0.0, 300.0, 0.0, 0.0)) < 1e-9
+    h = ctf.ctf_polar(s, 0.0, df, df, 0.0, 0.0, 300.0, 2.7, 0.1)
+    assert h[1] < 0   # negative at low frequency under underfocus
+
+
+def test_pin4_grid_even_and_output_real():
+    rng = np.random.default_rng(10)
+    for D in (32, 33):
+        v = _views(rng, 2, D, 1.1, astig=True)
+        H = ctf.ctf_grid_for(v)
+        neg = (-np.arange(D)) % D
+        np.testing.assert_allclose(H, H[:, neg][:, :, neg], atol=1e-15)
+        Q = rng.standard_normal((2, D, D))
+        Z = np.fft.ifft2(H * np.fft.fft2(Q))
+        assert np.abs(Z.imag).max() < 1e-15 * np.abs(Z.real).max() * D
+
+
+# ----------------------------------------------------- PIN-5 Fourier slice
+
+def test_pin5_fourier_slice():
+    """p^2 DFT(Q) equals the 3-D transform on the central slice (Eq. 11)."""
+    rng = np.random.default_rng(11)
+    D, p = 128, 1.0
+    g = _mixture(rng, 6, 8.0, 2.5, 3.5)
+    v = _views(rng, 3, D, p, shift_px=2.0)
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)
+    R = Rotation.from_quat(g.quats.astype(np.float64)[:, [1, 2, 3, 0]]).as_matrix()
+    s = np.exp(g.log_scales.astype(np.float64))
+    Sig = np.einsum("nij,nj,nkj->nik", R, s ** 2, R)
+    c = D // 2
+    f = np.fft.fftfreq(D) * D
+    KX, KY = np.meshgrid(f, f)                       # [ky, kx]
+    k3 = np.stack([KX / (D * p), -KY / (D * p), np.zeros_like(KX)], -1)
+    idx = np.arange(D)
+    origin = np.exp(-2j * np.pi * (idx[None, :] + idx[:, None]) * c / D)
+    for b in range(3):
+        W = v.rot[b].astype(np.float64)
+        xi = k3 @ W                                   # W^T k, world frequency
+        t = np.array([v.shift[b, 0], v.shift[b, 1], 0.0])
+        Vhat = np.zeros((D, D), complex)
+        for n in range(g.n):
+            quad = np.einsum("...i,ij,...j->...", xi, Sig[n], xi)
+            Vhat += g.amps[n] * np.exp(-2j * np.pi * xi @ g.means[n].astype(np.float64)) \
+                * np.exp(-2 * np.pi ** 2 * quad)
+        ref = Vhat * np.exp(-2j * np.pi * (k3 @ t)) * origin
+        got = p * p * np.fft.fft2(Q[b])
+        assert np.abs(got - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+# -------------------------------------------------------- PIN-6 isotropic
+
+def test_pin6_isotropic_reduction():
+    rng = np.random.default_rng(12)
+    D, p = 40, 1.0
+    g = _mixture(rng, 5, 6.0, 1.0, 2.5, iso=True)
+    v = _views(rng, 2, D, p, shift_px=1.5)
+    Q = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)
+    xs, ys = (np.arange(D) - D // 2) * p, -(np.arange(D) - D // 2) * p
+    for b in range(2):
+        ref = np.zeros((D, D))
+        for n in range(g.n):
+            sd = float(np.exp(np.float64(g.log_scales[n, 0])))
+            m = v.rot[b].astype(np.float64) @ g.means[n]
+            m = m[:2] + v.shift[b]
+            r2 = (xs[None, :] - m[0]) ** 2 + (ys[:, None] - m[1]) ** 2
+            ref += float(g.amps[n]) / (2 * np.pi * sd * sd) * np.exp(-r2 / (2 * sd * sd))
+        np.testing.assert_allclose(Q[b], ref, rtol=1e-11, atol=1e-15)
+    # invariance to the quaternion and zero quaternion gradient
+    g2 = dataclasses.replace(g, quats=inputs.haar_quaternions(rng, g.n).astype(np.float32))
+    Q2 = model.render_pre_ctf(g2.means, g2.log_scales, g2.quats, g2.amps, v.rot, v.shift, D, p)
+    np.testing.assert_allclose(Q, Q2, rtol=1e-12, atol=1e-16)
+    Y = rng.standard_normal(Q.shape) * 0.01
+    gr = objective.loss_and_grad(g, v, Y)["grads"]
+    assert np.abs(gr["quats"]).max() < 1e-12 * np.abs(gr["means"]).max()
+    # A uniform change of all three log-scales keeps the Gaussian isotropic,
+    # so the summed log-scale gradient cannot depend on the quaternion (a
+    # single-axis change breaks isotropy along R e_k and does depend on it).
+    gr2 = objective.loss_and_grad(g2, v, Y)["grads"]
+    np.testing.assert_allclose(gr["log_scales"].sum(1), gr2["log_scales"].sum(1), rtol=1e-10)
+    np.testing.assert_allclose(gr["means"], gr2["means"], rtol=1e-10, atol=1e-14)
+
+
+# -------------------------------------------------------- PIN-7 symmetries
+
+def test_pin7_integer_shift_is_roll():
+    rng = np.random.default_rng(13)
+    D, p = 64, 1.5
+    g = _mixture(rng, 10, 12.0, 1.5, 3.0)
+    v = _views(rng, 1, D, p)
+    Q0 = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)[0]
+    shift = np.array([[3 * p, -2 * p]], np.float32)
+    Q1 = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, shift, D, p)[0]
+    # +3 px in x = 3 columns right; -2 px in y = 2 rows down (y-flip)
+    np.testing.assert_allclose(Q1, np.roll(np.roll(Q0, 3, axis=1), 2, axis=0), atol=1e-12 * Q0.max())
+
+
+def test_pin7_inplane_rotation_is_permutation():
+    rng = np.random.default_rng(14)
+    D, p = 32, 1.0
+    g = _mixture(rng, 6, 5.0, 1.0, 2.0)
+    v = _views(rng, 1, D, p)
+    Q0 = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, D, p)[0]
+    Rz = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]], np.float64)
+    rot = (Rz @ v.rot[0])[None]
+    Q1 = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, rot, v.shift, D, p)[0]
+    c = D // 2
+    ii, jj = np.meshgrid(np.arange(1, D), np.arange(1, D), indexing="ij")
+    np.testing.assert_allclose(Q1[ii, jj], Q0[jj, 2 * c - ii], atol=1e-13 * Q0.max())
+
+
+def test_pin7_linear_in_amplitude_and_permutation_invariant():
+    rng = np.random.default_rng(15)
+    D, p = 32, 1.0
+    g = _mixture(rng, 8, 5.0, 1.0, 2.0)
+    v = _views(rng, 2, D, p)
+    f = lambda gg: model.render_pre_ctf(gg.means, gg.log_scales, gg.quats, gg.amps,
+                                        v.rot, v.shift, D, p)
+    Q = f(g)
+    a2 = rng.uniform(0.1, 1.0, g.n)
+    Qa = f(dataclasses.replace(g, amps=a2))
+    Qs = f(dataclasses.replace(g, amps=g.amps.astype(np.float64) + a2))
+    np.testing.assert_allclose(Qs, Q + Qa, rtol=1e-12, atol=1e-15)
+    perm = rng.permutation(g.n)
+    gp = inputs.Mixture(g.means[perm], g.log_scales[perm], g.quats[perm], g.amps[perm])
+    np.testing.assert_allclose(f(gp), Q, rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------ PIN-8 adjointness
+
+def test_pin8_ctf_self_adjoint_and_parseval():
+    rng = np.random.default_rng(16)
+    v = _views(rng, 2, 40, 1.2, astig=True)
+    H = ctf.ctf_grid_for(v)
+    u = rng.standard_normal((2, 40, 40))
+    w = rng.standard_normal((2, 40, 40))
+    lhs = np.sum(ctf.apply_ctf(u, H) * w)
+    rhs = np.sum(u * ctf.apply_ctf(w, H))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    X = ctf.apply_ctf(u, H)
+    direct = np.sum((X - w) ** 2)
+    fourier = np.sum(np.abs(np.fft.fft2(X - w)) ** 2) / 40 ** 2
+    assert abs(direct - fourier) < 1e-12 * direct
+
+
+# ------------------------------------------------------ PIN-9 gradients
+
+@pytest.mark.parametrize("acts", [("exp", "identity"), ("softplus", "softplus")])
+@pytest.mark.parametrize("reduction", ["sum", "mean"])
+def test_pin9_gradient_vs_finite_differences(acts, reduction):
+    rng = np.random.default_rng(17)
+    D, p = 24, 1.0
+    g = _mixture(rng, 4, 4.0, 0.8, 2.0)
+    v = _views(rng, 3, D, p, shift_px=1.0, astig=True)
+    Y = rng.standard_normal((3, D, D)) * 0.01
+    kw = dict(scale_act=acts[0], amp_act=acts[1], reduction=reduction)
+    out = objective.loss_and_grad(g, v, Y, **kw)
+    for field in ("means", "log_scales", "quats", "amps"):
+        arr = getattr(g, field)
+        ent = list(np.ndindex(arr.shape))
+        fd = objective.finite_difference(g, v, Y, field, ent, **kw)
+        an = np.array([out["grads"][field][e] for e in ent])
+        assert np.abs(fd - an).max() <= 1e-7 * np.abs(an).max(), field
+    gq = out["grads"]["quats"]
+    q64 = g.quats.astype(np.float64)
+    qhat = q64 / np.linalg.norm(q64, axis=1, keepdims=True)
+    assert np.abs((gq * qhat).sum(1)).max() < 1e-12 * np.abs(gq).max()
+
+
+def test_pin9_global_translation():
+    rng = np.random.default_rng(18)
+    D, p = 24, 1.0
+    g = _mixture(rng, 4, 4.0, 0.8, 2.0)
+    v = _views(rng, 2, D, p)
+    Y = rng.standard_normal((2, D, D)) * 0.01
+    gm = objective.loss_and_grad(g, v, Y)["grads"]["means"].sum(0)
+    h = 1e-6
+    for k in range(3):
+        vals = []
+        for sg in (1, -1):
+            m = g.means.astype(np.float64).copy()
+            m[:, k] += sg * h
+            vals.append(objective.forward(dataclasses.replace(g, means=m), v, Y)["loss"])
+        assert abs((vals[0] - vals[1]) / (2 * h) - gm[k]) < 1e-7 * np.abs(gm).max()
+
+
+# ------------------------------------------------------ PIN-10 truncation
+
+def test_pin10_truncation_modes():
+    g, v, _ = inputs.c1(b=4)
+    full = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift, v.D, v.pixel)
+    faithful = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift,
+                                    v.D, v.pixel, model.Q_FAITHFUL)
+    matched = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, v.rot, v.shift,
+                                   v.D, v.pixel, 2 * np.log(1e6))
+    for b in range(4):
+        scale = np.abs(full[b]).max()
+        assert np.abs(faithful[b] - full[b]).max() <= 1e-13 * scale
+        assert np.abs(matched[b] - full[b]).max() <= 3e-6 * scale
+
+
+# ------------------------------------------------------ PIN-11 DFT
+
+@pytest.mark.parametrize("D", [6, 9, 16])
+def test_pin11_fft_is_dft(D):
+    rng = np.random.default_rng(D)
+    x = rng.standard_normal((D, D))
+    k = np.arange(D)
+    Fm = np.exp(-2j * np.pi * np.outer(k, k) / D)
+    ref = Fm @ x @ Fm.T
+    np.testing.assert_allclose(np.fft.fft2(x), ref, atol=1e-12 * np.abs(ref).max())
+
+
+# ------------------------------------------------------ PIN-12 Haar sampler
+
+def test_pin12_haar_rotations():
+    rng = np.random.default_rng(19)
+    R = inputs.haar_rotations(rng, 20000)
+    np.testing.assert_allclose(np.einsum("bji,bjk->bik", R, R), np.eye(3)[None].repeat(20000, 0), atol=1e-12)
+    assert np.all(np.linalg.det(R) > 0)
+    ang = np.arccos(np.clip((np.trace(R, axis1=1, axis2=2) - 1) / 2, -1, 1))
+    assert abs(ang.mean() - (np.pi / 2 + 2 / np.pi)) < 0.01
+    ks = stats.kstest(ang, lambda t: (t - np.sin(t)) / np.pi)
+    assert ks.pvalue > 1e-3
+    assert np.abs(R.mean(0)).max() < 0.02
+    q = inputs.haar_quaternions(rng, 20000)
+    angq = 2 * np.arccos(np.clip(np.abs(q[:, 0]), 0, 1))
+    assert stats.kstest(angq, lambda t: (t - np.sin(t)) / np.pi).pvalue > 1e-3
+
+
+# ------------------------------------------------------------ Adam
+
+def test_adam_first_steps_closed_form():
+    rng = np.random.default_rng(20)
+    p0 = rng.standard_normal(100)
+    g1 = rng.standard_normal(100)
+    p1, m, v = adam.adam_step(p0, g1, 0, 0, 1, lr=1e-3, eps=0.0)
+    np.testing.assert_allclose(p1, p0 - 1e-3 * np.sign(g1), rtol=0, atol=1e-15)
+    g2 = rng.standard_normal(100)
+    p2, _, _ = adam.adam_step(p1, g2, m, v, 2, lr=1e-3, eps=0.0)
+    mh = (0.9 * 0.1 * g1 + 0.1 * g2) / (1 - 0.81)
+    vh = (0.999 * 0.001 * g1 ** 2 + 0.001 * g2 ** 2) / (1 - 0.999 ** 2)
+    np.testing.assert_allclose(p2, p1 - 1e-3 * mh / np.sqrt(vh), rtol=1e-12)
