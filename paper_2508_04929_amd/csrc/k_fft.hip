@@ -1,0 +1,318 @@
+// Fourier-space CTF application, loss and adjoint (App. A.2, Eq. 14; Sec. 3.3.5).
+//
+// X = F^-1(H^ . F(Q)) is computed as
+//   rows:     real FFT of every row (two rows packed as one complex FFT)
+//   columns:  for each of the D/2+1 half-spectrum columns: FFT over rows,
+//             multiply by H^ (real, evaluated on the fly with an FP64 phase)
+//             and the 1/D^2 normalisation, inverse FFT over rows
+//   rows:     inverse real FFT of every row (two rows packed again)
+// Every transform is a mixed-radix (4, 2, 3) Stockham FFT in LDS with
+// twiddles from a host-built FP64-accurate table.  Because H^ is real and
+// even, the same column pass is its own adjoint, so the loss gradient
+// G_Q = F^-1(H^ . F(G_X)) reuses the three passes; the row pass between the
+// two applications fuses the inverse rows of X, the residual X - Y, the
+// squared-error partial sums and the forward rows of G_X.
+#include "cs_internal.hpp"
+
+namespace cs {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One Stockham transform of length P.L by a team of `ts` threads (thread
+// index t within the team).  x holds the input, y is scratch; returns the
+// buffer that holds the result.  Every thread of the block must call it
+// (it synchronises the block after every stage).
+__device__ float2 *fft_team(float2 *x, float2 *y, const FftPlan &P, const float2 *tw, int t,
+                            int ts, bool inverse) {
+  const int L = P.L;
+  int Ns = 1;
+  const float sg = inverse ? 1.f : -1.f;  // sign of the exponent
+  for (int st = 0; st < P.nst; ++st) {
+    const int R = P.radix[st];
+    const int LR = L / R;
+    const int tws = L / (Ns * R);
+    for (int j = t; j < LR; j += ts) {
+      const int k = j % Ns;
+      const int base = (j / Ns) * Ns * R + k;
+      if (R == 4) {
+        float2 v0 = x[j], v1 = x[j + LR], v2 = x[j + 2 * LR], v3 = x[j + 3 * LR];
+        if (k) {
+          float2 w1 = tw[k * tws], w2 = tw[2 * k * tws], w3 = tw[3 * k * tws];
+          if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+          v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
+        }
+        const float2 a0 = make_float2(v0.x + v2.x, v0.y + v2.y);
+        const float2 a1 = make_float2(v0.x - v2.x, v0.y - v2.y);
+        const float2 a2 = make_float2(v1.x + v3.x, v1.y + v3.y);
+        const float2 a3 = make_float2(v1.x - v3.x, v1.y - v3.y);
+        // y1 = a1 + sg*i*a3, y3 = a1 - sg*i*a3
+        y[base] = make_float2(a0.x + a2.x, a0.y + a2.y);
+        y[base + Ns] = make_float2(a1.x - sg * a3.y, a1.y + sg * a3.x);
+        y[base + 2 * Ns] = make_float2(a0.x - a2.x, a0.y - a2.y);
+        y[base + 3 * Ns] = make_float2(a1.x + sg * a3.y, a1.y - sg * a3.x);
+      } else if (R == 2) {
+        float2 v0 = x[j], v1 = x[j + LR];
+        if (k) {
+          float2 w1 = tw[k * tws];
+          if (inverse) w1.y = -w1.y;
+          v1 = cmul(v1, w1);
+        }
+        y[base] = make_float2(v0.x + v1.x, v0.y + v1.y);
+        y[base + Ns] = make_float2(v0.x - v1.x, v0.y - v1.y);
+      } else {  // R == 3
+        float2 v0 = x[j], v1 = x[j + LR], v2 = x[j + 2 * LR];
+        if (k) {
+          float2 w1 = tw[k * tws], w2 = tw[2 * k * tws];
+          if (inverse) { w1.y = -w1.y; w2.y = -w2.y; }
+          v1 = cmul(v1, w1); v2 = cmul(v2, w2);
+        }
+        const float c3 = 0.86602540378443864676f;  // sqrt(3)/2
+        const float2 t1 = make_float2(v1.x + v2.x, v1.y + v2.y);
+        const float2 t2 = make_float2(v1.x - v2.x, v1.y - v2.y);
+        const float2 m = make_float2(v0.x - 0.5f * t1.x, v0.y - 0.5f * t1.y);
+        // y1 = m + sg*i*c3*t2, y2 = m - sg*i*c3*t2
+        y[base] = make_float2(v0.x + t1.x, v0.y + t1.y);
+        y[base + Ns] = make_float2(m.x - sg * c3 * t2.y, m.y + sg * c3 * t2.x);
+        y[base + 2 * Ns] = make_float2(m.x + sg * c3 * t2.y, m.y - sg * c3 * t2.x);
+      }
+    }
+    __syncthreads();
+    float2 *tmp = x; x = y; y = tmp;
+    Ns *= R;
+  }
+  return x;
+}
+
+// Rows per block in the row kernels: 4 teams of 64 threads, one row pair each.
+constexpr int kRowTeams = 4;
+
+// ---------------------------------------------------------------------------
+// Forward row pass: spec[b][r][0..D/2] = rFFT(src[b][r][:]) for every row.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split_store(const float2 *res, int L, int t, float2 *spec_a,
+                                            float2 *spec_b, bool valid) {
+  for (int k = t; k <= L / 2; k += 64) {
+    const float2 Z = res[k];
+    const float2 Zm = res[(L - k) % L];
+    // A = (Z + conj(Zm)) / 2,  B = (Z - conj(Zm)) / (2i)
+    const float dx = Z.x - Zm.x, dy = Z.y + Zm.y;
+    if (valid) {
+      spec_a[k] = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+      spec_b[k] = make_float2(0.5f * dy, -0.5f * dx);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_fft_rows_fwd(const float *src, FftPlan P, const float2 *tw, int B, float2 *spec) {
+  extern __shared__ float2 lds[];
+  const int L = P.L, Dh = L / 2 + 1;
+  const int team = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int pr = blockIdx.x * kRowTeams + team;  // row pair
+  const int b = blockIdx.y;
+  const bool valid = pr < L / 2;
+  float2 *x = lds + team * 2 * L, *y = x + L;
+  const float *ra = src + ((size_t)b * L + 2 * pr) * L;
+  for (int j = t; j < L; j += 64) x[j] = valid ? make_float2(ra[j], ra[L + j]) : make_float2(0.f, 0.f);
+  __syncthreads();
+  const float2 *res = fft_team(x, y, P, tw, t, 64, false);
+  float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
+  split_store(res, L, t, sa, sa + Dh, valid);
+}
+
+// ---------------------------------------------------------------------------
+// CTF on the DFT grid.  Index k has frequency f(k)/(D p) with f(k) = k for
+// k < D/2 (k = D/2 maps to -D/2) and k - D above; the row frequency is
+// negated (y-flip of Eq. 13).  The Nyquist row/column value is the mean
+// over the two mirror frequencies, which keeps H^ exactly even.
+// ---------------------------------------------------------------------------
+__device__ double ctf_at(double sx, double sy, const CtfDev &c, double du, double dv,
+                         double c2a, double s2a, double ph) {
+  const double s2 = sx * sx + sy * sy;
+  double df = 0.5 * (du + dv);
+  if (s2 > 0.0 && du != dv) {
+    const double cos2 = (sx * sx - sy * sy) / s2, sin2 = 2.0 * sx * sy / s2;
+    df += 0.5 * (du - dv) * (cos2 * c2a + sin2 * s2a);
+  }
+  const double chi = M_PI * c.lam * df * s2 - 0.5 * M_PI * c.cs * c.lam * c.lam * c.lam * s2 * s2 - ph;
+  double sn, cs;
+  sincos(chi, &sn, &cs);
+  double h = -(sqrt(1.0 - c.w * c.w) * sn + c.w * cs);
+  if (c.bfactor != 0.0) h *= exp(-0.25 * c.bfactor * s2);
+  return h;
+}
+
+__device__ float ctf_grid_value(int ky, int kx, int L, float pixel, const CtfDev &c, int b) {
+  const double du = c.defocus_u[b], dv = c.defocus_v[b];
+  const double a = c.astig ? (double)c.astig[b] : 0.0;
+  const double ph = c.phase ? (double)c.phase[b] : 0.0;
+  const double c2a = cos(2.0 * a), s2a = sin(2.0 * a);
+  const int half = L / 2;
+  const double inv = 1.0 / ((double)L * (double)pixel);
+  const int fkx = (kx < (L + 1) / 2) ? kx : kx - L;
+  const int fky = (ky < (L + 1) / 2) ? ky : ky - L;
+  const double sx = fkx * inv, sy = -fky * inv;
+  double h = ctf_at(sx, sy, c, du, dv, c2a, s2a, ph);
+  if ((L % 2 == 0) && (kx == half || ky == half)) {
+    const double mx = (kx == half) ? -sx : sx, my = (ky == half) ? -sy : sy;
+    h = 0.5 * (h + ctf_at(mx, my, c, du, dv, c2a, s2a, ph));
+  }
+  return (float)h;
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: for cpw adjacent half-spectrum columns per block, FFT over
+// rows, times H^ / D^2, inverse FFT over rows, in place.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, float pixel,
+               CtfDev ctf) {
+  extern __shared__ float2 lds[];
+  const int L = P.L, Dh = L / 2 + 1;
+  const int b = blockIdx.y;
+  const int kx0 = blockIdx.x * cpw;
+  const int ts = 256 / cpw;
+  const int team = threadIdx.x / ts, t = threadIdx.x % ts;
+  float2 *img = spec + (size_t)b * L * Dh;
+  // coalesced load: consecutive threads take consecutive columns of a row
+  for (int q = threadIdx.x; q < cpw * L; q += 256) {
+    const int c = q % cpw, r = q / cpw;
+    const int kx = kx0 + c;
+    lds[c * 2 * L + r] = (kx < Dh) ? img[(size_t)r * Dh + kx] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2 *x = lds + team * 2 * L, *y = x + L;
+  float2 *res = fft_team(x, y, P, tw, t, ts, false);
+  const int kx = kx0 + team;
+  const float norm = 1.f / ((float)L * (float)L);
+  for (int ky = t; ky < L; ky += ts) {
+    const float h = (ctf.enabled && kx < Dh) ? ctf_grid_value(ky, kx, L, pixel, ctf, b) : 1.f;
+    const float2 z = res[ky];
+    res[ky] = make_float2(z.x * h * norm, z.y * h * norm);
+  }
+  __syncthreads();
+  float2 *other = (res == x) ? y : x;
+  float2 *out = fft_team(res, other, P, tw, t, ts, true);
+  // every team's result sits in the same half of its buffer pair
+  const int oofs = (int)(out - (lds + team * 2 * L));
+  for (int q = threadIdx.x; q < cpw * L; q += 256) {
+    const int c = q % cpw, r = q / cpw;
+    const int kc = kx0 + c;
+    if (kc < Dh) img[(size_t)r * Dh + kc] = lds[c * 2 * L + oofs + r];
+  }
+}
+
+// Hermitian-packed inverse of two half-spectrum rows into one complex row.
+__device__ __forceinline__ void pack_inverse(const float2 *sa, const float2 *sb, int L, int t,
+                                             float2 *x, bool valid) {
+  const int half = L / 2;
+  for (int k = t; k < L; k += 64) {
+    float2 A, Bv;
+    if (!valid) {
+      A = Bv = make_float2(0.f, 0.f);
+    } else if (k <= half) {
+      A = sa[k];
+      Bv = sb[k];
+      if (k == 0 || (k == half && (L % 2 == 0))) { A.y = 0.f; Bv.y = 0.f; }
+    } else {
+      A = sa[L - k];
+      Bv = sb[L - k];
+      A.y = -A.y;
+      Bv.y = -Bv.y;
+    }
+    x[k] = make_float2(A.x - Bv.y, A.y + Bv.x);  // A + i B
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_fft_rows_inv(const float2 *spec, FftPlan P, const float2 *tw, int B, float *dst) {
+  extern __shared__ float2 lds[];
+  const int L = P.L, Dh = L / 2 + 1;
+  const int team = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int pr = blockIdx.x * kRowTeams + team;
+  const int b = blockIdx.y;
+  const bool valid = pr < L / 2;
+  float2 *x = lds + team * 2 * L, *y = x + L;
+  const float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
+  pack_inverse(sa, sa + Dh, L, t, x, valid);
+  __syncthreads();
+  const float2 *res = fft_team(x, y, P, tw, t, 64, true);
+  if (valid) {
+    float *ra = dst + ((size_t)b * L + 2 * pr) * L;
+    for (int j = t; j < L; j += 64) {
+      const float2 z = res[j];
+      ra[j] = z.x;
+      ra[L + j] = z.y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused: inverse rows of X, optional X output, residual R = X - Y, partial
+// sums of R^2 per row pair, G_X = grad_scale * R and the forward rows of
+// G_X written back into spec.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, int B, const float *obs,
+                    float *images_out, float grad_scale, float *loss_part) {
+  extern __shared__ float2 lds[];
+  const int L = P.L, Dh = L / 2 + 1;
+  const int team = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int pr = blockIdx.x * kRowTeams + team;
+  const int b = blockIdx.y;
+  const bool valid = pr < L / 2;
+  float2 *x = lds + team * 2 * L, *y = x + L;
+  float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
+  pack_inverse(sa, sa + Dh, L, t, x, valid);
+  __syncthreads();
+  float2 *res = fft_team(x, y, P, tw, t, 64, true);
+  float2 *other = (res == x) ? y : x;
+  float acc = 0.f;
+  const size_t row0 = ((size_t)b * L + 2 * pr) * L;
+  for (int j = t; j < L; j += 64) {
+    float2 g = make_float2(0.f, 0.f);
+    if (valid) {
+      const float2 z = res[j];
+      if (images_out) {
+        images_out[row0 + j] = z.x;
+        images_out[row0 + L + j] = z.y;
+      }
+      const float ra = z.x - obs[row0 + j], rb = z.y - obs[row0 + L + j];
+      acc += ra * ra + rb * rb;
+      g = make_float2(grad_scale * ra, grad_scale * rb);
+    }
+    other[j] = g;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (t == 0 && valid) loss_part[(size_t)b * (L / 2) + pr] = acc;
+  __syncthreads();
+  const float2 *r2 = fft_team(other, res, P, tw, t, 64, false);
+  split_store(r2, L, t, sa, sa + Dh, valid);
+}
+
+// loss[b] = scale * sum of the row-pair partials of image b; loss[B] = total.
+__global__ void __launch_bounds__(256)
+k_loss_reduce(const float *loss_part, int B, int parts, float scale, float *loss) {
+  __shared__ double red[4];
+  double total = 0.0;
+  for (int b = 0; b < B; ++b) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < parts; k += 256) s += (double)loss_part[(size_t)b * parts + k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double v = scale * (red[0] + red[1] + red[2] + red[3]);
+      loss[b] = (float)v;
+      total += v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[B] = (float)total;
+}
+
+}  // namespace cs

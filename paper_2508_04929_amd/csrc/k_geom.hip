@@ -1,0 +1,430 @@
+// Per-Gaussian and per-(image, Gaussian) kernels: covariance construction,
+// projection, owner-tile binning, the per-Gaussian gradient chain, the pair
+// counter and Adam.
+#include "cs_internal.hpp"
+
+namespace cs {
+
+// ---------------------------------------------------------------------------
+// Eq. 5 with the Sec. 3.3.1 activations: s = exp(l) or softplus(l),
+// A = a or softplus(a), q normalised, Sigma = R diag(s)^2 R^T.
+// Also clears `zero_count` ints of zero_buf (the binning counters).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_build(const float *means, const float *log_scales, const float *quats, const float *amps,
+        Geom G, float4 *gc, int *zero_buf, int zero_count) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n < zero_count) zero_buf[n] = 0;
+  if (n >= G.N) return;
+  float s[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float l = log_scales[3 * n + k];
+    s[k] = G.scale_act ? softplusf(l) : __expf(l);
+  }
+  const float a = amps[n];
+  const float A = G.amp_act ? softplusf(a) : a;
+  float w = quats[4 * n + 0], x = quats[4 * n + 1], y = quats[4 * n + 2], z = quats[4 * n + 3];
+  const float inv = 1.f / fmaxf(sqrtf(w * w + x * x + y * y + z * z), 1e-12f);
+  w *= inv; x *= inv; y *= inv; z *= inv;
+  const float R[3][3] = {
+      {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y)},
+      {2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x)},
+      {2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)}};
+  float M[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[r][k] = R[r][k] * s[k];
+  auto sig = [&](int i, int j) { return M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2]; };
+  gc[3 * n + 0] = make_float4(means[3 * n + 0], means[3 * n + 1], means[3 * n + 2], A);
+  gc[3 * n + 1] = make_float4(sig(0, 0), sig(0, 1), sig(0, 2), sig(1, 1));
+  gc[3 * n + 2] = make_float4(sig(1, 2), sig(2, 2), 0.f, 0.f);
+}
+
+__device__ __forceinline__ void load_pose(const float *rot, const float *shift, int b,
+                                          float p0[3], float p1[3], float &tx, float &ty) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    p0[k] = rot[9 * b + k];
+    p1[k] = rot[9 * b + 3 + k];
+  }
+  tx = shift ? shift[2 * b] : 0.f;
+  ty = shift ? shift[2 * b + 1] : 0.f;
+}
+
+// Owner-tile key of a projected Gaussian: -1 when it touches no pixel of
+// the image, the owner tile when its pixel box lies inside that tile's
+// canvas (tile plus halo), G.ntiles ("wide") otherwise.
+__device__ __forceinline__ int tile_key(const Proj &P, const Geom &G) {
+  if (!(isfinite(P.u) && isfinite(P.v) && isfinite(P.hx) && isfinite(P.hy))) return -1;
+  const float fj0 = fmaxf(ceilf(P.u - P.hx), 0.f);
+  const float fj1 = fminf(floorf(P.u + P.hx), (float)(G.D - 1));
+  const float fi0 = fmaxf(ceilf(P.v - P.hy), 0.f);
+  const float fi1 = fminf(floorf(P.v + P.hy), (float)(G.D - 1));
+  if (!(fj0 <= fj1 && fi0 <= fi1)) return -1;
+  const int tx = (int)fminf(fmaxf(floorf(P.u / (float)G.T), 0.f), (float)(G.ntx - 1));
+  const int ty = (int)fminf(fmaxf(floorf(P.v / (float)G.T), 0.f), (float)(G.ntx - 1));
+  const int j0 = (int)fj0, j1 = (int)fj1, i0 = (int)fi0, i1 = (int)fi1;
+  const bool fast = j0 >= tx * G.T - G.halo && j1 <= tx * G.T + G.T - 1 + G.halo &&
+                    i0 >= ty * G.T - G.halo && i1 <= ty * G.T + G.T - 1 + G.halo;
+  return fast ? ty * G.ntx + tx : G.ntiles;
+}
+
+// ---------------------------------------------------------------------------
+// Binning pass 1: key per (image, Gaussian) and per-bin counts.
+// Block: 256 Gaussians x kImgPerBinBlock images; LDS histogram per image.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_bin_count(const float4 *gc, const float *rot, const float *shift, Geom G, int *key,
+            int *count) {
+  extern __shared__ int hist[];  // [kImgPerBinBlock][K]
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int b0 = blockIdx.y * kImgPerBinBlock;
+  for (int i = threadIdx.x; i < kImgPerBinBlock * G.K; i += kBlock) hist[i] = 0;
+  __syncthreads();
+  float4 g0 = make_float4(0, 0, 0, 0), g1 = g0, g2 = g0;
+  if (n < G.N) {
+    g0 = gc[3 * n];
+    g1 = gc[3 * n + 1];
+    g2 = gc[3 * n + 2];
+  }
+  for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
+    const int b = b0 + bi;
+    if (b >= G.B) break;
+    if (n < G.N) {
+      float p0[3], p1[3], tx, ty;
+      load_pose(rot, shift, b, p0, p1, tx, ty);
+      Proj P;
+      project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
+      const int k = tile_key(P, G);
+      key[(size_t)b * G.N + n] = k;
+      if (k >= 0) atomicAdd(&hist[bi * G.K + k], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kImgPerBinBlock * G.K; i += kBlock) {
+    const int b = b0 + i / G.K;
+    const int c = hist[i];
+    if (b < G.B && c) atomicAdd(&count[b * G.K + i % G.K], c);
+  }
+}
+
+// Exclusive scan across one block of 1024 threads (16 waves of 64).
+__device__ int block_scan_1024(int val, int *sh, int &total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = val;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    int s = lane < 16 ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int y = __shfl_up(s, o, 64);
+      if (lane >= o) s += y;
+    }
+    if (lane < 16) sh[lane] = s;
+  }
+  __syncthreads();
+  const int prefix = wid > 0 ? sh[wid - 1] : 0;
+  total = sh[15];
+  __syncthreads();
+  return prefix + x - val;
+}
+
+// ---------------------------------------------------------------------------
+// Binning pass 2 (one block of 1024 threads): list offsets per bin and the
+// work items.  A work item is a chunk of at most G.budget Gaussians of one
+// owner tile.  Also resets the work-queue counters.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+k_scan(const int *count, Geom G, int *off, int *cursor, int4 *items, int *item_off,
+       int *n_items, int *queues) {
+  __shared__ int sh[16];
+  const int total = G.B * G.K;
+  const int seg = (total + 1023) / 1024;
+  const int e0 = min(threadIdx.x * seg, total), e1 = min(e0 + seg, total);
+  int s = 0, si = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int c = count[e];
+    s += c;
+    if (e % G.K < G.ntiles) si += (c + G.budget - 1) / G.budget;
+  }
+  int tot, itot;
+  int pre = block_scan_1024(s, sh, tot);
+  int ipre = block_scan_1024(si, sh, itot);
+  for (int e = e0; e < e1; ++e) {
+    const int c = count[e];
+    off[e] = pre;
+    cursor[e] = pre;
+    item_off[e] = ipre;
+    const int t = e % G.K;
+    if (t < G.ntiles) {
+      const int nc = (c + G.budget - 1) / G.budget;
+      for (int k = 0; k < nc; ++k)
+        items[ipre + k] = make_int4(e / G.K, t, pre + k * G.budget, min(G.budget, c - k * G.budget));
+      ipre += nc;
+    }
+    pre += c;
+  }
+  if (threadIdx.x == 0) {
+    item_off[total] = itot;
+    n_items[0] = itot;
+    queues[0] = 0;
+    queues[1] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Binning pass 3: write the 32-byte splat record of every visible
+// (image, Gaussian) into its bin's segment of the list:
+//   rec0 = (u, v, al, be), rec1 = (ga, w, n, i0 | i1 << 16)
+// with (al, be, ga) the exp2-scaled pixel conic and [i0, i1] the clipped
+// row range of the q_cut ellipse.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, const int *key,
+              int *cursor, float4 *list) {
+  extern __shared__ int sm[];  // cnt[kImgPerBinBlock*K], base[kImgPerBinBlock*K]
+  int *cnt = sm;
+  int *base = sm + kImgPerBinBlock * G.K;
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int b0 = blockIdx.y * kImgPerBinBlock;
+  for (int i = threadIdx.x; i < kImgPerBinBlock * G.K; i += kBlock) cnt[i] = 0;
+  __syncthreads();
+  int kk[kImgPerBinBlock], rank[kImgPerBinBlock];
+#pragma unroll
+  for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
+    const int b = b0 + bi;
+    kk[bi] = -1;
+    rank[bi] = 0;
+    if (b < G.B && n < G.N) {
+      kk[bi] = key[(size_t)b * G.N + n];
+      if (kk[bi] >= 0) rank[bi] = atomicAdd(&cnt[bi * G.K + kk[bi]], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kImgPerBinBlock * G.K; i += kBlock) {
+    const int b = b0 + i / G.K;
+    const int c = cnt[i];
+    if (b < G.B && c) base[i] = atomicAdd(&cursor[b * G.K + i % G.K], c);
+  }
+  __syncthreads();
+  if (n >= G.N) return;
+  const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
+#pragma unroll
+  for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
+    if (kk[bi] < 0) continue;
+    const int b = b0 + bi;
+    float p0[3], p1[3], tx, ty;
+    load_pose(rot, shift, b, p0, p1, tx, ty);
+    Proj P;
+    project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
+    const int i0 = clamp_px(ceilf(P.v - P.hy), 0, G.D - 1);
+    const int i1 = clamp_px(floorf(P.v + P.hy), 0, G.D - 1);
+    const int pos = base[bi * G.K + kk[bi]] + rank[bi];
+    list[2 * (size_t)pos] = make_float4(P.u, P.v, P.al, P.be);
+    list[2 * (size_t)pos + 1] =
+        make_float4(P.ga, P.w, __int_as_float(n), __int_as_float(i0 | (i1 << 16)));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-Gaussian gradient chain.  For every image where the Gaussian is
+// visible, the six pixel moments written by the backward splat,
+//   m = sum_pixels G_Q e * (1, dj, di, dj^2, dj di, di^2),  e = exp(-q/2),
+// give (pixel units, a b c the pixel conic, w the weight):
+//   dL/dw = m0,  dL/du = w (a m1 + b m2),  dL/dv = w (b m1 + c m2),
+//   dL/da = -w m3 / 2,  dL/db = -w m4,  dL/dc = -w m5 / 2.
+// These map to the screen mean and conic C = Sigma~^-1 (Eq. 18, 20), then
+//   dL/dSigma~ = -C G_C C - (w dL/dw / 2) C     (Eq. 20 with |C|^1/2 in w)
+// and to the world frame: dmu += P^T dmu~, dSigma += P^T dSigma~ P (Eq. 21).
+// Finally Sigma = M M^T with M = R diag(s): dM = 2 dSigma M, ds_k =
+// sum_r dM_rk R_rk, dR = dM diag(s), then the unit-quaternion and
+// activation derivatives (the 3DGS chain the paper defers to, App. A.2).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_chain(const float4 *gc, const float *log_scales, const float *quats, const float *amps,
+        const float *rot, const float *shift, Geom G, const int *key, const float *mom,
+        float *g_means, float *g_log_scales, float *g_quats, float *g_amps) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= G.N) return;
+  const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
+  const float p = G.pixel, p2 = p * p, ip = 1.f / p;
+  float dmu[3] = {0, 0, 0};
+  float dS[6] = {0, 0, 0, 0, 0, 0};  // xx xy xz yy yz zz
+  float dw_sum = 0.f;                // sum_b dL/dw * w / A  (= dL/dA)
+  for (int b = 0; b < G.B; ++b) {
+    if (key[(size_t)b * G.N + n] < 0) continue;
+    float p0[3], p1[3], tx, ty;
+    load_pose(rot, shift, b, p0, p1, tx, ty);
+    Proj P;
+    project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
+    const float *m = mom + ((size_t)b * G.N + n) * 6;
+    const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4], m5 = m[5];
+    const float inv_det = 1.f / P.det;
+    const float Cxx = P.syy * inv_det, Cxy = -P.sxy * inv_det, Cyy = P.sxx * inv_det;
+    const float a = p2 * Cxx, bb = -p2 * Cxy, c = p2 * Cyy;
+    const float w = P.w;
+    const float dLdu = w * (a * m1 + bb * m2);
+    const float dLdv = w * (bb * m1 + c * m2);
+    const float dmx = dLdu * ip, dmy = -dLdv * ip;
+    // symmetric gradient w.r.t. C (entries), from d/da, d/db, d/dc
+    const float Gxx = -0.5f * w * m3 * p2;
+    const float Gxy = 0.5f * w * m4 * p2;
+    const float Gyy = -0.5f * w * m5 * p2;
+    // -C G C - (w m0 / 2) C
+    const float t_xx = Cxx * Gxx + Cxy * Gxy, t_xy = Cxx * Gxy + Cxy * Gyy;
+    const float t_yx = Cxy * Gxx + Cyy * Gxy, t_yy = Cxy * Gxy + Cyy * Gyy;
+    const float hw = 0.5f * w * m0;
+    const float Sxx = -(t_xx * Cxx + t_xy * Cxy) - hw * Cxx;
+    const float Sxy = -(t_xx * Cxy + t_xy * Cyy) - hw * Cxy;
+    const float Syy = -(t_yx * Cxy + t_yy * Cyy) - hw * Cyy;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dmu[k] += p0[k] * dmx + p1[k] * dmy;
+    const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int i = ii[e], j = jj[e];
+      dS[e] += Sxx * p0[i] * p0[j] + Sxy * (p0[i] * p1[j] + p1[i] * p0[j]) + Syy * p1[i] * p1[j];
+    }
+    dw_sum += m0 * rsqrtf(P.det) * 0.15915494309189535f;
+  }
+  // Sigma = M M^T, M = R diag(s)
+  float s[3], dsdl[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float l = log_scales[3 * n + k];
+    if (G.scale_act) {
+      s[k] = softplusf(l);
+      dsdl[k] = sigmoidf_(l);
+    } else {
+      s[k] = __expf(l);
+      dsdl[k] = s[k];
+    }
+  }
+  float qw = quats[4 * n + 0], qx = quats[4 * n + 1], qy = quats[4 * n + 2], qz = quats[4 * n + 3];
+  const float qn = fmaxf(sqrtf(qw * qw + qx * qx + qy * qy + qz * qz), 1e-12f);
+  const float iq = 1.f / qn;
+  qw *= iq; qx *= iq; qy *= iq; qz *= iq;
+  const float R[3][3] = {
+      {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
+      {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
+      {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
+  const float Sg[3][3] = {{dS[0], dS[1], dS[2]}, {dS[1], dS[3], dS[4]}, {dS[2], dS[4], dS[5]}};
+  float dM[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dM[r][k] = 2.f * (Sg[r][0] * R[0][k] * s[k] + Sg[r][1] * R[1][k] * s[k] + Sg[r][2] * R[2][k] * s[k]);
+  float dR[3][3];
+  float ds[3] = {0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ds[k] += dM[r][k] * R[r][k];
+      dR[r][k] = dM[r][k] * s[k];
+    }
+  // dR/dq for the unit-quaternion form of R
+  const float dqw = 2.f * (-qz * dR[0][1] + qy * dR[0][2] + qz * dR[1][0] - qx * dR[1][2] -
+                           qy * dR[2][0] + qx * dR[2][1]);
+  const float dqx = 2.f * (qy * dR[0][1] + qz * dR[0][2] + qy * dR[1][0] - 2.f * qx * dR[1][1] -
+                           qw * dR[1][2] + qz * dR[2][0] + qw * dR[2][1] - 2.f * qx * dR[2][2]);
+  const float dqy = 2.f * (-2.f * qy * dR[0][0] + qx * dR[0][1] + qw * dR[0][2] + qx * dR[1][0] +
+                           qz * dR[1][2] - qw * dR[2][0] + qz * dR[2][1] - 2.f * qy * dR[2][2]);
+  const float dqz = 2.f * (-2.f * qz * dR[0][0] - qw * dR[0][1] + qx * dR[0][2] + qw * dR[1][0] -
+                           2.f * qz * dR[1][1] + qy * dR[1][2] + qx * dR[2][0] + qy * dR[2][1]);
+  const float dot = qw * dqw + qx * dqx + qy * dqy + qz * dqz;
+  if (g_means) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g_means[3 * n + k] = dmu[k];
+  }
+  if (g_log_scales) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g_log_scales[3 * n + k] = ds[k] * dsdl[k];
+  }
+  if (g_quats) {
+    g_quats[4 * n + 0] = (dqw - qw * dot) * iq;
+    g_quats[4 * n + 1] = (dqx - qx * dot) * iq;
+    g_quats[4 * n + 2] = (dqy - qy * dot) * iq;
+    g_quats[4 * n + 3] = (dqz - qz * dot) * iq;
+  }
+  if (g_amps) {
+    const float a = amps[n];
+    g_amps[n] = dw_sum * (G.amp_act ? sigmoidf_(a) : 1.f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact-footprint pair count per image: pixels of the image with squared
+// Mahalanobis distance <= q_cut, summed over Gaussians (the splat's
+// algorithmic work), using the renderer's per-row spans.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_pair_count(const float4 *gc, const float *rot, const float *shift, Geom G,
+             unsigned long long *counts) {
+  __shared__ unsigned long long part[kBlock / 64];
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int b = blockIdx.y;
+  unsigned long long cnt = 0;
+  if (n < G.N) {
+    const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
+    float p0[3], p1[3], tx, ty;
+    load_pose(rot, shift, b, p0, p1, tx, ty);
+    Proj P;
+    project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
+    if (isfinite(P.u) && isfinite(P.v) && isfinite(P.hy)) {
+      const int i0 = clamp_px(ceilf(P.v - P.hy), 0, G.D);
+      const int i1 = clamp_px(floorf(P.v + P.hy), -1, G.D - 1);
+      const float det_s = P.al * P.ga - P.be * P.be;
+      const float ia = 1.f / P.al;
+      for (int i = i0; i <= i1; ++i) {
+        const float di = (float)i - P.v;
+        const float disc = P.al * G.qk - det_s * di * di;
+        if (disc < 0.f) continue;
+        const float h = sqrtf(disc) * ia;
+        const float cen = P.u - P.be * di * ia;
+        const int j0 = clamp_px(ceilf(cen - h), 0, G.D);
+        const int j1 = clamp_px(floorf(cen + h), -1, G.D - 1);
+        if (j1 >= j0) cnt += (unsigned long long)(j1 - j0 + 1);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < kBlock / 64; ++k) t += part[k];
+    if (t) atomicAdd(&counts[b], t);
+  }
+}
+
+// Adam (Alg. 1 "Adam(grad L)"), bias corrections precomputed on the host.
+__global__ void __launch_bounds__(kBlock)
+k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+       float eps, float bc1, float bc2) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(float *p, int64_t n, float value) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+}  // namespace cs

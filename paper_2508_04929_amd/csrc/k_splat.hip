@@ -1,0 +1,302 @@
+// Forward and adjoint splat kernels (Alg. 2 SumSplats and its backward).
+//
+// Work decomposition: every visible (image, Gaussian) record belongs to one
+// owner tile (T x T pixels); its whole truncated footprint lies inside the
+// tile's canvas, the tile plus a halo on every side.  A work item is a chunk
+// of at most `budget` records of one owner tile.  Inside an item each lane
+// owns one Gaussian and walks its exact footprint row by row: the row span
+// comes from the q_cut ellipse, and along a row the Gaussian obeys the
+// two-multiply recurrence
+//     e(j+1) = e(j) r(j),   r(j+1) = r(j) K,   K = exp(-a)
+// (a is the pixel-unit conic's xx entry), so no transcendental is evaluated
+// per pixel.  The forward accumulates into an LDS canvas with LDS float
+// atomics (the sum is order-free: no alpha compositing, Sec. 3.3.4); the
+// backward reads G_Q from an LDS copy of the canvas region and accumulates
+// six pixel moments per Gaussian in registers, so no per-pixel state is
+// stored between the passes.
+#include "cs_internal.hpp"
+
+namespace cs {
+
+struct Span {
+  int j0, j1;
+  float di;
+};
+
+// Exact column span of row i for the ellipse q <= q_cut, clipped to
+// [clo, chi].  Returns false for an empty row.
+__device__ __forceinline__ bool row_span(float u, float v, float al, float be, float det_s,
+                                         float inv_al, float qk, int i, int clo, int chi,
+                                         Span &s) {
+  const float di = (float)i - v;
+  const float disc = al * qk - det_s * di * di;
+  if (!(disc >= 0.f)) return false;
+  const float h = sqrtf(disc) * inv_al;
+  const float cen = u - be * di * inv_al;
+  s.j0 = clamp_px(ceilf(cen - h), clo, chi + 1);
+  s.j1 = clamp_px(floorf(cen + h), clo - 1, chi);
+  s.di = di;
+  return s.j0 <= s.j1;
+}
+
+__device__ __forceinline__ int next_item(int *queue, int *slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
+  __syncthreads();
+  return *slot;
+}
+
+// ---------------------------------------------------------------------------
+// Forward: partial canvas of one work item.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queue, Geom G,
+            float *partials) {
+  extern __shared__ float canvas[];  // C rows of stride S
+  __shared__ int slot;
+  const int nitems = *n_items;
+  const int CS = G.C * G.S;
+  for (;;) {
+    const int it = next_item(queue, &slot);
+    if (it >= nitems) break;
+    for (int i = threadIdx.x; i < CS; i += kBlock) canvas[i] = 0.f;
+    __syncthreads();
+    const int4 itm = items[it];
+    const int ty = itm.y / G.ntx, tx = itm.y % G.ntx;
+    const int R0 = ty * G.T - G.halo, C0 = tx * G.T - G.halo;
+    const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
+    const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
+    for (int g = threadIdx.x; g < itm.w; g += kBlock) {
+      const size_t rec = 2 * (size_t)(itm.z + g);
+      const float4 r0 = list[rec], r1 = list[rec + 1];
+      const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x, w = r1.y;
+      const int rows = __float_as_int(r1.w);
+      const int i0 = max(rows & 0xffff, rlo), i1 = min(rows >> 16, rhi);
+      const float det_s = al * ga - be * be;
+      const float inv_al = 1.f / al;
+      const float K = exp2f(-2.f * al);
+      for (int i = i0; i <= i1; ++i) {
+        Span s;
+        if (!row_span(u, v, al, be, det_s, inv_al, G.qk, i, clo, chi, s)) continue;
+        const float dj = (float)s.j0 - u;
+        float e = w * exp2f(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
+        float r = exp2f(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
+        float *px = canvas + (i - R0) * G.S + (s.j0 - C0);
+        for (int j = s.j0; j <= s.j1; ++j) {
+          atomicAdd(px, e);
+          ++px;
+          e *= r;
+          r *= K;
+        }
+      }
+    }
+    __syncthreads();
+    float *out = partials + (size_t)it * G.C * G.C;
+    for (int i = threadIdx.x; i < G.C * G.C; i += kBlock) {
+      const int r = i / G.C, c = i - r * G.C;
+      out[i] = canvas[r * G.S + c];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Q for one (image, tile): the sum of every partial canvas that overlaps it,
+// taken over the 3 x 3 neighbourhood of owner tiles in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, Geom G,
+                float *Q) {
+  const int t = blockIdx.x, b = blockIdx.y;
+  const int ty = t / G.ntx, tx = t % G.ntx;
+  const int r_lo = ty * G.T, r_hi = min(r_lo + G.T, G.D);
+  const int c_lo = tx * G.T, c_hi = min(c_lo + G.T, G.D);
+  const int npx = (r_hi - r_lo) * (c_hi - c_lo);
+  const int wdt = c_hi - c_lo;
+  float *img = Q + (size_t)b * G.D * G.D;
+  for (int base = 0; base < npx; base += kBlock * 8) {
+    float acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int sy = ty + dy;
+      if (sy < 0 || sy >= G.ntx) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int sx = tx + dx;
+        if (sx < 0 || sx >= G.ntx) continue;
+        const int e = b * G.K + sy * G.ntx + sx;
+        const int R0 = sy * G.T - G.halo, C0 = sx * G.T - G.halo;
+        for (int it = item_off[e]; it < item_off[e + 1]; ++it) {
+          const float *part = partials + (size_t)it * G.C * G.C;
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int q = base + k * kBlock + threadIdx.x;
+            if (q >= npx) break;
+            const int i = r_lo + q / wdt, j = c_lo + q % wdt;
+            const int ri = i - R0, cj = j - C0;
+            if (ri >= 0 && ri < G.C && cj >= 0 && cj < G.C) acc[k] += part[ri * G.C + cj];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int q = base + k * kBlock + threadIdx.x;
+      if (q < npx) img[(size_t)(r_lo + q / wdt) * G.D + c_lo + q % wdt] = acc[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wide Gaussians (footprint larger than the canvas): one block per record,
+// threads over the pixel box, exp per pixel, device atomics into Q.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wide_box(const float4 r0, const float4 r1, const Geom &G,
+                                         int &i0, int &i1, int &j0, int &j1) {
+  const int rows = __float_as_int(r1.w);
+  i0 = rows & 0xffff;
+  i1 = rows >> 16;
+  const float det_s = r0.z * r1.x - r0.w * r0.w;
+  const float hx = sqrtf(G.qk * r1.x / det_s);
+  j0 = clamp_px(ceilf(r0.x - hx), 0, G.D);
+  j1 = clamp_px(floorf(r0.x + hx), -1, G.D - 1);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_big_fwd(const float4 *list, const int *off, const int *count, Geom G, float *Q) {
+  for (int b = 0; b < G.B; ++b) {
+    const int e = b * G.K + G.ntiles;
+    const int cnt = count[e], start = off[e];
+    for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+      const float4 r0 = list[2 * (size_t)(start + k)], r1 = list[2 * (size_t)(start + k) + 1];
+      int i0, i1, j0, j1;
+      wide_box(r0, r1, G, i0, i1, j0, j1);
+      if (i1 < i0 || j1 < j0) continue;
+      const int wdt = j1 - j0 + 1;
+      const long npx = (long)(i1 - i0 + 1) * wdt;
+      for (long q = threadIdx.x; q < npx; q += kBlock) {
+        const int i = i0 + (int)(q / wdt), j = j0 + (int)(q % wdt);
+        const float dj = (float)j - r0.x, di = (float)i - r0.y;
+        const float qq = r0.z * dj * dj + 2.f * r0.w * dj * di + r1.x * di * di;
+        if (qq <= G.qk) atomicAdd(&Q[((size_t)b * G.D + i) * G.D + j], r1.y * exp2f(-qq));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: six pixel moments per (image, Gaussian) of one work item,
+//   m = sum G_Q e (1, dj, di, dj^2, dj di, di^2),  e = exp(-q/2),
+// with dj = j - u, di = i - v (pixels).  Written to mom[(b N + n) 6 + k].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_splat_bwd(const float4 *list, const int4 *items, const int *n_items, int *queue, Geom G,
+            const float *GQ, float *mom) {
+  extern __shared__ float gq[];  // C rows of stride S
+  __shared__ int slot;
+  const int nitems = *n_items;
+  for (;;) {
+    const int it = next_item(queue, &slot);
+    if (it >= nitems) break;
+    const int4 itm = items[it];
+    const int b = itm.x;
+    const int ty = itm.y / G.ntx, tx = itm.y % G.ntx;
+    const int R0 = ty * G.T - G.halo, C0 = tx * G.T - G.halo;
+    const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
+    const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
+    const float *src = GQ + (size_t)b * G.D * G.D;
+    for (int q = threadIdx.x; q < G.C * G.C; q += kBlock) {
+      const int r = q / G.C, c = q - r * G.C;
+      const int i = R0 + r, j = C0 + c;
+      gq[r * G.S + c] = (i >= 0 && i < G.D && j >= 0 && j < G.D) ? src[(size_t)i * G.D + j] : 0.f;
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < itm.w; g += kBlock) {
+      const size_t rec = 2 * (size_t)(itm.z + g);
+      const float4 r0 = list[rec], r1 = list[rec + 1];
+      const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x;
+      const int n = __float_as_int(r1.z);
+      const int rows = __float_as_int(r1.w);
+      const int i0 = max(rows & 0xffff, rlo), i1 = min(rows >> 16, rhi);
+      const float det_s = al * ga - be * be;
+      const float inv_al = 1.f / al;
+      const float K = exp2f(-2.f * al);
+      float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
+      for (int i = i0; i <= i1; ++i) {
+        Span s;
+        if (!row_span(u, v, al, be, det_s, inv_al, G.qk, i, clo, chi, s)) continue;
+        float dj = (float)s.j0 - u;
+        float e = exp2f(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
+        float r = exp2f(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
+        const float *px = gq + (i - R0) * G.S + (s.j0 - C0);
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int j = s.j0; j <= s.j1; ++j) {
+          const float t = *px * e;
+          ++px;
+          s0 += t;
+          const float tdj = t * dj;
+          s1 += tdj;
+          s2 += tdj * dj;
+          e *= r;
+          r *= K;
+          dj += 1.f;
+        }
+        m0 += s0;
+        m1 += s1;
+        m2 += s0 * s.di;
+        m3 += s2;
+        m4 += s1 * s.di;
+        m5 += s0 * s.di * s.di;
+      }
+      float *o = mom + ((size_t)b * G.N + n) * 6;
+      o[0] = m0; o[1] = m1; o[2] = m2; o[3] = m3; o[4] = m4; o[5] = m5;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_big_bwd(const float4 *list, const int *off, const int *count, Geom G, const float *GQ,
+          float *mom) {
+  __shared__ float red[6][kBlock / 64];
+  for (int b = 0; b < G.B; ++b) {
+    const int e = b * G.K + G.ntiles;
+    const int cnt = count[e], start = off[e];
+    for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+      const float4 r0 = list[2 * (size_t)(start + k)], r1 = list[2 * (size_t)(start + k) + 1];
+      int i0, i1, j0, j1;
+      wide_box(r0, r1, G, i0, i1, j0, j1);
+      float m[6] = {0, 0, 0, 0, 0, 0};
+      if (i1 >= i0 && j1 >= j0) {
+        const int wdt = j1 - j0 + 1;
+        const long npx = (long)(i1 - i0 + 1) * wdt;
+        for (long q = threadIdx.x; q < npx; q += kBlock) {
+          const int i = i0 + (int)(q / wdt), j = j0 + (int)(q % wdt);
+          const float dj = (float)j - r0.x, di = (float)i - r0.y;
+          const float qq = r0.z * dj * dj + 2.f * r0.w * dj * di + r1.x * di * di;
+          if (qq <= G.qk) {
+            const float t = GQ[((size_t)b * G.D + i) * G.D + j] * exp2f(-qq);
+            m[0] += t; m[1] += t * dj; m[2] += t * di;
+            m[3] += t * dj * dj; m[4] += t * dj * di; m[5] += t * di * di;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        float x = m[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = x;
+      }
+      __syncthreads();
+      if (threadIdx.x < 6) {
+        float x = 0.f;
+        for (int wv = 0; wv < kBlock / 64; ++wv) x += red[threadIdx.x][wv];
+        const int n = __float_as_int(r1.z);
+        mom[((size_t)b * G.N + n) * 6 + threadIdx.x] = x;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace cs
