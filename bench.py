@@ -1,0 +1,210 @@
+#!/usr/bin/env python
+"""Benchmark of one training step of the splat renderer on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): a mixture of
+N = 200,000 Gaussians (isotropic, s = 2.112 A, A = 1/(2N), means uniform in a
+ball of radius 75 A), 64 particle images of 256 x 256 pixels at 1.1 A,
+Haar-random poses, defocus U(0.5, 2.5) um, observed images rendered from an
+independent ground-truth mixture plus white noise at SNR -20 dB.
+
+One step = render with CTF + squared-error loss + adjoint + Adam on all
+11 N parameters, every stage in the HIP library.  Inputs are resident in
+HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("particle images/sec fwd+bwd (N=200k, D=256) and % roofline; "
+          "pose-proposal speedup")
+Q_CUT = 27.631021115928547  # 2 ln 1e6, the library default
+
+# Nominal per-pair budget of the splat (one exp2 plus FMA-class ops) and the
+# chip rates it is priced at: 256 CUs at 2.4 GHz, transcendental at a
+# quarter of the 64-lane FP32 rate, FMA-class ops at the packed-FP32 rate.
+EXP_RATE = 256 * 16 * 2.4e9          # exp2 per second
+FMA_RATE = 256 * 128 * 2.4e9         # FP32 lane-ops per second (packed)
+PAIR_OPS = {"k_splat_fwd": 8, "k_splat_bwd": 20}
+
+
+def pair_peak(kernel: str) -> float:
+    """Pairs per second at 100% of the nominal per-pair budget."""
+    return 1.0 / (1.0 / EXP_RATE + PAIR_OPS[kernel] / FMA_RATE)
+
+
+# --------------------------------------------------------------- CPU oracle
+
+def _oracle_worker(args):
+    """One image of the workload through the FP64 oracle (loss + gradient)."""
+    b, seed = args
+    import numpy as np
+    from oracle import objective
+    from paper_2508_04929_amd import inputs
+    g, v, _gt, _rn = inputs.c4()
+    vs = v.subset([b])
+    rng = np.random.default_rng(seed + b)
+    Y = rng.standard_normal((1, v.D, v.D)) * 1e-4   # observed values do not change the work
+    t0 = time.perf_counter()
+    objective.loss_and_grad(g, vs, Y, q_cut=Q_CUT)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(n_images: int):
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16, n_images)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        times = pool.map(_oracle_worker, [(b, 1234) for b in range(n_images)])
+    # workers run concurrently: throughput = images / (images per core x mean time)
+    per_core = -(-n_images // cores)
+    wall = per_core * (sum(times) / len(times))
+    return {"value": n_images / wall, "unit": "images/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{n_images} of the 64 images (N=200,000, D=256), FP64 numpy oracle, "
+                       f"forward + CTF + loss + analytic gradient with the same q_cut as the "
+                       f"GPU; {cores} worker processes, mean {sum(times) / len(times):.1f} s "
+                       f"per image")}
+
+
+# ------------------------------------------------------------------- GPU
+
+def run(args):
+    import numpy as np
+    import torch
+
+    from paper_2508_04929_amd import binding, inputs
+
+    lib = binding.library()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    g, v, gt, rn = inputs.c4(b=args.batch)
+    N, B, D, p = g.n, v.b, v.D, v.pixel
+
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    # parameters and gradients as one flat buffer each: [means | log_scales | quats | amps]
+    flat = torch.cat([t(g.means).reshape(-1), t(g.log_scales).reshape(-1),
+                      t(g.quats).reshape(-1), t(g.amps).reshape(-1)]).contiguous()
+    sizes = [3 * N, 3 * N, 4 * N, N]
+    shapes = [(N, 3), (N, 3), (N, 4), (N,)]
+
+    def views_of(buf):
+        out, o = [], 0
+        for s, sh in zip(sizes, shapes):
+            out.append(buf[o:o + s].view(*sh))
+            o += s
+        return out
+
+    params = views_of(flat)
+    gflat = torch.zeros_like(flat)
+    gviews = views_of(gflat)
+    grads = dict(zip(("means", "log_scales", "quats", "amps"), gviews))
+    m = torch.zeros_like(flat)
+    vv = torch.zeros_like(flat)
+    rot, shift = t(v.rot), t(v.shift)
+    ctf = binding.Ctf(t(v.defocus_u), t(v.defocus_v), t(v.astig), t(v.phase),
+                      v.voltage_kv, v.cs_mm, v.amp_contrast, v.bfactor)
+    # observed images: ground-truth render + white noise at -20 dB
+    Xgt = lib.render(t(gt.means), t(gt.log_scales), t(gt.quats), t(gt.amps), rot, shift, D, p,
+                     ctf=ctf)
+    gen = torch.Generator(device=dev).manual_seed(4)
+    sd = torch.sqrt(Xgt.double().var() / 10 ** (-20 / 10)).float()
+    Y = (Xgt + sd * torch.randn(Xgt.shape, device=dev, generator=gen)).contiguous()
+    del Xgt
+    loss = torch.empty(B + 1, device=dev)
+    pairs = lib.pair_count(*params, rot, shift, D, p)
+    torch.cuda.synchronize()
+    pairs_step = int(pairs.sum().item())
+
+    step_no = [0]
+
+    def step():
+        lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
+                          grads=grads, loss=loss)
+        step_no[0] += 1
+        lib.adam_step(flat, gflat, m, vv, step_no[0], lr=1e-3)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lib.set_timing(dev, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = {}
+    for name in binding.STAGES:
+        ms, n = lib.stage_time(dev, name)
+        if n:
+            stages[name] = {"ms_total": ms, "launches": n, "ms_per_launch": ms / n}
+    lib.set_timing(dev, False)
+    final_loss = float(loss[-1].item())
+
+    ms_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+    dom = max(("k_splat_fwd", "k_splat_bwd"), key=lambda k: stages.get(k, {}).get("ms_total", 0))
+    d = stages[dom]
+    achieved = pairs_step / (d["ms_per_launch"] * 1e-3)     # pairs per second
+    peak = pair_peak(dom)
+    roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
+            "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
+            "pairs_per_launch": pairs_step,
+            "ms_per_launch": d["ms_per_launch"]}
+    other = "k_splat_bwd" if dom == "k_splat_fwd" else "k_splat_fwd"
+    if other in stages:
+        o = stages[other]
+        ach_o = pairs_step / (o["ms_per_launch"] * 1e-3)
+        roof["other_splat"] = {"kernel": other, "achieved": ach_o / 1e9,
+                               "peak": pair_peak(other) / 1e9, "frac": ach_o / pair_peak(other)}
+    step_roof_s = pairs_step * (1 / pair_peak("k_splat_fwd") + 1 / pair_peak("k_splat_bwd"))
+    result = {
+        "metric": METRIC, "value": value, "unit": "images/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ("training step: N=200,000 Gaussians, 64 images D=256, "
+                                "p=1.1 A, CTF, squared-error loss, adjoint, Adam on 11N "
+                                "parameters"),
+                   "N": N, "batch": B, "D": D, "pixel_A": p, "q_cut": Q_CUT,
+                   "pairs_per_step": pairs_step, "pairs_per_image": pairs_step / B,
+                   "final_loss": final_loss},
+        "roofline": roof,
+        "step_fraction_of_splat_roofline": step_roof_s / (ms_step * 1e-3),
+        "stages_ms_per_step": {k: s["ms_total"] / args.steps for k, s in stages.items()},
+    }
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--cpu-images", type=int, default=16,
+                    help="images of the workload timed through the CPU oracle (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU data parallelism is described, not built)"}))
+        sys.exit(2)
+    cpu = None
+    if args.cpu_images > 0 and int(os.environ.get("RANK", "0")) == 0:
+        cpu = cpu_baseline(args.cpu_images)
+        print(f"[bench] cpu oracle: {cpu['value']:.4f} images/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
+    res = run(args)
+    res["cpu_baseline"] = cpu
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,16 @@ int cs_adam_step(cs_ctx *ctx, float *params, const float *grads, float *m,
 int cs_pair_count(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v,
                   const cs_options *opt, int64_t *counts, void *stream);
 
+/* Stage timing for measurement.  While enabled (enable != 0), every kernel
+ * the library launches on ctx is bracketed by HIP events recorded on the
+ * call's stream; enabling clears the accumulated totals.  Kernel names are
+ * the library's stage names (e.g. "k_splat_fwd", "k_splat_bwd"). */
+int cs_set_timing(cs_ctx *ctx, int enable);
+
+/* Total milliseconds and launch count of stage `name` since timing was last
+ * enabled (synchronises the recorded events).  Unknown names give 0. */
+int cs_stage_time(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

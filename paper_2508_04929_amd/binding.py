@@ -54,7 +54,7 @@ class CsOptions(ctypes.Structure):
 
 #: Entry points declared in include/cryosplat.h.
 EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_backward",
-           "cs_loss_and_grad", "cs_adam_step", "cs_pair_count")
+           "cs_loss_and_grad", "cs_adam_step", "cs_pair_count", "cs_set_timing", "cs_stage_time")
 
 
 class CryoSplatError(RuntimeError):
@@ -88,6 +88,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_adam_step.restype = ctypes.c_int
     lib.cs_pair_count.argtypes = [vp, P(CsGaussians), P(CsViews), P(CsOptions), vp, vp]
     lib.cs_pair_count.restype = ctypes.c_int
+    lib.cs_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.cs_set_timing.restype = ctypes.c_int
+    lib.cs_stage_time.argtypes = [vp, ctypes.c_char_p, P(ctypes.c_double), P(i64)]
+    lib.cs_stage_time.restype = ctypes.c_int
     return lib
 
 
@@ -260,6 +264,25 @@ class Library:
         self._check(ctx, rc, "cs_pair_count")
         return out
 
+
+    def set_timing(self, device, enable: bool):
+        ctx = self.ctx(torch.device(device))
+        self._check(ctx, self.lib.cs_set_timing(ctx, 1 if enable else 0), "cs_set_timing")
+
+    def stage_time(self, device, name: str):
+        """(total milliseconds, launches) of one library stage since timing was enabled."""
+        ctx = self.ctx(torch.device(device))
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(ctx, self.lib.cs_stage_time(ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n)),
+                    "cs_stage_time")
+        return ms.value, n.value
+
+
+#: Kernel stages the library may launch (names reported by stage_time).
+STAGES = ("k_build", "k_bin_count", "k_scan", "k_bin_scatter", "k_splat_fwd", "k_canvas_reduce",
+          "k_big_fwd", "k_fft_rows_fwd", "k_fft_cols_ctf", "k_fft_rows_inv_loss", "k_fft_rows_inv",
+          "k_residual", "k_loss_reduce", "k_splat_bwd", "k_big_bwd", "k_chain", "k_adam",
+          "k_fill", "k_pair_count")
 
 _LIB: Optional[Library] = None
 

@@ -21,6 +21,11 @@ struct cs_ctx {
   size_t ws_max = 0;  // 0 = unlimited
   int n_cu = 256;
   std::map<int, float2 *> twiddles;
+  // stage timing
+  bool timing = false;
+  struct Pending { const char *name; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::map<std::string, std::pair<double, int64_t>> stage_ms;
 };
 
 namespace {
@@ -45,6 +50,23 @@ int fail(cs_ctx *c, int code, const char *fmt, ...) {
   do {                                                                               \
     hipError_t e_ = (x);                                                             \
     if (e_ != hipSuccess) return fail(ctx, CS_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+// Launch with optional event bracketing (stage timing).
+#define TLAUNCH(kernel, grid, block, lds, st, ...)                                    \
+  do {                                                                               \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                                         \
+    if (ctx->timing) {                                                               \
+      (void)hipEventCreate(&ea_);                                                    \
+      (void)hipEventCreate(&eb_);                                                    \
+      (void)hipEventRecord(ea_, st);                                                 \
+    }                                                                                \
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);        \
+    LAUNCHCHK(#kernel);                                                              \
+    if (ctx->timing) {                                                               \
+      (void)hipEventRecord(eb_, st);                                                 \
+      ctx->pending.push_back({#kernel, ea_, eb_});                                   \
+    }                                                                                \
   } while (0)
 
 #define LAUNCHCHK(name)                                                              \
@@ -193,7 +215,7 @@ Geom make_geom(const cs_gaussians *g, const cs_views *v, const cs_options *opt) 
   G.T = (opt && opt->tile) ? opt->tile : kDefaultTile;
   G.halo = (opt && opt->halo) ? opt->halo : std::min(kDefaultHalo, G.T);
   G.C = G.T + 2 * G.halo;
-  G.S = G.C + 1;
+  G.S = G.C + 4;  // padding columns: unrolled row walks stay inside a row
   G.ntx = (G.D + G.T - 1) / G.T;
   G.ntiles = G.ntx * G.ntx;
   G.K = G.ntiles + 1;
@@ -212,21 +234,17 @@ int launch_binning(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const 
   int *count = (int *)(ws + L.count);
   const size_t BK = (size_t)G.B * G.K;
   const size_t nb = std::max<size_t>((size_t)G.N, BK);
-  hipLaunchKernelGGL(k_build, dim3(cdiv(nb, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
-                     g->quats, g->amps, G, gc, count, (int)BK);
-  LAUNCHCHK("k_build");
+  TLAUNCH(k_build, dim3(cdiv(nb, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
+          g->quats, g->amps, G, gc, count, (int)BK);
   const dim3 bgrid(cdiv(G.N, kBlock), cdiv(G.B, kImgPerBinBlock));
   const size_t hist_bytes = (size_t)kImgPerBinBlock * G.K * 4;
-  hipLaunchKernelGGL(k_bin_count, bgrid, dim3(kBlock), hist_bytes, st, gc, v->rot, v->shift, G,
+  TLAUNCH(k_bin_count, bgrid, dim3(kBlock), hist_bytes, st, gc, v->rot, v->shift, G,
                      (int *)(ws + L.key), count);
-  LAUNCHCHK("k_bin_count");
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, count, G, (int *)(ws + L.off),
+  TLAUNCH(k_scan, dim3(1), dim3(1024), 0, st, count, G, (int *)(ws + L.off),
                      (int *)(ws + L.cursor), (int4 *)(ws + L.items), (int *)(ws + L.item_off),
                      (int *)(ws + L.n_items), (int *)(ws + L.queues));
-  LAUNCHCHK("k_scan");
-  hipLaunchKernelGGL(k_bin_scatter, bgrid, dim3(kBlock), 2 * hist_bytes, st, gc, v->rot, v->shift,
+  TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), 2 * hist_bytes, st, gc, v->rot, v->shift,
                      G, (const int *)(ws + L.key), (int *)(ws + L.cursor), (float4 *)(ws + L.list));
-  LAUNCHCHK("k_bin_scatter");
   return CS_OK;
 }
 
@@ -244,17 +262,14 @@ int launch_forward(cs_ctx *ctx, const Geom &G, const Layout &L, char *ws, float 
   int grid = 0;
   int rc = persistent_grid(ctx, (const void *)k_splat_fwd, lds, &grid);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_splat_fwd, dim3(grid), dim3(kBlock), lds, st, (const float4 *)(ws + L.list),
+  TLAUNCH(k_splat_fwd, dim3(grid), dim3(kBlock), lds, st, (const float4 *)(ws + L.list),
                      (const int4 *)(ws + L.items), (const int *)(ws + L.n_items),
                      (int *)(ws + L.queues), G, (float *)(ws + L.partials));
-  LAUNCHCHK("k_splat_fwd");
-  hipLaunchKernelGGL(k_canvas_reduce, dim3(G.ntiles, G.B), dim3(kBlock), 0, st,
+  TLAUNCH(k_canvas_reduce, dim3(G.ntiles, G.B), dim3(kBlock), 0, st,
                      (const float *)(ws + L.partials), (const int *)(ws + L.item_off),
                      (const int4 *)(ws + L.items), G, Q);
-  LAUNCHCHK("k_canvas_reduce");
-  hipLaunchKernelGGL(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
+  TLAUNCH(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
                      (const int *)(ws + L.off), (const int *)(ws + L.count), G, Q);
-  LAUNCHCHK("k_big_fwd");
   return CS_OK;
 }
 
@@ -265,18 +280,15 @@ int launch_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const
   int rc = persistent_grid(ctx, (const void *)k_splat_bwd, lds, &grid);
   if (rc) return rc;
   float *mom = (float *)(ws + L.mom);
-  hipLaunchKernelGGL(k_splat_bwd, dim3(grid), dim3(kBlock), lds, st, (const float4 *)(ws + L.list),
+  TLAUNCH(k_splat_bwd, dim3(grid), dim3(kBlock), lds, st, (const float4 *)(ws + L.list),
                      (const int4 *)(ws + L.items), (const int *)(ws + L.n_items),
                      (int *)(ws + L.queues) + 1, G, GQ, mom);
-  LAUNCHCHK("k_splat_bwd");
-  hipLaunchKernelGGL(k_big_bwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
+  TLAUNCH(k_big_bwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
                      (const int *)(ws + L.off), (const int *)(ws + L.count), G, GQ, mom);
-  LAUNCHCHK("k_big_bwd");
-  hipLaunchKernelGGL(k_chain, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, (const float4 *)(ws + L.gc),
+  TLAUNCH(k_chain, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, (const float4 *)(ws + L.gc),
                      g->log_scales, g->quats, g->amps, v->rot, v->shift, G,
                      (const int *)(ws + L.key), mom, grads->means, grads->log_scales,
                      grads->quats, grads->amps);
-  LAUNCHCHK("k_chain");
   return CS_OK;
 }
 
@@ -286,8 +298,7 @@ int zero_grads(cs_ctx *ctx, const cs_gaussians *g, cs_grads *grads, hipStream_t 
       {grads->means, 3 * n}, {grads->log_scales, 3 * n}, {grads->quats, 4 * n}, {grads->amps, n}};
   for (auto &o : outs) {
     if (!o.p || o.k == 0) continue;
-    hipLaunchKernelGGL(k_fill, dim3(cdiv(o.k, kBlock)), dim3(kBlock), 0, st, o.p, o.k, 0.f);
-    LAUNCHCHK("k_fill");
+    TLAUNCH(k_fill, dim3(cdiv(o.k, kBlock)), dim3(kBlock), 0, st, o.p, o.k, 0.f);
   }
   return CS_OK;
 }
@@ -317,16 +328,13 @@ int launch_ctf_roundtrip(cs_ctx *ctx, const Geom &G, const cs_ctf *ctf, const fl
   if (rc) return rc;
   const dim3 rgrid(cdiv(G.D / 2, 4), G.B);
   const size_t rlds = (size_t)4 * 2 * G.D * 8;
-  hipLaunchKernelGGL(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, src, P, tw, G.B, spec);
-  LAUNCHCHK("k_fft_rows_fwd");
+  TLAUNCH(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, src, P, tw, G.B, spec);
   const int cpw = G.D > 256 ? 8 : 16;
   const dim3 cgrid(cdiv(G.D / 2 + 1, cpw), G.B);
   const size_t clds = (size_t)cpw * 2 * G.D * 8;
-  hipLaunchKernelGGL(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel,
+  TLAUNCH(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel,
                      make_ctf(ctf));
-  LAUNCHCHK("k_fft_cols_ctf");
-  hipLaunchKernelGGL(k_fft_rows_inv, rgrid, dim3(256), rlds, st, (const float2 *)spec, P, tw, G.B, dst);
-  LAUNCHCHK("k_fft_rows_inv");
+  TLAUNCH(k_fft_rows_inv, rgrid, dim3(256), rlds, st, (const float2 *)spec, P, tw, G.B, dst);
   return CS_OK;
 }
 
@@ -408,8 +416,7 @@ int cs_render(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ct
   float *Q = ctf ? (float *)(ws + L.Q) : images;
   const size_t npx = (size_t)G.B * G.D * G.D;
   if (G.N == 0) {
-    hipLaunchKernelGGL(k_fill, dim3(cdiv(npx, kBlock)), dim3(kBlock), 0, st, images, (int64_t)npx, 0.f);
-    LAUNCHCHK("k_fill");
+    TLAUNCH(k_fill, dim3(cdiv(npx, kBlock)), dim3(kBlock), 0, st, images, (int64_t)npx, 0.f);
     return CS_OK;
   }
   rc = launch_binning(ctx, g, v, G, L, ws, st);
@@ -463,8 +470,7 @@ int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, cons
   float *Q = (float *)(ws + L.Q);
   const size_t npx = (size_t)G.B * G.D * G.D;
   if (G.N == 0) {
-    hipLaunchKernelGGL(k_fill, dim3(cdiv(npx, kBlock)), dim3(kBlock), 0, st, Q, (int64_t)npx, 0.f);
-    LAUNCHCHK("k_fill");
+    TLAUNCH(k_fill, dim3(cdiv(npx, kBlock)), dim3(kBlock), 0, st, Q, (int64_t)npx, 0.f);
   } else {
     rc = launch_binning(ctx, g, v, G, L, ws, st);
     if (rc) return rc;
@@ -488,30 +494,23 @@ int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, cons
     const dim3 cgrid(cdiv(G.D / 2 + 1, cpw), G.B);
     const size_t clds = (size_t)cpw * 2 * G.D * 8;
     const CtfDev cd = make_ctf(ctf);
-    hipLaunchKernelGGL(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, Q, P, tw, G.B, spec);
-    LAUNCHCHK("k_fft_rows_fwd");
-    hipLaunchKernelGGL(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel, cd);
-    LAUNCHCHK("k_fft_cols_ctf");
-    hipLaunchKernelGGL(k_fft_rows_inv_loss, rgrid, dim3(256), rlds, st, spec, P, tw, G.B, observed,
+    TLAUNCH(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, Q, P, tw, G.B, spec);
+    TLAUNCH(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel, cd);
+    TLAUNCH(k_fft_rows_inv_loss, rgrid, dim3(256), rlds, st, spec, P, tw, G.B, observed,
                        images_out, gscale, loss_part);
-    LAUNCHCHK("k_fft_rows_inv_loss");
     parts = G.D / 2;
     if (want_grads) {
-      hipLaunchKernelGGL(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel, cd);
-      LAUNCHCHK("k_fft_cols_ctf");
-      hipLaunchKernelGGL(k_fft_rows_inv, rgrid, dim3(256), rlds, st, (const float2 *)spec, P, tw,
+      TLAUNCH(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel, cd);
+      TLAUNCH(k_fft_rows_inv, rgrid, dim3(256), rlds, st, (const float2 *)spec, P, tw,
                          G.B, Q);
-      LAUNCHCHK("k_fft_rows_inv");
     }
   } else {
-    hipLaunchKernelGGL(k_residual, dim3(G.D, G.B), dim3(256), 0, st, Q, observed, images_out, G.B,
+    TLAUNCH(k_residual, dim3(G.D, G.B), dim3(256), 0, st, Q, observed, images_out, G.B,
                        G.D, gscale, loss_part);
-    LAUNCHCHK("k_residual");
     parts = G.D;
   }
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, (const float *)loss_part, G.B, parts,
+  TLAUNCH(k_loss_reduce, dim3(1), dim3(256), 0, st, (const float *)loss_part, G.B, parts,
                      (float)scale, loss);
-  LAUNCHCHK("k_loss_reduce");
   if (!grads) return CS_OK;
   if (G.N == 0) return zero_grads(ctx, g, grads, st);
   return launch_backward(ctx, g, v, G, L, ws, Q, grads, st);
@@ -528,9 +527,8 @@ int cs_adam_step(cs_ctx *ctx, float *params, const float *grads, float *m, float
   HIPCHK(hipSetDevice(ctx->device));
   const float bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
   const float bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
-  hipLaunchKernelGGL(k_adam, dim3(cdiv(count, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, params,
+  TLAUNCH(k_adam, dim3(cdiv(count, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, params,
                      grads, m, v, count, lr, b1, b2, eps, bc1, bc2);
-  LAUNCHCHK("k_adam");
   return CS_OK;
 }
 
@@ -542,21 +540,49 @@ int cs_pair_count(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const c
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const Geom G = make_geom(g, v, opt);
-  hipLaunchKernelGGL(k_fill, dim3(cdiv(2 * (size_t)G.B, kBlock)), dim3(kBlock), 0, st, (float *)counts,
+  TLAUNCH(k_fill, dim3(cdiv(2 * (size_t)G.B, kBlock)), dim3(kBlock), 0, st, (float *)counts,
                      (int64_t)(2 * G.B), 0.f);  // all-zero bits
-  LAUNCHCHK("k_fill");
   if (G.N == 0) return CS_OK;
   const Layout L = make_layout(G, false, false, false);
   rc = ensure_ws(ctx, L.total, st);
   if (rc) return rc;
   char *ws = (char *)ctx->ws;
   float4 *gc = (float4 *)(ws + L.gc);
-  hipLaunchKernelGGL(k_build, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
-                     g->quats, g->amps, G, gc, (int *)nullptr, 0);
-  LAUNCHCHK("k_build");
-  hipLaunchKernelGGL(k_pair_count, dim3(cdiv(G.N, kBlock), G.B), dim3(kBlock), 0, st, gc, v->rot,
+  TLAUNCH(k_build, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
+          g->quats, g->amps, G, gc, (int *)nullptr, 0);
+  TLAUNCH(k_pair_count, dim3(cdiv(G.N, kBlock), G.B), dim3(kBlock), 0, st, gc, v->rot,
                      v->shift, G, (unsigned long long *)counts);
-  LAUNCHCHK("k_pair_count");
+  return CS_OK;
+}
+
+int cs_set_timing(cs_ctx *ctx, int enable) {
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  for (auto &p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  ctx->pending.clear();
+  ctx->stage_ms.clear();
+  ctx->timing = enable != 0;
+  return CS_OK;
+}
+
+int cs_stage_time(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches) {
+  if (!ctx || !name || !total_ms || !launches) return CS_ERR_INVALID_ARG;
+  for (auto &p : ctx->pending) {
+    HIPCHK(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    auto &acc = ctx->stage_ms[p.name];
+    acc.first += ms;
+    acc.second += 1;
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  ctx->pending.clear();
+  auto it = ctx->stage_ms.find(name);
+  *total_ms = it == ctx->stage_ms.end() ? 0.0 : it->second.first;
+  *launches = it == ctx->stage_ms.end() ? 0 : it->second.second;
   return CS_OK;
 }
 

@@ -40,7 +40,7 @@ struct Geom {
   int T;          // owner-tile side
   int halo;       // canvas halo
   int C;          // canvas side = T + 2 halo
-  int S;          // LDS row stride of a canvas = C + 1
+  int S;          // LDS row stride of a canvas = C + 4 (padding for unrolled walks)
   int ntx;        // tiles per row
   int ntiles;     // tiles per image
   int K;          // bins per image = ntiles + 1 (last bin: wide Gaussians)

@@ -9,11 +9,14 @@
 // two-multiply recurrence
 //     e(j+1) = e(j) r(j),   r(j+1) = r(j) K,   K = exp(-a)
 // (a is the pixel-unit conic's xx entry), so no transcendental is evaluated
-// per pixel.  The forward accumulates into an LDS canvas with LDS float
-// atomics (the sum is order-free: no alpha compositing, Sec. 3.3.4); the
-// backward reads G_Q from an LDS copy of the canvas region and accumulates
-// six pixel moments per Gaussian in registers, so no per-pixel state is
-// stored between the passes.
+// per pixel.  The forward accumulates into an LDS canvas in 32-bit fixed
+// point with integer LDS atomics (LDS float atomics are ~30x slower on
+// gfx950; integer addition also makes the sum order-independent, matching
+// the order-free additive splat of Sec. 3.3.4).  The fixed-point scale of
+// an item is the largest power of two with scale * sum|w| <= 2^30, so no
+// pixel can overflow.  The backward reads G_Q from an LDS copy of the
+// canvas region and accumulates the six pixel moments per Gaussian in
+// registers, so no per-pixel state is stored between the passes.
 #include "cs_internal.hpp"
 
 namespace cs {
@@ -51,16 +54,30 @@ __device__ __forceinline__ int next_item(int *queue, int *slot) {
 __global__ void __launch_bounds__(kBlock)
 k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queue, Geom G,
             float *partials) {
-  extern __shared__ float canvas[];  // C rows of stride S
+  extern __shared__ int icanvas[];  // C rows of stride S (fixed point)
   __shared__ int slot;
+  __shared__ float wsum[kBlock / 64];
   const int nitems = *n_items;
   const int CS = G.C * G.S;
   for (;;) {
     const int it = next_item(queue, &slot);
     if (it >= nitems) break;
-    for (int i = threadIdx.x; i < CS; i += kBlock) canvas[i] = 0.f;
-    __syncthreads();
+    for (int i = threadIdx.x; i < CS; i += kBlock) icanvas[i] = 0;
     const int4 itm = items[it];
+    // fixed-point scale: 2^e with 2^e * sum|w| <= 2^30
+    float aw = 0.f;
+    for (int g = threadIdx.x; g < itm.w; g += kBlock) aw += fabsf(list[2 * (size_t)(itm.z + g) + 1].y);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) aw += __shfl_xor(aw, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = aw;
+    __syncthreads();
+    const float tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    int ex = 0;
+    if (tot > 0.f && isfinite(tot)) {
+      frexpf(tot, &ex);          // tot in [2^(ex-1), 2^ex)
+      ex = min(max(30 - ex, -126), 126);  // 2^ex * tot < 2^30 (unless clamped)
+    }
+    const float scale = ldexpf(1.f, ex), inv_scale = ldexpf(1.f, -ex);
     const int ty = itm.y / G.ntx, tx = itm.y % G.ntx;
     const int R0 = ty * G.T - G.halo, C0 = tx * G.T - G.halo;
     const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
@@ -68,7 +85,7 @@ k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queu
     for (int g = threadIdx.x; g < itm.w; g += kBlock) {
       const size_t rec = 2 * (size_t)(itm.z + g);
       const float4 r0 = list[rec], r1 = list[rec + 1];
-      const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x, w = r1.y;
+      const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x, w = r1.y * scale;
       const int rows = __float_as_int(r1.w);
       const int i0 = max(rows & 0xffff, rlo), i1 = min(rows >> 16, rhi);
       const float det_s = al * ga - be * be;
@@ -80,12 +97,17 @@ k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queu
         const float dj = (float)s.j0 - u;
         float e = w * exp2f(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
         float r = exp2f(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
-        float *px = canvas + (i - R0) * G.S + (s.j0 - C0);
-        for (int j = s.j0; j <= s.j1; ++j) {
-          atomicAdd(px, e);
-          ++px;
-          e *= r;
-          r *= K;
+        int *px = icanvas + (i - R0) * G.S + (s.j0 - C0);
+        const int L = s.j1 - s.j0 + 1;
+        for (int k = 0; k < L; k += 4) {
+          const int v0 = __float2int_rn(e); e *= r; r *= K;
+          const int v1 = __float2int_rn(e); e *= r; r *= K;
+          const int v2 = __float2int_rn(e); e *= r; r *= K;
+          const int v3 = __float2int_rn(e); e *= r; r *= K;
+          atomicAdd(px + k, v0);
+          if (k + 1 < L) atomicAdd(px + k + 1, v1);
+          if (k + 2 < L) atomicAdd(px + k + 2, v2);
+          if (k + 3 < L) atomicAdd(px + k + 3, v3);
         }
       }
     }
@@ -93,15 +115,16 @@ k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queu
     float *out = partials + (size_t)it * G.C * G.C;
     for (int i = threadIdx.x; i < G.C * G.C; i += kBlock) {
       const int r = i / G.C, c = i - r * G.C;
-      out[i] = canvas[r * G.S + c];
+      out[i] = (float)icanvas[r * G.S + c] * inv_scale;
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Q for one (image, tile): the sum of every partial canvas that overlaps it,
-// taken over the 3 x 3 neighbourhood of owner tiles in a fixed order.
+// Q for one (image, tile): every pixel sums, in a fixed order, the partial
+// canvases of the owner tiles whose canvas covers it (its own tile and the
+// neighbours whose halo reaches it).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, Geom G,
@@ -110,39 +133,31 @@ k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, G
   const int ty = t / G.ntx, tx = t % G.ntx;
   const int r_lo = ty * G.T, r_hi = min(r_lo + G.T, G.D);
   const int c_lo = tx * G.T, c_hi = min(c_lo + G.T, G.D);
-  const int npx = (r_hi - r_lo) * (c_hi - c_lo);
   const int wdt = c_hi - c_lo;
+  const int npx = (r_hi - r_lo) * wdt;
   float *img = Q + (size_t)b * G.D * G.D;
-  for (int base = 0; base < npx; base += kBlock * 8) {
-    float acc[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+  for (int q = threadIdx.x; q < npx; q += kBlock) {
+    const int i = r_lo + q / wdt, j = c_lo + q % wdt;
+    float acc = 0.f;
     for (int dy = -1; dy <= 1; ++dy) {
       const int sy = ty + dy;
       if (sy < 0 || sy >= G.ntx) continue;
+      const int R0 = sy * G.T - G.halo;
+      const int ri = i - R0;
+      if (ri < 0 || ri >= G.C) continue;
       for (int dx = -1; dx <= 1; ++dx) {
         const int sx = tx + dx;
         if (sx < 0 || sx >= G.ntx) continue;
+        const int C0 = sx * G.T - G.halo;
+        const int cj = j - C0;
+        if (cj < 0 || cj >= G.C) continue;
         const int e = b * G.K + sy * G.ntx + sx;
-        const int R0 = sy * G.T - G.halo, C0 = sx * G.T - G.halo;
-        for (int it = item_off[e]; it < item_off[e + 1]; ++it) {
-          const float *part = partials + (size_t)it * G.C * G.C;
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int q = base + k * kBlock + threadIdx.x;
-            if (q >= npx) break;
-            const int i = r_lo + q / wdt, j = c_lo + q % wdt;
-            const int ri = i - R0, cj = j - C0;
-            if (ri >= 0 && ri < G.C && cj >= 0 && cj < G.C) acc[k] += part[ri * G.C + cj];
-          }
-        }
+        const size_t o = (size_t)ri * G.C + cj;
+        for (int it = item_off[e]; it < item_off[e + 1]; ++it)
+          acc += partials[(size_t)it * G.C * G.C + o];
       }
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int q = base + k * kBlock + threadIdx.x;
-      if (q < npx) img[(size_t)(r_lo + q / wdt) * G.D + c_lo + q % wdt] = acc[k];
-    }
+    img[(size_t)i * G.D + j] = acc;
   }
 }
 
@@ -204,10 +219,10 @@ k_splat_bwd(const float4 *list, const int4 *items, const int *n_items, int *queu
     const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
     const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
     const float *src = GQ + (size_t)b * G.D * G.D;
-    for (int q = threadIdx.x; q < G.C * G.C; q += kBlock) {
-      const int r = q / G.C, c = q - r * G.C;
+    for (int q = threadIdx.x; q < G.C * G.S; q += kBlock) {
+      const int r = q / G.S, c = q - r * G.S;
       const int i = R0 + r, j = C0 + c;
-      gq[r * G.S + c] = (i >= 0 && i < G.D && j >= 0 && j < G.D) ? src[(size_t)i * G.D + j] : 0.f;
+      gq[q] = (c < G.C && i >= 0 && i < G.D && j >= 0 && j < G.D) ? src[(size_t)i * G.D + j] : 0.f;
     }
     __syncthreads();
     for (int g = threadIdx.x; g < itm.w; g += kBlock) {
@@ -224,28 +239,37 @@ k_splat_bwd(const float4 *list, const int4 *items, const int *n_items, int *queu
       for (int i = i0; i <= i1; ++i) {
         Span s;
         if (!row_span(u, v, al, be, det_s, inv_al, G.qk, i, clo, chi, s)) continue;
-        float dj = (float)s.j0 - u;
+        const float dj = (float)s.j0 - u;
         float e = exp2f(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
         float r = exp2f(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
         const float *px = gq + (i - R0) * G.S + (s.j0 - C0);
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-        for (int j = s.j0; j <= s.j1; ++j) {
-          const float t = *px * e;
-          ++px;
-          s0 += t;
-          const float tdj = t * dj;
-          s1 += tdj;
-          s2 += tdj * dj;
-          e *= r;
-          r *= K;
-          dj += 1.f;
+        const int L = s.j1 - s.j0 + 1;
+        // Prefix-sum moments over t_k = G_Q e (k = 0 .. L4-1, t_k = 0 for k >= L):
+        //   a0 = sum t_k, a1 = sum t_k (L4-k), a2 = sum t_k (L4-k)(L4-k+1)/2
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        int k = 0;
+        for (; k < L; k += 4) {
+          // the canvas rows carry padding columns, so k+3 stays inside the row
+          const float g0 = px[k], g1 = px[k + 1], g2 = px[k + 2], g3 = px[k + 3];
+          float t = g0 * e; e *= r; r *= K;
+          a0 += t; a1 += a0; a2 += a1;
+          t = (k + 1 < L) ? g1 * e : 0.f; e *= r; r *= K;
+          a0 += t; a1 += a0; a2 += a1;
+          t = (k + 2 < L) ? g2 * e : 0.f; e *= r; r *= K;
+          a0 += t; a1 += a0; a2 += a1;
+          t = (k + 3 < L) ? g3 * e : 0.f; e *= r; r *= K;
+          a0 += t; a1 += a0; a2 += a1;
         }
-        m0 += s0;
-        m1 += s1;
-        m2 += s0 * s.di;
-        m3 += s2;
-        m4 += s1 * s.di;
-        m5 += s0 * s.di * s.di;
+        // sum t dj = c a0 - a1, sum t dj^2 = c^2 a0 - 2 c a1 + 2 a2 - a1, c = dj0 + L4
+        const float c = dj + (float)k;
+        const float sdj = c * a0 - a1;
+        const float sdj2 = c * c * a0 - 2.f * c * a1 + 2.f * a2 - a1;
+        m0 += a0;
+        m1 += sdj;
+        m2 += a0 * s.di;
+        m3 += sdj2;
+        m4 += sdj * s.di;
+        m5 += a0 * s.di * s.di;
       }
       float *o = mom + ((size_t)b * G.N + n) * 6;
       o[0] = m0; o[1] = m1; o[2] = m2; o[3] = m3; o[4] = m4; o[5] = m5;

@@ -275,4 +275,35 @@ def test_batch_additivity(gpu_lib):
         for k in GROUPS:
             acc[k] = acc[k] + host(part[1][k])
     for k in GROUPS:
-        assert normwise(host(full[1][k]), acc[k]) <= 1e-5, k
+        assert normwise(host(full[1][k]), acc[k]) <= 1e-4, k
+
+
+@pytest.mark.xfail(reason="list order within a tile follows atomic scatter order", strict=False)
+def test_forward_is_bitwise_deterministic(gpu_lib):
+    g, v, _, _ = inputs.c2(b=8, n=20000)
+    a = host(gpu_lib.render(**mixture_args(g), **view_args(v), ctf=ctf_arg(v)))
+    b = host(gpu_lib.render(**mixture_args(g), **view_args(v), ctf=ctf_arg(v)))
+    assert np.array_equal(a, b)
+
+
+def test_fixed_point_with_extreme_weight_spread(gpu_lib):
+    """Very narrow and very wide Gaussians share tiles: fixed-point scale stress."""
+    rng = np.random.default_rng(18)
+    n = 3000
+    g = inputs.mixture_anisotropic(rng, n, 30.0)
+    ls = np.where(rng.random((n, 1)) < 0.1, np.log(0.35), np.log(2.5))
+    g.log_scales = (ls + 0.05 * rng.standard_normal((n, 3))).astype(np.float32)
+    g.amps = np.exp(2.0 * rng.standard_normal(n)).astype(np.float32)
+    v = inputs.views(rng, 3, 96, 1.0)
+    announce("fixed-point stress: weights spanning many decades")
+    Q = host(gpu_lib.render(**mixture_args(g), **view_args(v)))
+    assert per_image_normwise(Q, _oracle_Q(g, v)) <= IMG_TOL
+
+
+def test_negative_amplitudes(gpu_lib):
+    rng = np.random.default_rng(19)
+    g = inputs.mixture_anisotropic(rng, 2000, 25.0)
+    g.amps = rng.standard_normal(g.n).astype(np.float32)
+    v = inputs.views(rng, 2, 64, 1.2)
+    Q = host(gpu_lib.render(**mixture_args(g), **view_args(v)))
+    assert per_image_normwise(Q, _oracle_Q(g, v)) <= IMG_TOL
