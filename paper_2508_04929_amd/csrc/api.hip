@@ -96,10 +96,11 @@ double electron_wavelength_A(double kv) {
 
 // Workspace carve-up for one call.
 struct Layout {
-  size_t gc = 0, key = 0, count = 0, off = 0, cursor = 0, item_off = 0, n_items = 0, queues = 0,
-         items = 0, list = 0, partials = 0, Q = 0, spec = 0, mom = 0, loss_part = 0;
+  size_t gc = 0, key = 0, count = 0, off = 0, blk = 0, item_off = 0, n_items = 0, queues = 0,
+         items = 0, list = 0, partials = 0, Q = 0, spec = 0, ctf = 0, mom = 0, loss_part = 0;
   size_t total = 0;
   int max_items = 0;
+  int nbx = 0;  // Gaussian blocks of the binning kernels
 };
 
 Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_fft) {
@@ -113,7 +114,8 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
   L.key = take(BN * 4 + 4);
   L.count = take(BK * 4);
   L.off = take(BK * 4);
-  L.cursor = take(BK * 4);
+  L.nbx = (int)((G.N + kBlock - 1) / kBlock);
+  L.blk = take(BK * (size_t)std::max(L.nbx, 1) * 4);
   L.item_off = take((BK + 1) * 4);
   L.n_items = take(16);
   L.queues = take(16);
@@ -121,7 +123,10 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
   L.list = take(BN * 32 + 32);
   if (need_partials) L.partials = take((size_t)L.max_items * G.C * G.C * 4);
   L.Q = take((size_t)G.B * G.D * G.D * 4);
-  if (need_fft) L.spec = take((size_t)G.B * G.D * (G.D / 2 + 1) * 8);
+  if (need_fft) {
+    L.spec = take((size_t)G.B * G.D * (G.D / 2 + 1) * 8);
+    L.ctf = take((size_t)G.B * G.D * (G.D / 2 + 1) * 4);
+  }
   if (need_mom) L.mom = take(BN * 24 + 32);
   L.loss_part = take((size_t)G.B * G.D * 4);
   L.total = o;
@@ -239,12 +244,15 @@ int launch_binning(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const 
   const dim3 bgrid(cdiv(G.N, kBlock), cdiv(G.B, kImgPerBinBlock));
   const size_t hist_bytes = (size_t)kImgPerBinBlock * G.K * 4;
   TLAUNCH(k_bin_count, bgrid, dim3(kBlock), hist_bytes, st, gc, v->rot, v->shift, G,
-                     (int *)(ws + L.key), count);
+          (int *)(ws + L.key), (int *)(ws + L.blk), L.nbx);
+  TLAUNCH(k_bin_blockscan, dim3((unsigned)BK), dim3(kBlock), 0, st, (int *)(ws + L.blk), L.nbx,
+          count);
   TLAUNCH(k_scan, dim3(1), dim3(1024), 0, st, count, G, (int *)(ws + L.off),
-                     (int *)(ws + L.cursor), (int4 *)(ws + L.items), (int *)(ws + L.item_off),
-                     (int *)(ws + L.n_items), (int *)(ws + L.queues));
-  TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), 2 * hist_bytes, st, gc, v->rot, v->shift,
-                     G, (const int *)(ws + L.key), (int *)(ws + L.cursor), (float4 *)(ws + L.list));
+          (int4 *)(ws + L.items), (int *)(ws + L.item_off), (int *)(ws + L.n_items),
+          (int *)(ws + L.queues));
+  TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), (size_t)(kBlock / 64) * G.K * 4, st, gc, v->rot,
+          v->shift, G, (const int *)(ws + L.key), (const int *)(ws + L.off),
+          (const int *)(ws + L.blk), L.nbx, (float4 *)(ws + L.list));
   return CS_OK;
 }
 
@@ -318,23 +326,45 @@ CtfDev make_ctf(const cs_ctf *ctf) {
   return c;
 }
 
+// Launch shapes of the FFT kernels for one image side.
+struct FftLaunch {
+  FftPlan P;
+  const float2 *tw = nullptr;
+  dim3 rgrid, cgrid;
+  size_t rlds = 0, clds = 0;
+  int cpw = 16;
+};
+
+int fft_setup(cs_ctx *ctx, const Geom &G, FftLaunch &F) {
+  fft_plan(G.D, F.P);
+  int rc = get_twiddles(ctx, G.D, &F.tw);
+  if (rc) return rc;
+  F.rgrid = dim3(cdiv(G.D / 2, 4), G.B);
+  F.rlds = (size_t)(4 * 2 + 1) * G.D * 8;  // four row pairs (ping-pong) + twiddles
+  F.cpw = G.D > 256 ? 8 : 16;
+  F.cgrid = dim3(cdiv(G.D / 2 + 1, F.cpw), G.B);
+  F.clds = (size_t)(F.cpw * 2 + 1) * G.D * 8;
+  return CS_OK;
+}
+
+int launch_ctf_table(cs_ctx *ctx, const Geom &G, const cs_ctf *ctf, float *table, hipStream_t st) {
+  const size_t n = (size_t)G.B * G.D * (G.D / 2 + 1);
+  TLAUNCH(k_ctf_table, dim3(cdiv(n, 256)), dim3(256), 0, st, G.D, G.pixel, make_ctf(ctf), G.B, table);
+  return CS_OK;
+}
+
 // src (real [B][D][D]) -> spec -> H^ -> dst (real), i.e. dst = F^-1(H^ F src).
 int launch_ctf_roundtrip(cs_ctx *ctx, const Geom &G, const cs_ctf *ctf, const float *src,
-                         float2 *spec, float *dst, hipStream_t st) {
-  FftPlan P;
-  fft_plan(G.D, P);
-  const float2 *tw = nullptr;
-  int rc = get_twiddles(ctx, G.D, &tw);
+                         float2 *spec, float *table, float *dst, hipStream_t st) {
+  FftLaunch F;
+  int rc = fft_setup(ctx, G, F);
   if (rc) return rc;
-  const dim3 rgrid(cdiv(G.D / 2, 4), G.B);
-  const size_t rlds = (size_t)4 * 2 * G.D * 8;
-  TLAUNCH(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, src, P, tw, G.B, spec);
-  const int cpw = G.D > 256 ? 8 : 16;
-  const dim3 cgrid(cdiv(G.D / 2 + 1, cpw), G.B);
-  const size_t clds = (size_t)cpw * 2 * G.D * 8;
-  TLAUNCH(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel,
-                     make_ctf(ctf));
-  TLAUNCH(k_fft_rows_inv, rgrid, dim3(256), rlds, st, (const float2 *)spec, P, tw, G.B, dst);
+  rc = launch_ctf_table(ctx, G, ctf, table, st);
+  if (rc) return rc;
+  TLAUNCH(k_fft_rows_fwd, F.rgrid, dim3(256), F.rlds, st, src, F.P, F.tw, G.B, spec);
+  TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw,
+          (const float *)table);
+  TLAUNCH(k_fft_rows_inv, F.rgrid, dim3(256), F.rlds, st, (const float2 *)spec, F.P, F.tw, G.B, dst);
   return CS_OK;
 }
 
@@ -423,7 +453,9 @@ int cs_render(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ct
   if (rc) return rc;
   rc = launch_forward(ctx, G, L, ws, Q, st);
   if (rc) return rc;
-  if (ctf) return launch_ctf_roundtrip(ctx, G, ctf, Q, (float2 *)(ws + L.spec), images, st);
+  if (ctf)
+    return launch_ctf_roundtrip(ctx, G, ctf, Q, (float2 *)(ws + L.spec), (float *)(ws + L.ctf),
+                                images, st);
   return CS_OK;
 }
 
@@ -443,7 +475,8 @@ int cs_render_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, co
   char *ws = (char *)ctx->ws;
   const float *GQ = d_images;
   if (ctf) {
-    rc = launch_ctf_roundtrip(ctx, G, ctf, d_images, (float2 *)(ws + L.spec), (float *)(ws + L.Q), st);
+    rc = launch_ctf_roundtrip(ctx, G, ctf, d_images, (float2 *)(ws + L.spec), (float *)(ws + L.ctf),
+                              (float *)(ws + L.Q), st);
     if (rc) return rc;
     GQ = (const float *)(ws + L.Q);
   }
@@ -482,27 +515,24 @@ int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, cons
   float *loss_part = (float *)(ws + L.loss_part);
   int parts;
   if (ctf) {
-    FftPlan P;
-    fft_plan(G.D, P);
-    const float2 *tw = nullptr;
-    rc = get_twiddles(ctx, G.D, &tw);
+    FftLaunch F;
+    rc = fft_setup(ctx, G, F);
     if (rc) return rc;
     float2 *spec = (float2 *)(ws + L.spec);
-    const dim3 rgrid(cdiv(G.D / 2, 4), G.B);
-    const size_t rlds = (size_t)4 * 2 * G.D * 8;
-    const int cpw = G.D > 256 ? 8 : 16;
-    const dim3 cgrid(cdiv(G.D / 2 + 1, cpw), G.B);
-    const size_t clds = (size_t)cpw * 2 * G.D * 8;
-    const CtfDev cd = make_ctf(ctf);
-    TLAUNCH(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, Q, P, tw, G.B, spec);
-    TLAUNCH(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel, cd);
-    TLAUNCH(k_fft_rows_inv_loss, rgrid, dim3(256), rlds, st, spec, P, tw, G.B, observed,
-                       images_out, gscale, loss_part);
+    float *table = (float *)(ws + L.ctf);
+    rc = launch_ctf_table(ctx, G, ctf, table, st);
+    if (rc) return rc;
+    TLAUNCH(k_fft_rows_fwd, F.rgrid, dim3(256), F.rlds, st, Q, F.P, F.tw, G.B, spec);
+    TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw,
+            (const float *)table);
+    TLAUNCH(k_fft_rows_inv_loss, F.rgrid, dim3(256), F.rlds, st, spec, F.P, F.tw, G.B, observed,
+            images_out, gscale, loss_part);
     parts = G.D / 2;
     if (want_grads) {
-      TLAUNCH(k_fft_cols_ctf, cgrid, dim3(256), clds, st, spec, P, tw, G.B, cpw, G.pixel, cd);
-      TLAUNCH(k_fft_rows_inv, rgrid, dim3(256), rlds, st, (const float2 *)spec, P, tw,
-                         G.B, Q);
+      TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw,
+              (const float *)table);
+      TLAUNCH(k_fft_rows_inv, F.rgrid, dim3(256), F.rlds, st, (const float2 *)spec, F.P, F.tw,
+              G.B, Q);
     }
   } else {
     TLAUNCH(k_residual, dim3(G.D, G.B), dim3(256), 0, st, Q, observed, images_out, G.B,

@@ -3,10 +3,11 @@
 // Data flow of one loss_and_grad call (all on the caller's stream):
 //   k_build        per Gaussian: activations, Sigma = R diag(s)^2 R^T (Eq. 5)
 //   k_bin_count    per (image, Gaussian): projection (Eq. 6, 8, 12, 13), cull,
-//                  owner tile, per-tile counts
+//                  owner tile, per-block bin counts
+//   k_bin_blockscan per bin: scan of the block counts, bin totals
 //   k_scan         exclusive scans -> list offsets, work items (tile chunks)
 //   k_bin_scatter  per (image, Gaussian): 32-byte splat record into its
-//                  owner tile's segment of the list
+//                  owner tile's segment of the list (stable: by index)
 //   k_splat_fwd    per work item: additive splat (Eq. 9) into an LDS canvas
 //                  covering the owner tile plus a halo -> partial canvases
 //   k_canvas_reduce per tile: sum of the overlapping partial canvases -> Q
@@ -132,13 +133,16 @@ __global__ void k_build(const float *means, const float *log_scales, const float
                         const float *amps, Geom G, float4 *gc, int *zero_buf, int zero_count);
 
 __global__ void k_bin_count(const float4 *gc, const float *rot, const float *shift, Geom G,
-                            int *key, int *count);
+                            int *key, int *blk, int nbx);
 
-__global__ void k_scan(const int *count, Geom G, int *off, int *cursor, int4 *items,
-                       int *item_off, int *n_items, int *queues);
+__global__ void k_bin_blockscan(int *blk, int nbx, int *count);
+
+__global__ void k_scan(const int *count, Geom G, int *off, int4 *items, int *item_off,
+                       int *n_items, int *queues);
 
 __global__ void k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G,
-                              const int *key, int *cursor, float4 *list);
+                              const int *key, const int *off, const int *blk, int nbx,
+                              float4 *list);
 
 __global__ void k_splat_fwd(const float4 *list, const int4 *items, const int *n_items,
                             int *queue, Geom G, float *partials);
@@ -170,8 +174,10 @@ __global__ void k_fill(float *p, int64_t n, float value);
 
 __global__ void k_fft_rows_fwd(const float *src, FftPlan P, const float2 *tw, int B, float2 *spec);
 
+__global__ void k_ctf_table(int L, float pixel, CtfDev ctf, int B, float *table);
+
 __global__ void k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw,
-                               float pixel, CtfDev ctf);
+                               const float *table);
 
 __global__ void k_fft_rows_inv(const float2 *spec, FftPlan P, const float2 *tw, int B,
                                float *dst);

@@ -114,10 +114,12 @@ k_fft_rows_fwd(const float *src, FftPlan P, const float2 *tw, int B, float2 *spe
   const int b = blockIdx.y;
   const bool valid = pr < L / 2;
   float2 *x = lds + team * 2 * L, *y = x + L;
+  float2 *twl = lds + kRowTeams * 2 * L;
+  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
   const float *ra = src + ((size_t)b * L + 2 * pr) * L;
   for (int j = t; j < L; j += 64) x[j] = valid ? make_float2(ra[j], ra[L + j]) : make_float2(0.f, 0.f);
   __syncthreads();
-  const float2 *res = fft_team(x, y, P, tw, t, 64, false);
+  const float2 *res = fft_team(x, y, P, twl, t, 64, false);
   float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
   split_store(res, L, t, sa, sa + Dh, valid);
 }
@@ -162,13 +164,26 @@ __device__ float ctf_grid_value(int ky, int kx, int L, float pixel, const CtfDev
   return (float)h;
 }
 
+// H^ / D^2 on the half-spectrum grid [B][D][D/2+1], once per call.
+__global__ void __launch_bounds__(256)
+k_ctf_table(int L, float pixel, CtfDev ctf, int B, float *table) {
+  const int Dh = L / 2 + 1;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t per = (size_t)L * Dh;
+  if (idx >= per * B) return;
+  const int b = (int)(idx / per);
+  const int r = (int)(idx % per);
+  const int ky = r / Dh, kx = r % Dh;
+  const float norm = 1.f / ((float)L * (float)L);
+  table[idx] = (ctf.enabled ? ctf_grid_value(ky, kx, L, pixel, ctf, b) : 1.f) * norm;
+}
+
 // ---------------------------------------------------------------------------
 // Column pass: for cpw adjacent half-spectrum columns per block, FFT over
-// rows, times H^ / D^2, inverse FFT over rows, in place.
+// rows, times the table H^ / D^2, inverse FFT over rows, in place.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
-k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, float pixel,
-               CtfDev ctf) {
+k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, const float *table) {
   extern __shared__ float2 lds[];
   const int L = P.L, Dh = L / 2 + 1;
   const int b = blockIdx.y;
@@ -176,6 +191,8 @@ k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, float 
   const int ts = 256 / cpw;
   const int team = threadIdx.x / ts, t = threadIdx.x % ts;
   float2 *img = spec + (size_t)b * L * Dh;
+  float2 *twl = lds + (size_t)cpw * 2 * L;
+  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
   // coalesced load: consecutive threads take consecutive columns of a row
   for (int q = threadIdx.x; q < cpw * L; q += 256) {
     const int c = q % cpw, r = q / cpw;
@@ -184,17 +201,17 @@ k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, float 
   }
   __syncthreads();
   float2 *x = lds + team * 2 * L, *y = x + L;
-  float2 *res = fft_team(x, y, P, tw, t, ts, false);
+  float2 *res = fft_team(x, y, P, twl, t, ts, false);
   const int kx = kx0 + team;
-  const float norm = 1.f / ((float)L * (float)L);
+  const float *hcol = table + (size_t)b * L * Dh;
   for (int ky = t; ky < L; ky += ts) {
-    const float h = (ctf.enabled && kx < Dh) ? ctf_grid_value(ky, kx, L, pixel, ctf, b) : 1.f;
+    const float h = (kx < Dh) ? hcol[(size_t)ky * Dh + kx] : 0.f;
     const float2 z = res[ky];
-    res[ky] = make_float2(z.x * h * norm, z.y * h * norm);
+    res[ky] = make_float2(z.x * h, z.y * h);
   }
   __syncthreads();
   float2 *other = (res == x) ? y : x;
-  float2 *out = fft_team(res, other, P, tw, t, ts, true);
+  float2 *out = fft_team(res, other, P, twl, t, ts, true);
   // every team's result sits in the same half of its buffer pair
   const int oofs = (int)(out - (lds + team * 2 * L));
   for (int q = threadIdx.x; q < cpw * L; q += 256) {
@@ -235,10 +252,12 @@ k_fft_rows_inv(const float2 *spec, FftPlan P, const float2 *tw, int B, float *ds
   const int b = blockIdx.y;
   const bool valid = pr < L / 2;
   float2 *x = lds + team * 2 * L, *y = x + L;
+  float2 *twl = lds + kRowTeams * 2 * L;
+  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
   const float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
   pack_inverse(sa, sa + Dh, L, t, x, valid);
   __syncthreads();
-  const float2 *res = fft_team(x, y, P, tw, t, 64, true);
+  const float2 *res = fft_team(x, y, P, twl, t, 64, true);
   if (valid) {
     float *ra = dst + ((size_t)b * L + 2 * pr) * L;
     for (int j = t; j < L; j += 64) {
@@ -264,10 +283,12 @@ k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, int B, const floa
   const int b = blockIdx.y;
   const bool valid = pr < L / 2;
   float2 *x = lds + team * 2 * L, *y = x + L;
+  float2 *twl = lds + kRowTeams * 2 * L;
+  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
   float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
   pack_inverse(sa, sa + Dh, L, t, x, valid);
   __syncthreads();
-  float2 *res = fft_team(x, y, P, tw, t, 64, true);
+  float2 *res = fft_team(x, y, P, twl, t, 64, true);
   float2 *other = (res == x) ? y : x;
   float acc = 0.f;
   const size_t row0 = ((size_t)b * L + 2 * pr) * L;
@@ -289,7 +310,7 @@ k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, int B, const floa
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (t == 0 && valid) loss_part[(size_t)b * (L / 2) + pr] = acc;
   __syncthreads();
-  const float2 *r2 = fft_team(other, res, P, tw, t, 64, false);
+  const float2 *r2 = fft_team(other, res, P, twl, t, 64, false);
   split_store(r2, L, t, sa, sa + Dh, valid);
 }
 

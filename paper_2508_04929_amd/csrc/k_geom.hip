@@ -72,12 +72,15 @@ __device__ __forceinline__ int tile_key(const Proj &P, const Geom &G) {
 }
 
 // ---------------------------------------------------------------------------
-// Binning pass 1: key per (image, Gaussian) and per-bin counts.
-// Block: 256 Gaussians x kImgPerBinBlock images; LDS histogram per image.
+// Binning pass 1: key per (image, Gaussian) and per-block bin counts.
+// Block (x, y): Gaussians [256 x, 256 x + 256) of images [8 y, 8 y + 8);
+// blk[(b K + k) nbx + x] receives the block's count of bin k of image b
+// (every bin, zeros included), so that a scan over x orders the bin's
+// entries by Gaussian index.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_bin_count(const float4 *gc, const float *rot, const float *shift, Geom G, int *key,
-            int *count) {
+            int *blk, int nbx) {
   extern __shared__ int hist[];  // [kImgPerBinBlock][K]
   const int n = blockIdx.x * kBlock + threadIdx.x;
   const int b0 = blockIdx.y * kImgPerBinBlock;
@@ -105,9 +108,40 @@ k_bin_count(const float4 *gc, const float *rot, const float *shift, Geom G, int 
   __syncthreads();
   for (int i = threadIdx.x; i < kImgPerBinBlock * G.K; i += kBlock) {
     const int b = b0 + i / G.K;
-    const int c = hist[i];
-    if (b < G.B && c) atomicAdd(&count[b * G.K + i % G.K], c);
+    if (b < G.B) blk[((size_t)b * G.K + i % G.K) * nbx + blockIdx.x] = hist[i];
   }
+}
+
+// Per bin: exclusive scan of the per-block counts over blocks (in place)
+// and the bin total.  One block of 256 threads per bin.
+__global__ void __launch_bounds__(kBlock)
+k_bin_blockscan(int *blk, int nbx, int *count) {
+  __shared__ int wsum[kBlock / 64];
+  int *row = blk + (size_t)blockIdx.x * nbx;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int carry = 0;
+  for (int base = 0; base < nbx; base += kBlock) {
+    const int x = base + threadIdx.x;
+    const int val = x < nbx ? row[x] : 0;
+    int inc = val;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int wpre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      wpre += (w < wid) ? wsum[w] : 0;
+      tot += wsum[w];
+    }
+    if (x < nbx) row[x] = carry + wpre + inc - val;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[blockIdx.x] = carry;
 }
 
 // Exclusive scan across one block of 1024 threads (16 waves of 64).
@@ -143,8 +177,8 @@ __device__ int block_scan_1024(int val, int *sh, int &total) {
 // owner tile.  Also resets the work-queue counters.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024)
-k_scan(const int *count, Geom G, int *off, int *cursor, int4 *items, int *item_off,
-       int *n_items, int *queues) {
+k_scan(const int *count, Geom G, int *off, int4 *items, int *item_off, int *n_items,
+       int *queues) {
   __shared__ int sh[16];
   const int total = G.B * G.K;
   const int seg = (total + 1023) / 1024;
@@ -161,7 +195,6 @@ k_scan(const int *count, Geom G, int *off, int *cursor, int4 *items, int *item_o
   for (int e = e0; e < e1; ++e) {
     const int c = count[e];
     off[e] = pre;
-    cursor[e] = pre;
     item_off[e] = ipre;
     const int t = e % G.K;
     if (t < G.ntiles) {
@@ -185,52 +218,58 @@ k_scan(const int *count, Geom G, int *off, int *cursor, int4 *items, int *item_o
 // (image, Gaussian) into its bin's segment of the list:
 //   rec0 = (u, v, al, be), rec1 = (ga, w, n, i0 | i1 << 16)
 // with (al, be, ga) the exp2-scaled pixel conic and [i0, i1] the clipped
-// row range of the q_cut ellipse.
+// row range of the q_cut ellipse.  The position is the bin offset plus the
+// block's scanned offset plus the stable rank inside the block, so every
+// bin lists its Gaussians in increasing index (a deterministic counting
+// sort; no device atomics).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, const int *key,
-              int *cursor, float4 *list) {
-  extern __shared__ int sm[];  // cnt[kImgPerBinBlock*K], base[kImgPerBinBlock*K]
-  int *cnt = sm;
-  int *base = sm + kImgPerBinBlock * G.K;
+              const int *off, const int *blk, int nbx, float4 *list) {
+  extern __shared__ int wcnt[];  // [kBlock/64][K] per-wave bin counts
   const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int b0 = blockIdx.y * kImgPerBinBlock;
-  for (int i = threadIdx.x; i < kImgPerBinBlock * G.K; i += kBlock) cnt[i] = 0;
-  __syncthreads();
-  int kk[kImgPerBinBlock], rank[kImgPerBinBlock];
-#pragma unroll
+  float4 g0 = make_float4(0, 0, 0, 0), g1 = g0, g2 = g0;
+  if (n < G.N) {
+    g0 = gc[3 * n];
+    g1 = gc[3 * n + 1];
+    g2 = gc[3 * n + 2];
+  }
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
     const int b = b0 + bi;
-    kk[bi] = -1;
-    rank[bi] = 0;
-    if (b < G.B && n < G.N) {
-      kk[bi] = key[(size_t)b * G.N + n];
-      if (kk[bi] >= 0) rank[bi] = atomicAdd(&cnt[bi * G.K + kk[bi]], 1);
+    if (b >= G.B) break;
+    for (int i = threadIdx.x; i < (kBlock / 64) * G.K; i += kBlock) wcnt[i] = 0;
+    __syncthreads();
+    const int k = (n < G.N) ? key[(size_t)b * G.N + n] : -1;
+    // stable rank among the lanes of this wave with the same bin
+    int rank = 0;
+    unsigned long long active = __ballot(k >= 0);
+    while (active) {
+      const int leader = __ffsll((long long)active) - 1;
+      const int kk = __shfl(k, leader, 64);
+      const unsigned long long m = __ballot(k == kk) & active;
+      if (k == kk) rank = __popcll(m & below);
+      if (lane == leader) wcnt[wid * G.K + kk] = __popcll(m);
+      active &= ~m;
     }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kImgPerBinBlock * G.K; i += kBlock) {
-    const int b = b0 + i / G.K;
-    const int c = cnt[i];
-    if (b < G.B && c) base[i] = atomicAdd(&cursor[b * G.K + i % G.K], c);
-  }
-  __syncthreads();
-  if (n >= G.N) return;
-  const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
-#pragma unroll
-  for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
-    if (kk[bi] < 0) continue;
-    const int b = b0 + bi;
-    float p0[3], p1[3], tx, ty;
-    load_pose(rot, shift, b, p0, p1, tx, ty);
-    Proj P;
-    project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
-    const int i0 = clamp_px(ceilf(P.v - P.hy), 0, G.D - 1);
-    const int i1 = clamp_px(floorf(P.v + P.hy), 0, G.D - 1);
-    const int pos = base[bi * G.K + kk[bi]] + rank[bi];
-    list[2 * (size_t)pos] = make_float4(P.u, P.v, P.al, P.be);
-    list[2 * (size_t)pos + 1] =
-        make_float4(P.ga, P.w, __int_as_float(n), __int_as_float(i0 | (i1 << 16)));
+    __syncthreads();
+    if (k >= 0) {
+      for (int w = 0; w < wid; ++w) rank += wcnt[w * G.K + k];
+      const int e = b * G.K + k;
+      const int pos = off[e] + blk[(size_t)e * nbx + blockIdx.x] + rank;
+      float p0[3], p1[3], tx, ty;
+      load_pose(rot, shift, b, p0, p1, tx, ty);
+      Proj P;
+      project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
+      const int i0 = clamp_px(ceilf(P.v - P.hy), 0, G.D - 1);
+      const int i1 = clamp_px(floorf(P.v + P.hy), 0, G.D - 1);
+      list[2 * (size_t)pos] = make_float4(P.u, P.v, P.al, P.be);
+      list[2 * (size_t)pos + 1] =
+          make_float4(P.ga, P.w, __int_as_float(n), __int_as_float(i0 | (i1 << 16)));
+    }
+    __syncthreads();
   }
 }
 

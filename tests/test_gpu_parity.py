@@ -278,12 +278,16 @@ def test_batch_additivity(gpu_lib):
         assert normwise(host(full[1][k]), acc[k]) <= 1e-4, k
 
 
-@pytest.mark.xfail(reason="list order within a tile follows atomic scatter order", strict=False)
 def test_forward_is_bitwise_deterministic(gpu_lib):
     g, v, _, _ = inputs.c2(b=8, n=20000)
     a = host(gpu_lib.render(**mixture_args(g), **view_args(v), ctf=ctf_arg(v)))
     b = host(gpu_lib.render(**mixture_args(g), **view_args(v), ctf=ctf_arg(v)))
     assert np.array_equal(a, b)
+    Y = np.zeros((8, 128, 128), np.float32)
+    ga = gpu_lib.loss_and_grad(**mixture_args(g), **view_args(v), observed=dev(Y), ctf=ctf_arg(v))[1]
+    gb = gpu_lib.loss_and_grad(**mixture_args(g), **view_args(v), observed=dev(Y), ctf=ctf_arg(v))[1]
+    for k in GROUPS:
+        assert np.array_equal(host(ga[k]), host(gb[k])), k
 
 
 def test_fixed_point_with_extreme_weight_spread(gpu_lib):
