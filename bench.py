@@ -130,6 +130,14 @@ def run(args):
         step_no[0] += 1
         lib.adam_step(flat, gflat, m, vv, step_no[0], lr=1e-3)
 
+    if args.calib_copy_mib > 0:
+        # a plain device copy of known size, for scaling the HBM byte counters
+        nel = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(nel, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -189,6 +197,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB before warm-up (counter calibration)")
     ap.add_argument("--cpu-images", type=int, default=16,
                     help="images of the workload timed through the CPU oracle (0 = skip)")
     args = ap.parse_args()

@@ -277,7 +277,8 @@ int launch_forward(cs_ctx *ctx, const Geom &G, const Layout &L, char *ws, float 
                      (const float *)(ws + L.partials), (const int *)(ws + L.item_off),
                      (const int4 *)(ws + L.items), G, Q);
   TLAUNCH(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
-                     (const int *)(ws + L.off), (const int *)(ws + L.count), G, Q);
+          (const int *)(ws + L.off), (const int *)(ws + L.count), (const int *)(ws + L.n_items) + 1,
+          G, Q);
   return CS_OK;
 }
 
@@ -292,7 +293,8 @@ int launch_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const
                      (const int4 *)(ws + L.items), (const int *)(ws + L.n_items),
                      (int *)(ws + L.queues) + 1, G, GQ, mom);
   TLAUNCH(k_big_bwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
-                     (const int *)(ws + L.off), (const int *)(ws + L.count), G, GQ, mom);
+          (const int *)(ws + L.off), (const int *)(ws + L.count), (const int *)(ws + L.n_items) + 1,
+          G, GQ, mom);
   TLAUNCH(k_chain, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, (const float4 *)(ws + L.gc),
                      g->log_scales, g->quats, g->amps, v->rot, v->shift, G,
                      (const int *)(ws + L.key), mom, grads->means, grads->log_scales,
@@ -539,8 +541,9 @@ int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, cons
                        G.D, gscale, loss_part);
     parts = G.D;
   }
-  TLAUNCH(k_loss_reduce, dim3(1), dim3(256), 0, st, (const float *)loss_part, G.B, parts,
-                     (float)scale, loss);
+  TLAUNCH(k_loss_reduce, dim3(G.B), dim3(256), 0, st, (const float *)loss_part, G.B, parts,
+          (float)scale, loss);
+  TLAUNCH(k_loss_total, dim3(1), dim3(256), 0, st, loss, G.B);
   if (!grads) return CS_OK;
   if (G.N == 0) return zero_grads(ctx, g, grads, st);
   return launch_backward(ctx, g, v, G, L, ws, Q, grads, st);

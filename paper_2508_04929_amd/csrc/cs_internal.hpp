@@ -150,14 +150,14 @@ __global__ void k_splat_fwd(const float4 *list, const int4 *items, const int *n_
 __global__ void k_canvas_reduce(const float *partials, const int *item_off, const int4 *items,
                                 Geom G, float *Q);
 
-__global__ void k_big_fwd(const float4 *list, const int *off, const int *count, Geom G,
-                          float *Q);
+__global__ void k_big_fwd(const float4 *list, const int *off, const int *count,
+                          const int *n_wide, Geom G, float *Q);
 
 __global__ void k_splat_bwd(const float4 *list, const int4 *items, const int *n_items,
                             int *queue, Geom G, const float *GQ, float *mom);
 
-__global__ void k_big_bwd(const float4 *list, const int *off, const int *count, Geom G,
-                          const float *GQ, float *mom);
+__global__ void k_big_bwd(const float4 *list, const int *off, const int *count,
+                          const int *n_wide, Geom G, const float *GQ, float *mom);
 
 __global__ void k_chain(const float4 *gc, const float *log_scales, const float *quats,
                         const float *amps, const float *rot, const float *shift, Geom G,
@@ -187,5 +187,7 @@ __global__ void k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, i
                                     float *loss_part);
 
 __global__ void k_loss_reduce(const float *loss_part, int B, int parts, float scale, float *loss);
+
+__global__ void k_loss_total(float *loss, int B);
 
 }  // namespace cs

@@ -314,26 +314,30 @@ k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, int B, const floa
   split_store(r2, L, t, sa, sa + Dh, valid);
 }
 
-// loss[b] = scale * sum of the row-pair partials of image b; loss[B] = total.
+// loss[b] = scale * sum of the row-pair partials of image b (one block per
+// image, FP64 sums), then loss[B] = the total in image order.
 __global__ void __launch_bounds__(256)
 k_loss_reduce(const float *loss_part, int B, int parts, float scale, float *loss) {
   __shared__ double red[4];
-  double total = 0.0;
-  for (int b = 0; b < B; ++b) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < parts; k += 256) s += (double)loss_part[(size_t)b * parts + k];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < parts; k += 256) s += (double)loss_part[(size_t)b * parts + k];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const double v = scale * (red[0] + red[1] + red[2] + red[3]);
-      loss[b] = (float)v;
-      total += v;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) loss[B] = (float)total;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) loss[b] = (float)(scale * (red[0] + red[1] + red[2] + red[3]));
+}
+
+__global__ void __launch_bounds__(256) k_loss_total(float *loss, int B) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < B; b += 256) s += (double)loss[b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) loss[B] = (float)(red[0] + red[1] + red[2] + red[3]);
 }
 
 }  // namespace cs

@@ -183,15 +183,17 @@ k_scan(const int *count, Geom G, int *off, int4 *items, int *item_off, int *n_it
   const int total = G.B * G.K;
   const int seg = (total + 1023) / 1024;
   const int e0 = min(threadIdx.x * seg, total), e1 = min(e0 + seg, total);
-  int s = 0, si = 0;
+  int s = 0, si = 0, sw = 0;
   for (int e = e0; e < e1; ++e) {
     const int c = count[e];
     s += c;
     if (e % G.K < G.ntiles) si += (c + G.budget - 1) / G.budget;
+    else sw += c;
   }
-  int tot, itot;
+  int tot, itot, wtot;
   int pre = block_scan_1024(s, sh, tot);
   int ipre = block_scan_1024(si, sh, itot);
+  block_scan_1024(sw, sh, wtot);
   for (int e = e0; e < e1; ++e) {
     const int c = count[e];
     off[e] = pre;
@@ -208,6 +210,7 @@ k_scan(const int *count, Geom G, int *off, int4 *items, int *item_off, int *n_it
   if (threadIdx.x == 0) {
     item_off[total] = itot;
     n_items[0] = itot;
+    n_items[1] = wtot;  // wide (beyond-halo) records
     queues[0] = 0;
     queues[1] = 0;
   }

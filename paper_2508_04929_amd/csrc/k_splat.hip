@@ -26,6 +26,11 @@ struct Span {
   float di;
 };
 
+// Hardware exp2/sqrt (v_exp_f32 / v_sqrt_f32, about 1 ulp; results below
+// 2^-126 flush to zero, far under the 1e-6 truncation of every term).
+__device__ __forceinline__ float hexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Exact column span of row i for the ellipse q <= q_cut, clipped to
 // [clo, chi].  Returns false for an empty row.
 __device__ __forceinline__ bool row_span(float u, float v, float al, float be, float det_s,
@@ -34,7 +39,7 @@ __device__ __forceinline__ bool row_span(float u, float v, float al, float be, f
   const float di = (float)i - v;
   const float disc = al * qk - det_s * di * di;
   if (!(disc >= 0.f)) return false;
-  const float h = sqrtf(disc) * inv_al;
+  const float h = hsqrt(disc) * inv_al;
   const float cen = u - be * di * inv_al;
   s.j0 = clamp_px(ceilf(cen - h), clo, chi + 1);
   s.j1 = clamp_px(floorf(cen + h), clo - 1, chi);
@@ -90,24 +95,31 @@ k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queu
       const int i0 = max(rows & 0xffff, rlo), i1 = min(rows >> 16, rhi);
       const float det_s = al * ga - be * be;
       const float inv_al = 1.f / al;
-      const float K = exp2f(-2.f * al);
+      const float K = hexp2(-2.f * al);
       for (int i = i0; i <= i1; ++i) {
         Span s;
         if (!row_span(u, v, al, be, det_s, inv_al, G.qk, i, clo, chi, s)) continue;
         const float dj = (float)s.j0 - u;
-        float e = w * exp2f(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
-        float r = exp2f(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
+        float e = w * hexp2(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
+        float r = hexp2(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
         int *px = icanvas + (i - R0) * G.S + (s.j0 - C0);
         const int L = s.j1 - s.j0 + 1;
-        for (int k = 0; k < L; k += 4) {
+        const int L4 = L & ~3;
+        int k = 0;
+        for (; k < L4; k += 4) {
           const int v0 = __float2int_rn(e); e *= r; r *= K;
           const int v1 = __float2int_rn(e); e *= r; r *= K;
           const int v2 = __float2int_rn(e); e *= r; r *= K;
           const int v3 = __float2int_rn(e); e *= r; r *= K;
           atomicAdd(px + k, v0);
-          if (k + 1 < L) atomicAdd(px + k + 1, v1);
-          if (k + 2 < L) atomicAdd(px + k + 2, v2);
-          if (k + 3 < L) atomicAdd(px + k + 3, v3);
+          atomicAdd(px + k + 1, v1);
+          atomicAdd(px + k + 2, v2);
+          atomicAdd(px + k + 3, v3);
+        }
+        for (; k < L; ++k) {
+          atomicAdd(px + k, __float2int_rn(e));
+          e *= r;
+          r *= K;
         }
       }
     }
@@ -202,7 +214,9 @@ __device__ __forceinline__ void wide_box(const float4 r0, const float4 r1, const
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_big_fwd(const float4 *list, const int *off, const int *count, Geom G, float *Q) {
+k_big_fwd(const float4 *list, const int *off, const int *count, const int *n_wide, Geom G,
+          float *Q) {
+  if (*n_wide == 0) return;
   for (int b = 0; b < G.B; ++b) {
     const int e = b * G.K + G.ntiles;
     const int cnt = count[e], start = off[e];
@@ -259,34 +273,40 @@ k_splat_bwd(const float4 *list, const int4 *items, const int *n_items, int *queu
       const int i0 = max(rows & 0xffff, rlo), i1 = min(rows >> 16, rhi);
       const float det_s = al * ga - be * be;
       const float inv_al = 1.f / al;
-      const float K = exp2f(-2.f * al);
+      const float K = hexp2(-2.f * al);
       float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
       for (int i = i0; i <= i1; ++i) {
         Span s;
         if (!row_span(u, v, al, be, det_s, inv_al, G.qk, i, clo, chi, s)) continue;
         const float dj = (float)s.j0 - u;
-        float e = exp2f(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
-        float r = exp2f(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
+        float e = hexp2(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
+        float r = hexp2(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
         const float *px = gq + (i - R0) * G.S + (s.j0 - C0);
         const int L = s.j1 - s.j0 + 1;
-        // Prefix-sum moments over t_k = G_Q e (k = 0 .. L4-1, t_k = 0 for k >= L):
-        //   a0 = sum t_k, a1 = sum t_k (L4-k), a2 = sum t_k (L4-k)(L4-k+1)/2
+        // Prefix-sum moments over t_k = G_Q e, k = 0 .. L-1:
+        //   a0 = sum t_k, a1 = sum t_k (L-k), a2 = sum t_k (L-k)(L-k+1)/2
         float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        const int L4 = L & ~3;
         int k = 0;
-        for (; k < L; k += 4) {
-          // the canvas rows carry padding columns, so k+3 stays inside the row
+        for (; k < L4; k += 4) {
           const float g0 = px[k], g1 = px[k + 1], g2 = px[k + 2], g3 = px[k + 3];
           float t = g0 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
-          t = (k + 1 < L) ? g1 * e : 0.f; e *= r; r *= K;
+          t = g1 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
-          t = (k + 2 < L) ? g2 * e : 0.f; e *= r; r *= K;
+          t = g2 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
-          t = (k + 3 < L) ? g3 * e : 0.f; e *= r; r *= K;
+          t = g3 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
         }
-        // sum t dj = c a0 - a1, sum t dj^2 = c^2 a0 - 2 c a1 + 2 a2 - a1, c = dj0 + L4
-        const float c = dj + (float)k;
+        for (; k < L; ++k) {
+          const float t = px[k] * e;
+          e *= r;
+          r *= K;
+          a0 += t; a1 += a0; a2 += a1;
+        }
+        // sum t dj = c a0 - a1, sum t dj^2 = c^2 a0 - 2 c a1 + 2 a2 - a1, c = dj0 + L
+        const float c = dj + (float)L;
         const float sdj = c * a0 - a1;
         const float sdj2 = c * c * a0 - 2.f * c * a1 + 2.f * a2 - a1;
         m0 += a0;
@@ -304,9 +324,10 @@ k_splat_bwd(const float4 *list, const int4 *items, const int *n_items, int *queu
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_big_bwd(const float4 *list, const int *off, const int *count, Geom G, const float *GQ,
-          float *mom) {
+k_big_bwd(const float4 *list, const int *off, const int *count, const int *n_wide, Geom G,
+          const float *GQ, float *mom) {
   __shared__ float red[6][kBlock / 64];
+  if (*n_wide == 0) return;
   for (int b = 0; b < G.B; ++b) {
     const int e = b * G.K + G.ntiles;
     const int cnt = count[e], start = off[e];
