@@ -115,12 +115,17 @@ typedef struct {
 } cs_grads;
 
 /* Launch options; pass NULL for defaults.  Results do not depend on tile,
- * halo or budget beyond floating-point summation order. */
+ * halo or budget beyond floating-point summation order (for fixed options
+ * every result is bitwise reproducible). */
 typedef struct {
   float q_cut;    /* squared-Mahalanobis truncation; <= 0 selects 2 ln 1e6 */
   int32_t tile;   /* owner-tile side in pixels (16..128); 0 = automatic */
   int32_t halo;   /* canvas halo in pixels (0..tile); 0 = automatic */
   int32_t budget; /* Gaussians per work item (>= 64); 0 = automatic */
+  int32_t graph;  /* cs_loss_and_grad: 1 = capture the launch sequence once per
+                     argument signature (shapes, pointers, scalars) as a HIP
+                     graph and replay it; the first call with a signature
+                     must not itself be inside a caller's stream capture */
 } cs_options;
 
 /* Create a context on HIP device `device`.  *out receives the handle. */
@@ -153,6 +158,43 @@ int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v,
                      const cs_ctf *ctf, const cs_options *opt,
                      const float *observed, int32_t reduction, float *loss,
                      cs_grads *grads, float *images_out, void *stream);
+
+/* One independent rendering problem of a batched call: a mixture, its
+ * images (each problem has its own D and pixel size), CTF (NULL = none),
+ * launch options (zeros = defaults), observed images and outputs.  Loss and
+ * gradient semantics are those of cs_loss_and_grad; a problem whose four
+ * gradient pointers are all NULL is evaluated without its adjoint. */
+typedef struct {
+  cs_gaussians g;
+  cs_views v;
+  const cs_ctf *ctf;
+  cs_options opt;
+  const float *observed; /* [B][D][D] */
+  int32_t reduction;     /* CS_SUM or CS_MEAN */
+  float *loss;           /* device [B+1] */
+  cs_grads grads;
+  float *images_out;     /* [B][D][D] or NULL */
+} cs_problem;
+
+/* Batched forward + loss + adjoint over `count` independent problems
+ * (uneven mixture sizes and image sides).  The per-problem setup kernels
+ * run back to back; the forward and the adjoint splat are each ONE
+ * persistent launch whose blocks drain the work queues of all problems in
+ * order, so small problems do not leave the GPU idle.  With use_graph = 1
+ * the whole sequence is captured once per argument signature into a HIP
+ * graph and replayed with a single hipGraphLaunch on `stream`.
+ * 1 <= count; every problem is validated as in cs_loss_and_grad. */
+int cs_loss_and_grad_multi(cs_ctx *ctx, const cs_problem *problems, int32_t count,
+                           int32_t use_graph, void *stream);
+
+/* Launch-option autotuner: for every problem, times cs_loss_and_grad over
+ * candidate (tile, halo, budget) settings (`reps` timed calls each, median)
+ * and writes the fastest into problems[i].opt (q_cut and graph are kept).
+ * Choices are cached per context by (D, N, B, pixel, CTF, q_cut) and, when
+ * the environment variable CS_AUTOTUNE_CACHE names a file, persisted there
+ * (a missing or malformed file means "no cached entries").  The problems'
+ * output buffers are overwritten while tuning.  Synchronises `stream`. */
+int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, void *stream);
 
 /* Adam step (Alg. 1, Sec. 4.1) over `count` FP32 parameters in place:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

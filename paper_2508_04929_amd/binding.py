@@ -49,12 +49,19 @@ class CsGrads(ctypes.Structure):
 
 class CsOptions(ctypes.Structure):
     _fields_ = [("q_cut", ctypes.c_float), ("tile", ctypes.c_int32), ("halo", ctypes.c_int32),
-                ("budget", ctypes.c_int32)]
+                ("budget", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
+class CsProblem(ctypes.Structure):
+    _fields_ = [("g", CsGaussians), ("v", CsViews), ("ctf", ctypes.POINTER(CsCtf)),
+                ("opt", CsOptions), ("observed", ctypes.c_void_p), ("reduction", ctypes.c_int32),
+                ("loss", ctypes.c_void_p), ("grads", CsGrads), ("images_out", ctypes.c_void_p)]
 
 
 #: Entry points declared in include/cryosplat.h.
 EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_backward",
-           "cs_loss_and_grad", "cs_adam_step", "cs_pair_count", "cs_set_timing", "cs_stage_time")
+           "cs_loss_and_grad", "cs_loss_and_grad_multi", "cs_autotune", "cs_adam_step",
+           "cs_pair_count", "cs_set_timing", "cs_stage_time")
 
 
 class CryoSplatError(RuntimeError):
@@ -84,6 +91,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_loss_and_grad.argtypes = [vp, P(CsGaussians), P(CsViews), P(CsCtf), P(CsOptions), vp,
                                      i32, vp, P(CsGrads), vp, vp]
     lib.cs_loss_and_grad.restype = ctypes.c_int
+    lib.cs_loss_and_grad_multi.argtypes = [vp, P(CsProblem), i32, i32, vp]
+    lib.cs_loss_and_grad_multi.restype = ctypes.c_int
+    lib.cs_autotune.argtypes = [vp, P(CsProblem), i32, i32, vp]
+    lib.cs_autotune.restype = ctypes.c_int
     lib.cs_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, i64, f32, f32, f32, f32, vp]
     lib.cs_adam_step.restype = ctypes.c_int
     lib.cs_pair_count.argtypes = [vp, P(CsGaussians), P(CsViews), P(CsOptions), vp, vp]
@@ -114,6 +125,34 @@ class Options:
     tile: int = 0
     halo: int = 0
     budget: int = 0
+    graph: int = 0       # 1: capture/replay the call as a HIP graph
+
+
+@dataclasses.dataclass
+class Problem:
+    """One independent problem of a batched call (device tensors).
+
+    ``loss`` [B+1] and the gradient tensors are outputs; they are allocated
+    by :meth:`Library.make_problem` and reused across calls so that a
+    captured graph stays valid.
+    """
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    amps: torch.Tensor
+    rot: torch.Tensor
+    shift: Optional[torch.Tensor]
+    D: int
+    pixel: float
+    observed: torch.Tensor
+    ctf: Optional[Ctf] = None
+    options: Optional[Options] = None
+    reduction: str = "sum"
+    loss: Optional[torch.Tensor] = None
+    grads: Optional[dict] = None
+    images_out: Optional[torch.Tensor] = None
+    scale_act: str = "exp"
+    amp_act: str = "identity"
 
 
 def _ptr(t: Optional[torch.Tensor], name: str, device, shape=None):
@@ -176,7 +215,8 @@ class Library:
                       float(ctf.bfactor))
         o = None
         if options is not None:
-            o = CsOptions(float(options.q_cut), int(options.tile), int(options.halo), int(options.budget))
+            o = CsOptions(float(options.q_cut), int(options.tile), int(options.halo),
+                          int(options.budget), int(options.graph))
         return dev, n, b, g, v, c, o
 
     @staticmethod
@@ -242,6 +282,66 @@ class Library:
             torch.cuda.current_stream(dev).cuda_stream)
         self._check(ctx, rc, "cs_loss_and_grad")
         return loss, (grads if want_grads else None), images
+
+    # -- batched problems -------------------------------------------------
+    def make_problem(self, means, log_scales, quats, amps, rot, shift, D, pixel, observed,
+                     ctf=None, options=None, reduction="sum", want_grads=True, want_images=False,
+                     scale_act="exp", amp_act="identity") -> Problem:
+        dev = rot.device
+        n, b = means.shape[0], rot.shape[0]
+        z = lambda *s: torch.zeros(s, device=dev, dtype=torch.float32)
+        grads = ({"means": z(n, 3), "log_scales": z(n, 3), "quats": z(n, 4), "amps": z(n)}
+                 if want_grads else None)
+        return Problem(means, log_scales, quats, amps, rot, shift, D, pixel, observed, ctf,
+                       options or Options(), reduction, z(b + 1), grads,
+                       z(b, D, D) if want_images else None, scale_act, amp_act)
+
+    def _problem_struct(self, pr: Problem):
+        dev, n, b, g, v, c, o = self._pack(pr.means, pr.log_scales, pr.quats, pr.amps, pr.rot,
+                                           pr.shift, pr.D, pr.pixel, pr.ctf,
+                                           pr.options or Options(), pr.scale_act, pr.amp_act)
+        _ptr(pr.observed, "observed", dev, (b, pr.D, pr.D))
+        _ptr(pr.loss, "loss", dev, (b + 1,))
+        cg = CsGrads()
+        if pr.grads is not None:
+            cg = CsGrads(*(_ptr(pr.grads[k], k, dev) for k in ("means", "log_scales", "quats", "amps")))
+        io = _ptr(pr.images_out, "images_out", dev, (b, pr.D, pr.D)) if pr.images_out is not None else None
+        s = CsProblem(g, v, ctypes.pointer(c) if c is not None else None, o, pr.observed.data_ptr(),
+                      CS_MEAN if pr.reduction == "mean" else CS_SUM, pr.loss.data_ptr(), cg, io)
+        return dev, s, c
+
+    def _problem_array(self, problems):
+        structs, keep, dev = [], [], None
+        for pr in problems:
+            dev, s, c = self._problem_struct(pr)
+            structs.append(s)
+            keep.append(c)
+        arr = (CsProblem * len(structs))(*structs)
+        return dev, arr, keep
+
+    def loss_and_grad_multi(self, problems, use_graph=True):
+        """All problems' losses and gradients in one batched call (writes pr.loss / pr.grads)."""
+        dev, arr, keep = self._problem_array(problems)
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_loss_and_grad_multi(ctx, arr, len(problems), 1 if use_graph else 0,
+                                             torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_loss_and_grad_multi")
+        del keep
+        return problems
+
+    def autotune(self, problems, reps=2):
+        """Choose tile/halo/budget per problem (writes pr.options)."""
+        dev, arr, keep = self._problem_array(problems)
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_autotune(ctx, arr, len(problems), int(reps),
+                                  torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_autotune")
+        for pr, s in zip(problems, arr):
+            base = pr.options or Options()
+            pr.options = Options(q_cut=base.q_cut, tile=s.opt.tile, halo=s.opt.halo,
+                                 budget=s.opt.budget, graph=base.graph)
+        del keep
+        return problems
 
     def adam_step(self, params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         dev = params.device

@@ -1,10 +1,14 @@
-// Host side of libcryosplat: argument validation, workspace, launch order.
+// Host side of libcryosplat: argument validation, workspace, launch order,
+// batching of several problems, HIP-graph capture and the autotuner.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -26,6 +30,13 @@ struct cs_ctx {
   struct Pending { const char *name; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, int64_t>> stage_ms;
+  // graph capture
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
+  // autotuner cache: signature -> (tile, halo, budget)
+  std::map<std::string, std::vector<int>> tuned;
+  std::string tune_file;
 };
 
 namespace {
@@ -52,30 +63,32 @@ int fail(cs_ctx *c, int code, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(ctx, CS_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
 
-// Launch with optional event bracketing (stage timing).
-#define TLAUNCH(kernel, grid, block, lds, st, ...)                                    \
-  do {                                                                               \
-    hipEvent_t ea_ = nullptr, eb_ = nullptr;                                         \
-    if (ctx->timing) {                                                               \
-      (void)hipEventCreate(&ea_);                                                    \
-      (void)hipEventCreate(&eb_);                                                    \
-      (void)hipEventRecord(ea_, st);                                                 \
-    }                                                                                \
-    hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);        \
-    LAUNCHCHK(#kernel);                                                              \
-    if (ctx->timing) {                                                               \
-      (void)hipEventRecord(eb_, st);                                                 \
-      ctx->pending.push_back({#kernel, ea_, eb_});                                   \
-    }                                                                                \
-  } while (0)
-
 #define LAUNCHCHK(name)                                                              \
   do {                                                                               \
     hipError_t e_ = hipGetLastError();                                               \
     if (e_ != hipSuccess) return fail(ctx, CS_ERR_HIP, "launch %s: %s", name, hipGetErrorString(e_)); \
   } while (0)
 
+// Launch with optional event bracketing (stage timing; off during capture).
+#define TLAUNCH(kernel, grid, block, lds, st, ...)                                   \
+  do {                                                                               \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                                         \
+    const bool tm_ = ctx->timing && !ctx->capturing;                                 \
+    if (tm_) {                                                                       \
+      (void)hipEventCreate(&ea_);                                                    \
+      (void)hipEventCreate(&eb_);                                                    \
+      (void)hipEventRecord(ea_, st);                                                 \
+    }                                                                                \
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);                   \
+    LAUNCHCHK(#kernel);                                                              \
+    if (tm_) {                                                                       \
+      (void)hipEventRecord(eb_, st);                                                 \
+      ctx->pending.push_back({#kernel, ea_, eb_});                                   \
+    }                                                                                \
+  } while (0)
+
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 bool fft_plan(int L, FftPlan &P) {
   if (L < 2 || L > kMaxD) return false;
@@ -94,13 +107,44 @@ double electron_wavelength_A(double kv) {
   return h / std::sqrt(2.0 * m0 * eV * (1.0 + eV / (2.0 * m0 * c * c))) * 1e10;
 }
 
-// Workspace carve-up for one call.
+// ---------------------------------------------------------------------------
+// Per-problem plan
+// ---------------------------------------------------------------------------
+enum Mode { RENDER, BACKWARD, LOSS };
+
 struct Layout {
   size_t gc = 0, key = 0, count = 0, off = 0, blk = 0, item_off = 0, n_items = 0, queues = 0,
          items = 0, list = 0, partials = 0, Q = 0, spec = 0, ctf = 0, mom = 0, loss_part = 0;
   size_t total = 0;
   int max_items = 0;
   int nbx = 0;  // Gaussian blocks of the binning kernels
+};
+
+struct Plan {
+  Mode mode = LOSS;
+  cs_gaussians g{};
+  cs_views v{};
+  const cs_ctf *ctf = nullptr;
+  Geom G{};
+  Layout L;
+  char *ws = nullptr;  // this problem's workspace region
+  bool fwd = false;    // runs the forward splat
+  bool bwd = false;    // runs the adjoint
+  // RENDER
+  float *images = nullptr;
+  // BACKWARD
+  const float *d_images = nullptr;
+  // LOSS
+  const float *observed = nullptr;
+  int reduction = CS_SUM;
+  float *loss = nullptr;
+  float *images_out = nullptr;
+  cs_grads grads{};
+  float *Q() const { return (float *)(ws + L.Q); }
+  const float *GQ() const {
+    if (mode == BACKWARD && !ctf) return d_images;
+    return (const float *)(ws + L.Q);
+  }
 };
 
 Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_fft) {
@@ -110,11 +154,11 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
   const size_t BN = (size_t)G.B * G.N;
   const size_t BK = (size_t)G.B * G.K;
   L.max_items = (int)((size_t)G.B * G.ntiles + (BN + G.budget - 1) / G.budget);
+  L.nbx = (int)((G.N + kBlock - 1) / kBlock);
   L.gc = take((size_t)G.N * 48 + 16);
   L.key = take(BN * 4 + 4);
   L.count = take(BK * 4);
   L.off = take(BK * 4);
-  L.nbx = (int)((G.N + kBlock - 1) / kBlock);
   L.blk = take(BK * (size_t)std::max(L.nbx, 1) * 4);
   L.item_off = take((BK + 1) * 4);
   L.n_items = take(16);
@@ -135,6 +179,7 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
 
 int ensure_ws(cs_ctx *ctx, size_t need, hipStream_t stream) {
   if (need <= ctx->ws_bytes) return CS_OK;
+  if (ctx->capturing) return fail(ctx, CS_ERR_HIP, "workspace growth during graph capture");
   if (ctx->ws_max && need > ctx->ws_max)
     return fail(ctx, CS_ERR_OOM, "workspace of %zu bytes exceeds CS_WORKSPACE_MAX=%zu", need,
                 ctx->ws_max);
@@ -143,6 +188,9 @@ int ensure_ws(cs_ctx *ctx, size_t need, hipStream_t stream) {
     HIPCHK(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
+    // graphs captured against the old workspace are stale
+    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
   }
   size_t want = need + need / 4;
   if (ctx->ws_max && want > ctx->ws_max) want = need;
@@ -158,6 +206,7 @@ int ensure_ws(cs_ctx *ctx, size_t need, hipStream_t stream) {
 int get_twiddles(cs_ctx *ctx, int L, const float2 **out) {
   auto it = ctx->twiddles.find(L);
   if (it != ctx->twiddles.end()) { *out = it->second; return CS_OK; }
+  if (ctx->capturing) return fail(ctx, CS_ERR_HIP, "twiddle upload during graph capture");
   std::vector<float2> h(L);
   for (int k = 0; k < L; ++k) {
     const double a = 2.0 * M_PI * (double)k / (double)L;
@@ -220,7 +269,7 @@ Geom make_geom(const cs_gaussians *g, const cs_views *v, const cs_options *opt) 
   G.T = (opt && opt->tile) ? opt->tile : kDefaultTile;
   G.halo = (opt && opt->halo) ? opt->halo : std::min(kDefaultHalo, G.T);
   G.C = G.T + 2 * G.halo;
-  G.S = G.C + 4;  // padding columns: unrolled row walks stay inside a row
+  G.S = G.C + 4;  // padding columns keep unrolled row walks inside a row
   G.ntx = (G.D + G.T - 1) / G.T;
   G.ntiles = G.ntx * G.ntx;
   G.K = G.ntiles + 1;
@@ -228,89 +277,6 @@ Geom make_geom(const cs_gaussians *g, const cs_views *v, const cs_options *opt) 
   G.scale_act = g->scale_act;
   G.amp_act = g->amp_act;
   return G;
-}
-
-unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
-
-// k_build + binning (count, scan, scatter).
-int launch_binning(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const Geom &G,
-                   const Layout &L, char *ws, hipStream_t st) {
-  float4 *gc = (float4 *)(ws + L.gc);
-  int *count = (int *)(ws + L.count);
-  const size_t BK = (size_t)G.B * G.K;
-  const size_t nb = std::max<size_t>((size_t)G.N, BK);
-  TLAUNCH(k_build, dim3(cdiv(nb, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
-          g->quats, g->amps, G, gc, count, (int)BK);
-  const dim3 bgrid(cdiv(G.N, kBlock), cdiv(G.B, kImgPerBinBlock));
-  const size_t hist_bytes = (size_t)kImgPerBinBlock * G.K * 4;
-  TLAUNCH(k_bin_count, bgrid, dim3(kBlock), hist_bytes, st, gc, v->rot, v->shift, G,
-          (int *)(ws + L.key), (int *)(ws + L.blk), L.nbx);
-  TLAUNCH(k_bin_blockscan, dim3((unsigned)BK), dim3(kBlock), 0, st, (int *)(ws + L.blk), L.nbx,
-          count);
-  TLAUNCH(k_scan, dim3(1), dim3(1024), 0, st, count, G, (int *)(ws + L.off),
-          (int4 *)(ws + L.items), (int *)(ws + L.item_off), (int *)(ws + L.n_items),
-          (int *)(ws + L.queues));
-  TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), (size_t)(kBlock / 64) * G.K * 4, st, gc, v->rot,
-          v->shift, G, (const int *)(ws + L.key), (const int *)(ws + L.off),
-          (const int *)(ws + L.blk), L.nbx, (float4 *)(ws + L.list));
-  return CS_OK;
-}
-
-int persistent_grid(cs_ctx *ctx, const void *kernel, size_t lds, int *grid) {
-  int nb = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, lds));
-  if (nb < 1) nb = 1;
-  *grid = nb * ctx->n_cu;
-  return CS_OK;
-}
-
-// Splat forward into Q (ws or caller buffer).
-int launch_forward(cs_ctx *ctx, const Geom &G, const Layout &L, char *ws, float *Q, hipStream_t st) {
-  const size_t lds = (size_t)G.C * G.S * 4;
-  int grid = 0;
-  int rc = persistent_grid(ctx, (const void *)k_splat_fwd, lds, &grid);
-  if (rc) return rc;
-  TLAUNCH(k_splat_fwd, dim3(grid), dim3(kBlock), lds, st, (const float4 *)(ws + L.list),
-                     (const int4 *)(ws + L.items), (const int *)(ws + L.n_items),
-                     (int *)(ws + L.queues), G, (float *)(ws + L.partials));
-  TLAUNCH(k_canvas_reduce, dim3(G.ntiles, G.B), dim3(kBlock), 0, st,
-                     (const float *)(ws + L.partials), (const int *)(ws + L.item_off),
-                     (const int4 *)(ws + L.items), G, Q);
-  TLAUNCH(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
-          (const int *)(ws + L.off), (const int *)(ws + L.count), (const int *)(ws + L.n_items) + 1,
-          G, Q);
-  return CS_OK;
-}
-
-int launch_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const Geom &G,
-                    const Layout &L, char *ws, const float *GQ, cs_grads *grads, hipStream_t st) {
-  const size_t lds = (size_t)G.C * G.S * 4;
-  int grid = 0;
-  int rc = persistent_grid(ctx, (const void *)k_splat_bwd, lds, &grid);
-  if (rc) return rc;
-  float *mom = (float *)(ws + L.mom);
-  TLAUNCH(k_splat_bwd, dim3(grid), dim3(kBlock), lds, st, (const float4 *)(ws + L.list),
-                     (const int4 *)(ws + L.items), (const int *)(ws + L.n_items),
-                     (int *)(ws + L.queues) + 1, G, GQ, mom);
-  TLAUNCH(k_big_bwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + L.list),
-          (const int *)(ws + L.off), (const int *)(ws + L.count), (const int *)(ws + L.n_items) + 1,
-          G, GQ, mom);
-  TLAUNCH(k_chain, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, (const float4 *)(ws + L.gc),
-                     g->log_scales, g->quats, g->amps, v->rot, v->shift, G,
-                     (const int *)(ws + L.key), mom, grads->means, grads->log_scales,
-                     grads->quats, grads->amps);
-  return CS_OK;
-}
-
-int zero_grads(cs_ctx *ctx, const cs_gaussians *g, cs_grads *grads, hipStream_t st) {
-  const int64_t n = g->n;
-  struct { float *p; int64_t k; } outs[4] = {
-      {grads->means, 3 * n}, {grads->log_scales, 3 * n}, {grads->quats, 4 * n}, {grads->amps, n}};
-  for (auto &o : outs) {
-    if (!o.p || o.k == 0) continue;
-    TLAUNCH(k_fill, dim3(cdiv(o.k, kBlock)), dim3(kBlock), 0, st, o.p, o.k, 0.f);
-  }
-  return CS_OK;
 }
 
 CtfDev make_ctf(const cs_ctf *ctf) {
@@ -326,6 +292,108 @@ CtfDev make_ctf(const cs_ctf *ctf) {
   c.w = ctf->amp_contrast;
   c.bfactor = ctf->bfactor;
   return c;
+}
+
+bool has_grads(const cs_grads &g) { return g.means || g.log_scales || g.quats || g.amps; }
+
+// ---------------------------------------------------------------------------
+// Enqueue helpers
+// ---------------------------------------------------------------------------
+int launch_binning(cs_ctx *ctx, const Plan &P, hipStream_t st) {
+  const Geom &G = P.G;
+  const Layout &L = P.L;
+  char *ws = P.ws;
+  float4 *gc = (float4 *)(ws + L.gc);
+  int *count = (int *)(ws + L.count);
+  const size_t BK = (size_t)G.B * G.K;
+  const size_t nb = std::max<size_t>((size_t)G.N, BK);
+  TLAUNCH(k_build, dim3(cdiv(nb, kBlock)), dim3(kBlock), 0, st, P.g.means, P.g.log_scales,
+          P.g.quats, P.g.amps, G, gc, count, (int)BK);
+  const dim3 bgrid(cdiv(G.N, kBlock), cdiv(G.B, kImgPerBinBlock));
+  const size_t hist_bytes = (size_t)kImgPerBinBlock * G.K * 4;
+  TLAUNCH(k_bin_count, bgrid, dim3(kBlock), hist_bytes, st, gc, P.v.rot, P.v.shift, G,
+          (int *)(ws + L.key), (int *)(ws + L.blk), L.nbx);
+  TLAUNCH(k_bin_blockscan, dim3((unsigned)BK), dim3(kBlock), 0, st, (int *)(ws + L.blk), L.nbx,
+          count);
+  TLAUNCH(k_scan, dim3(1), dim3(1024), 0, st, count, G, (int *)(ws + L.off),
+          (int4 *)(ws + L.items), (int *)(ws + L.item_off), (int *)(ws + L.n_items),
+          (int *)(ws + L.queues));
+  TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), (size_t)(kBlock / 64) * G.K * 4, st, gc, P.v.rot,
+          P.v.shift, G, (const int *)(ws + L.key), (const int *)(ws + L.off),
+          (const int *)(ws + L.blk), L.nbx, (float4 *)(ws + L.list));
+  return CS_OK;
+}
+
+int persistent_grid(cs_ctx *ctx, const void *kernel, size_t lds, int *grid) {
+  int nb = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, lds));
+  if (nb < 1) nb = 1;
+  *grid = nb * ctx->n_cu;
+  return CS_OK;
+}
+
+ProbDev prob_dev(const Plan &P) {
+  ProbDev d;
+  d.G = P.G;
+  d.list = (const float4 *)(P.ws + P.L.list);
+  d.items = (const int4 *)(P.ws + P.L.items);
+  d.n_items = (const int *)(P.ws + P.L.n_items);
+  d.queue = (int *)(P.ws + P.L.queues);
+  d.partials = (float *)(P.ws + P.L.partials);
+  d.GQ = P.GQ();
+  d.mom = (float *)(P.ws + P.L.mom);
+  return d;
+}
+
+// One persistent launch of the forward or adjoint splat over the given
+// problems (chunks of kMaxProblems per launch).
+int launch_persistent(cs_ctx *ctx, bool forward, const std::vector<const Plan *> &ps,
+                      hipStream_t st) {
+  for (size_t c0 = 0; c0 < ps.size(); c0 += kMaxProblems) {
+    MultiProb MP{};
+    size_t lds = 0;
+    MP.count = (int)std::min<size_t>(kMaxProblems, ps.size() - c0);
+    for (int i = 0; i < MP.count; ++i) {
+      MP.p[i] = prob_dev(*ps[c0 + i]);
+      lds = std::max(lds, (size_t)MP.p[i].G.C * MP.p[i].G.S * 4);
+    }
+    int grid = 0;
+    int rc = persistent_grid(ctx, forward ? (const void *)k_splat_fwd : (const void *)k_splat_bwd,
+                             lds, &grid);
+    if (rc) return rc;
+    if (forward) {
+      TLAUNCH(k_splat_fwd, dim3(grid), dim3(kBlock), lds, st, MP);
+    } else {
+      TLAUNCH(k_splat_bwd, dim3(grid), dim3(kBlock), lds, st, MP);
+    }
+  }
+  return CS_OK;
+}
+
+// After the forward splat: Q of one problem (reduce + wide Gaussians).
+int launch_forward_finish(cs_ctx *ctx, const Plan &P, float *Q, hipStream_t st) {
+  const Geom &G = P.G;
+  char *ws = P.ws;
+  TLAUNCH(k_canvas_reduce, dim3(G.ntiles, G.B), dim3(kBlock), 0, st,
+          (const float *)(ws + P.L.partials), (const int *)(ws + P.L.item_off),
+          (const int4 *)(ws + P.L.items), G, Q);
+  TLAUNCH(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
+          (const int *)(ws + P.L.off), (const int *)(ws + P.L.count),
+          (const int *)(ws + P.L.n_items) + 1, G, Q);
+  return CS_OK;
+}
+
+int launch_backward_finish(cs_ctx *ctx, const Plan &P, hipStream_t st) {
+  const Geom &G = P.G;
+  char *ws = P.ws;
+  float *mom = (float *)(ws + P.L.mom);
+  TLAUNCH(k_big_bwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
+          (const int *)(ws + P.L.off), (const int *)(ws + P.L.count),
+          (const int *)(ws + P.L.n_items) + 1, G, P.GQ(), mom);
+  TLAUNCH(k_chain, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.gc),
+          P.g.log_scales, P.g.quats, P.g.amps, P.v.rot, P.v.shift, G, (const int *)(ws + P.L.key),
+          mom, P.grads.means, P.grads.log_scales, P.grads.quats, P.grads.amps);
+  return CS_OK;
 }
 
 // Launch shapes of the FFT kernels for one image side.
@@ -349,52 +417,279 @@ int fft_setup(cs_ctx *ctx, const Geom &G, FftLaunch &F) {
   return CS_OK;
 }
 
-int launch_ctf_table(cs_ctx *ctx, const Geom &G, const cs_ctf *ctf, float *table, hipStream_t st) {
+int launch_ctf_table(cs_ctx *ctx, const Plan &P, hipStream_t st) {
+  const Geom &G = P.G;
   const size_t n = (size_t)G.B * G.D * (G.D / 2 + 1);
-  TLAUNCH(k_ctf_table, dim3(cdiv(n, 256)), dim3(256), 0, st, G.D, G.pixel, make_ctf(ctf), G.B, table);
+  TLAUNCH(k_ctf_table, dim3(cdiv(n, 256)), dim3(256), 0, st, G.D, G.pixel, make_ctf(P.ctf), G.B,
+          (float *)(P.ws + P.L.ctf));
   return CS_OK;
 }
 
-// src (real [B][D][D]) -> spec -> H^ -> dst (real), i.e. dst = F^-1(H^ F src).
-int launch_ctf_roundtrip(cs_ctx *ctx, const Geom &G, const cs_ctf *ctf, const float *src,
-                         float2 *spec, float *table, float *dst, hipStream_t st) {
+// dst = F^-1(H^ F src) for one problem (CTF table already built).
+int launch_ctf_roundtrip(cs_ctx *ctx, const Plan &P, const float *src, float *dst, hipStream_t st) {
+  const Geom &G = P.G;
   FftLaunch F;
   int rc = fft_setup(ctx, G, F);
   if (rc) return rc;
-  rc = launch_ctf_table(ctx, G, ctf, table, st);
-  if (rc) return rc;
+  float2 *spec = (float2 *)(P.ws + P.L.spec);
   TLAUNCH(k_fft_rows_fwd, F.rgrid, dim3(256), F.rlds, st, src, F.P, F.tw, G.B, spec);
   TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw,
-          (const float *)table);
+          (const float *)(P.ws + P.L.ctf));
   TLAUNCH(k_fft_rows_inv, F.rgrid, dim3(256), F.rlds, st, (const float2 *)spec, F.P, F.tw, G.B, dst);
   return CS_OK;
 }
 
-}  // namespace
-
-// No-CTF residual: loss partials per row, optional X output, G_Q in place.
-namespace cs {
-__global__ void __launch_bounds__(256)
-k_residual(float *Q, const float *obs, float *images_out, int B, int D, float grad_scale,
-           float *loss_part) {
-  const int row = blockIdx.x, b = blockIdx.y;
-  const size_t o = ((size_t)b * D + row) * D;
-  float acc = 0.f;
-  for (int j = threadIdx.x; j < D; j += 256) {
-    const float x = Q[o + j];
-    if (images_out) images_out[o + j] = x;
-    const float r = x - obs[o + j];
-    acc += r * r;
-    Q[o + j] = grad_scale * r;
+// Loss of one problem from Q; leaves G_Q in Q when the adjoint follows.
+int launch_loss(cs_ctx *ctx, const Plan &P, hipStream_t st) {
+  const Geom &G = P.G;
+  float *Q = P.Q();
+  float *loss_part = (float *)(P.ws + P.L.loss_part);
+  const double scale = P.reduction == CS_MEAN ? 1.0 / ((double)G.B * G.D * G.D) : 1.0;
+  const float gscale = (float)(2.0 * scale);
+  int parts;
+  if (P.ctf) {
+    FftLaunch F;
+    int rc = fft_setup(ctx, G, F);
+    if (rc) return rc;
+    float2 *spec = (float2 *)(P.ws + P.L.spec);
+    const float *table = (const float *)(P.ws + P.L.ctf);
+    TLAUNCH(k_fft_rows_fwd, F.rgrid, dim3(256), F.rlds, st, Q, F.P, F.tw, G.B, spec);
+    TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw, table);
+    TLAUNCH(k_fft_rows_inv_loss, F.rgrid, dim3(256), F.rlds, st, spec, F.P, F.tw, G.B, P.observed,
+            P.images_out, gscale, loss_part);
+    parts = G.D / 2;
+    if (P.bwd) {
+      TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw, table);
+      TLAUNCH(k_fft_rows_inv, F.rgrid, dim3(256), F.rlds, st, (const float2 *)spec, F.P, F.tw, G.B, Q);
+    }
+  } else {
+    TLAUNCH(k_residual, dim3(G.D, G.B), dim3(256), 0, st, Q, P.observed, P.images_out, G.B, G.D,
+            gscale, loss_part);
+    parts = G.D;
   }
-  __shared__ float red[4];
-#pragma unroll
-  for (int s = 32; s > 0; s >>= 1) acc += __shfl_xor(acc, s, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) loss_part[(size_t)b * D + row] = red[0] + red[1] + red[2] + red[3];
+  TLAUNCH(k_loss_reduce, dim3(G.B), dim3(256), 0, st, (const float *)loss_part, G.B, parts,
+          (float)scale, P.loss);
+  TLAUNCH(k_loss_total, dim3(1), dim3(256), 0, st, P.loss, G.B);
+  return CS_OK;
 }
-}  // namespace cs
+
+int fill(cs_ctx *ctx, float *p, size_t n, hipStream_t st) {
+  if (!p || n == 0) return CS_OK;
+  TLAUNCH(k_fill, dim3(cdiv(n, kBlock)), dim3(kBlock), 0, st, p, (int64_t)n, 0.f);
+  return CS_OK;
+}
+
+// The whole launch sequence of a set of plans, in stage order.
+int enqueue(cs_ctx *ctx, std::vector<Plan> &plans, hipStream_t st) {
+  int rc;
+  for (auto &P : plans) {
+    if (P.ctf) {
+      rc = launch_ctf_table(ctx, P, st);
+      if (rc) return rc;
+    }
+    if (P.mode == BACKWARD && P.ctf) {
+      rc = launch_ctf_roundtrip(ctx, P, P.d_images, P.Q(), st);
+      if (rc) return rc;
+    }
+    if (P.fwd || P.bwd) {
+      rc = launch_binning(ctx, P, st);
+      if (rc) return rc;
+    }
+  }
+  std::vector<const Plan *> fw, bw;
+  for (auto &P : plans)
+    if (P.fwd) fw.push_back(&P);
+  if (!fw.empty()) {
+    rc = launch_persistent(ctx, true, fw, st);
+    if (rc) return rc;
+  }
+  for (auto &P : plans) {
+    if (P.mode == BACKWARD) continue;
+    // pre-CTF image: the caller's buffer for a CTF-free render, else workspace
+    float *Q = (P.mode == RENDER && !P.ctf) ? P.images : P.Q();
+    if (P.fwd) {
+      rc = launch_forward_finish(ctx, P, Q, st);
+    } else {
+      rc = fill(ctx, Q, (size_t)P.G.B * P.G.D * P.G.D, st);
+    }
+    if (rc) return rc;
+    if (P.mode == RENDER) {
+      if (P.ctf) rc = launch_ctf_roundtrip(ctx, P, Q, P.images, st);
+    } else {
+      rc = launch_loss(ctx, P, st);
+    }
+    if (rc) return rc;
+  }
+  for (auto &P : plans)
+    if (P.bwd) bw.push_back(&P);
+  if (!bw.empty()) {
+    rc = launch_persistent(ctx, false, bw, st);
+    if (rc) return rc;
+    for (const Plan *P : bw) {
+      rc = launch_backward_finish(ctx, *P, st);
+      if (rc) return rc;
+    }
+  }
+  return CS_OK;
+}
+
+// Workspace for all plans; assigns every plan its region and creates the
+// host-side resources the launches need (before any capture).
+int place(cs_ctx *ctx, std::vector<Plan> &plans, hipStream_t st) {
+  size_t total = 0;
+  std::vector<size_t> offs;
+  for (auto &P : plans) {
+    offs.push_back(total);
+    total += align_up(P.L.total);
+  }
+  int rc = ensure_ws(ctx, total, st);
+  if (rc) return rc;
+  for (size_t i = 0; i < plans.size(); ++i) plans[i].ws = (char *)ctx->ws + offs[i];
+  for (auto &P : plans) {
+    if (P.ctf) {
+      const float2 *tw;
+      rc = get_twiddles(ctx, P.G.D, &tw);
+      if (rc) return rc;
+    }
+  }
+  return CS_OK;
+}
+
+int make_loss_plan(cs_ctx *ctx, const cs_problem &pr, Plan &P) {
+  int rc = validate(ctx, &pr.g, &pr.v, pr.ctf, &pr.opt);
+  if (rc) return rc;
+  if (!pr.observed || !pr.loss) return fail(ctx, CS_ERR_INVALID_ARG, "null observed or loss");
+  if (pr.reduction != CS_SUM && pr.reduction != CS_MEAN) return fail(ctx, CS_ERR_INVALID_ARG, "bad reduction");
+  P.mode = LOSS;
+  P.g = pr.g;
+  P.v = pr.v;
+  P.ctf = pr.ctf;
+  P.G = make_geom(&pr.g, &pr.v, &pr.opt);
+  P.observed = pr.observed;
+  P.reduction = pr.reduction;
+  P.loss = pr.loss;
+  P.images_out = pr.images_out;
+  P.grads = pr.grads;
+  P.fwd = P.G.N > 0;
+  P.bwd = P.G.N > 0 && has_grads(pr.grads);
+  P.L = make_layout(P.G, P.fwd, P.bwd, P.ctf != nullptr);
+  return CS_OK;
+}
+
+// Signature of a batched call for the graph cache: every byte the captured
+// launches depend on (shapes, pointers, scalars, options, workspace).
+std::string signature(cs_ctx *ctx, const cs_problem *problems, int count) {
+  std::string s;
+  auto add = [&](const void *p, size_t n) { s.append((const char *)p, n); };
+  add(&ctx->ws, sizeof(void *));
+  add(&ctx->ws_bytes, sizeof(size_t));
+  for (int i = 0; i < count; ++i) {
+    const cs_problem &p = problems[i];
+    add(&p.g, sizeof(p.g));
+    add(&p.v, sizeof(p.v));
+    const int has_ctf = p.ctf != nullptr;
+    add(&has_ctf, sizeof(int));
+    if (p.ctf) add(p.ctf, sizeof(cs_ctf));
+    add(&p.opt, sizeof(p.opt));
+    add(&p.observed, sizeof(void *));
+    add(&p.reduction, sizeof(int32_t));
+    add(&p.loss, sizeof(void *));
+    add(&p.grads, sizeof(p.grads));
+    add(&p.images_out, sizeof(void *));
+  }
+  return s;
+}
+
+int run_loss_problems(cs_ctx *ctx, const cs_problem *problems, int count, bool use_graph,
+                      hipStream_t st) {
+  std::vector<Plan> plans(count);
+  for (int i = 0; i < count; ++i) {
+    int rc = make_loss_plan(ctx, problems[i], plans[i]);
+    if (rc) return rc;
+  }
+  int rc = place(ctx, plans, st);
+  if (rc) return rc;
+  if (!use_graph) return enqueue(ctx, plans, st);
+  const std::string key = signature(ctx, problems, count);
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    ctx->capturing = true;
+    rc = enqueue(ctx, plans, ctx->cap_stream);
+    ctx->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(ctx, CS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(ctx, CS_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    it = ctx->graphs.emplace(key, exec).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, st));
+  return CS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+std::string tune_key(const cs_problem &p) {
+  char buf[256];
+  const float qc = p.opt.q_cut > 0.f ? p.opt.q_cut : kDefaultQCut;
+  snprintf(buf, sizeof(buf), "D%d_N%lld_B%lld_p%.4f_ctf%d_q%.4f_act%d%d", p.v.d, (long long)p.g.n,
+           (long long)p.v.b, p.v.pixel, p.ctf ? 1 : 0, qc, p.g.scale_act, p.g.amp_act);
+  return buf;
+}
+
+void load_tune_file(cs_ctx *ctx) {
+  if (ctx->tune_file.empty()) return;
+  std::ifstream f(ctx->tune_file);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string key;
+    int t, h, b;
+    if (is >> key >> t >> h >> b && t >= 16 && t <= 128 && h >= 0 && h <= t && b >= 64)
+      ctx->tuned[key] = {t, h, b};
+  }
+}
+
+void save_tune_file(cs_ctx *ctx) {
+  if (ctx->tune_file.empty()) return;
+  std::ofstream f(ctx->tune_file, std::ios::trunc);
+  for (auto &kv : ctx->tuned)
+    f << kv.first << " " << kv.second[0] << " " << kv.second[1] << " " << kv.second[2] << "\n";
+}
+
+int time_problem(cs_ctx *ctx, const cs_problem &pr, int reps, hipStream_t st, double *ms_out) {
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  std::vector<double> ts;
+  int rc = run_loss_problems(ctx, &pr, 1, false, st);  // warm-up (also sizes the workspace)
+  for (int r = 0; r < reps && rc == CS_OK; ++r) {
+    (void)hipEventRecord(a, st);
+    rc = run_loss_problems(ctx, &pr, 1, false, st);
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    ts.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  std::sort(ts.begin(), ts.end());
+  *ms_out = ts.empty() ? 0.0 : ts[ts.size() / 2];
+  return CS_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -414,6 +709,9 @@ int cs_create(int device, cs_ctx **out) {
     c->n_cu = prop.multiProcessorCount;
   const char *cap = std::getenv("CS_WORKSPACE_MAX");
   if (cap) c->ws_max = (size_t)std::strtoull(cap, nullptr, 10);
+  const char *tf = std::getenv("CS_AUTOTUNE_CACHE");
+  if (tf) c->tune_file = tf;
+  load_tune_file(c);
   // allow canvases above 64 KiB of LDS
   (void)hipFuncSetAttribute((const void *)k_splat_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void *)k_splat_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -426,6 +724,12 @@ void cs_destroy(cs_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (auto &p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
   if (ctx->ws) (void)hipFree(ctx->ws);
   for (auto &kv : ctx->twiddles) (void)hipFree(kv.second);
   delete ctx;
@@ -440,25 +744,19 @@ int cs_render(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ct
   if (!images) return fail(ctx, CS_ERR_INVALID_ARG, "null images");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  const Geom G = make_geom(g, v, opt);
-  const Layout L = make_layout(G, true, false, ctf != nullptr);
-  rc = ensure_ws(ctx, L.total, st);
+  std::vector<Plan> plans(1);
+  Plan &P = plans[0];
+  P.mode = RENDER;
+  P.g = *g;
+  P.v = *v;
+  P.ctf = ctf;
+  P.G = make_geom(g, v, opt);
+  P.images = images;
+  P.fwd = P.G.N > 0;
+  P.L = make_layout(P.G, P.fwd, false, ctf != nullptr);
+  rc = place(ctx, plans, st);
   if (rc) return rc;
-  char *ws = (char *)ctx->ws;
-  float *Q = ctf ? (float *)(ws + L.Q) : images;
-  const size_t npx = (size_t)G.B * G.D * G.D;
-  if (G.N == 0) {
-    TLAUNCH(k_fill, dim3(cdiv(npx, kBlock)), dim3(kBlock), 0, st, images, (int64_t)npx, 0.f);
-    return CS_OK;
-  }
-  rc = launch_binning(ctx, g, v, G, L, ws, st);
-  if (rc) return rc;
-  rc = launch_forward(ctx, G, L, ws, Q, st);
-  if (rc) return rc;
-  if (ctf)
-    return launch_ctf_roundtrip(ctx, G, ctf, Q, (float2 *)(ws + L.spec), (float *)(ws + L.ctf),
-                                images, st);
-  return CS_OK;
+  return enqueue(ctx, plans, st);
 }
 
 int cs_render_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf *ctf,
@@ -469,84 +767,105 @@ int cs_render_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, co
   if (!d_images || !grads) return fail(ctx, CS_ERR_INVALID_ARG, "null d_images or grads");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  if (g->n == 0) return CS_OK;
-  const Geom G = make_geom(g, v, opt);
-  const Layout L = make_layout(G, false, true, ctf != nullptr);
-  rc = ensure_ws(ctx, L.total, st);
+  if (g->n == 0 || !has_grads(*grads)) return CS_OK;
+  std::vector<Plan> plans(1);
+  Plan &P = plans[0];
+  P.mode = BACKWARD;
+  P.g = *g;
+  P.v = *v;
+  P.ctf = ctf;
+  P.G = make_geom(g, v, opt);
+  P.d_images = d_images;
+  P.grads = *grads;
+  P.bwd = true;
+  P.L = make_layout(P.G, false, true, ctf != nullptr);
+  rc = place(ctx, plans, st);
   if (rc) return rc;
-  char *ws = (char *)ctx->ws;
-  const float *GQ = d_images;
-  if (ctf) {
-    rc = launch_ctf_roundtrip(ctx, G, ctf, d_images, (float2 *)(ws + L.spec), (float *)(ws + L.ctf),
-                              (float *)(ws + L.Q), st);
-    if (rc) return rc;
-    GQ = (const float *)(ws + L.Q);
-  }
-  rc = launch_binning(ctx, g, v, G, L, ws, st);
-  if (rc) return rc;
-  return launch_backward(ctx, g, v, G, L, ws, GQ, grads, st);
+  return enqueue(ctx, plans, st);
 }
 
 int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf *ctf,
                      const cs_options *opt, const float *observed, int32_t reduction,
                      float *loss, cs_grads *grads, float *images_out, void *stream) {
-  int rc = validate(ctx, g, v, ctf, opt);
-  if (rc) return rc;
-  if (!observed || !loss) return fail(ctx, CS_ERR_INVALID_ARG, "null observed or loss");
-  if (reduction != CS_SUM && reduction != CS_MEAN) return fail(ctx, CS_ERR_INVALID_ARG, "bad reduction");
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  if (!g || !v) return fail(ctx, CS_ERR_INVALID_ARG, "null gaussians or views");
+  HIPCHK(hipSetDevice(ctx->device));
+  cs_problem pr{};
+  pr.g = *g;
+  pr.v = *v;
+  pr.ctf = ctf;
+  if (opt) pr.opt = *opt;
+  pr.observed = observed;
+  pr.reduction = reduction;
+  pr.loss = loss;
+  if (grads) pr.grads = *grads;
+  pr.images_out = images_out;
+  return run_loss_problems(ctx, &pr, 1, opt && opt->graph, (hipStream_t)stream);
+}
+
+int cs_loss_and_grad_multi(cs_ctx *ctx, const cs_problem *problems, int32_t count,
+                           int32_t use_graph, void *stream) {
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  if (!problems || count < 1) return fail(ctx, CS_ERR_INVALID_ARG, "need at least one problem");
+  HIPCHK(hipSetDevice(ctx->device));
+  return run_loss_problems(ctx, problems, count, use_graph != 0, (hipStream_t)stream);
+}
+
+int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, void *stream) {
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  if (!problems || count < 1 || reps < 1) return fail(ctx, CS_ERR_INVALID_ARG, "bad autotune arguments");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  const Geom G = make_geom(g, v, opt);
-  const bool want_grads = grads && G.N > 0;
-  const Layout L = make_layout(G, true, want_grads, ctf != nullptr);
-  rc = ensure_ws(ctx, L.total, st);
-  if (rc) return rc;
-  char *ws = (char *)ctx->ws;
-  float *Q = (float *)(ws + L.Q);
-  const size_t npx = (size_t)G.B * G.D * G.D;
-  if (G.N == 0) {
-    TLAUNCH(k_fill, dim3(cdiv(npx, kBlock)), dim3(kBlock), 0, st, Q, (int64_t)npx, 0.f);
-  } else {
-    rc = launch_binning(ctx, g, v, G, L, ws, st);
-    if (rc) return rc;
-    rc = launch_forward(ctx, G, L, ws, Q, st);
-    if (rc) return rc;
-  }
-  const double scale = reduction == CS_MEAN ? 1.0 / ((double)G.B * G.D * G.D) : 1.0;
-  const float gscale = (float)(2.0 * scale);
-  float *loss_part = (float *)(ws + L.loss_part);
-  int parts;
-  if (ctf) {
-    FftLaunch F;
-    rc = fft_setup(ctx, G, F);
-    if (rc) return rc;
-    float2 *spec = (float2 *)(ws + L.spec);
-    float *table = (float *)(ws + L.ctf);
-    rc = launch_ctf_table(ctx, G, ctf, table, st);
-    if (rc) return rc;
-    TLAUNCH(k_fft_rows_fwd, F.rgrid, dim3(256), F.rlds, st, Q, F.P, F.tw, G.B, spec);
-    TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw,
-            (const float *)table);
-    TLAUNCH(k_fft_rows_inv_loss, F.rgrid, dim3(256), F.rlds, st, spec, F.P, F.tw, G.B, observed,
-            images_out, gscale, loss_part);
-    parts = G.D / 2;
-    if (want_grads) {
-      TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw,
-              (const float *)table);
-      TLAUNCH(k_fft_rows_inv, F.rgrid, dim3(256), F.rlds, st, (const float2 *)spec, F.P, F.tw,
-              G.B, Q);
+  const bool was_timing = ctx->timing;
+  ctx->timing = false;
+  int rc = CS_OK;
+  for (int i = 0; i < count && rc == CS_OK; ++i) {
+    cs_problem pr = problems[i];
+    pr.opt.graph = 0;
+    const std::string key = tune_key(pr);
+    auto hit = ctx->tuned.find(key);
+    if (hit == ctx->tuned.end()) {
+      // stage 1: tile x halo at the default budget; stage 2: budget
+      std::vector<int> best = {kDefaultTile, kDefaultHalo, kDefaultBudget};
+      double best_ms = 1e30;
+      const int tiles[] = {32, 48, 64, 96, 128};
+      const int halos[] = {8, 12, 16, 24};
+      for (int T : tiles) {
+        if (T > std::max(32, pr.v.d)) continue;
+        for (int h : halos) {
+          if (h > T) continue;
+          pr.opt.tile = T;
+          pr.opt.halo = h;
+          pr.opt.budget = kDefaultBudget;
+          double ms = 0;
+          rc = time_problem(ctx, pr, reps, st, &ms);
+          if (rc) break;
+          if (ms < best_ms) { best_ms = ms; best = {T, h, kDefaultBudget}; }
+        }
+        if (rc) break;
+      }
+      const int budgets[] = {1024, 4096, 8192};
+      for (int bgt : budgets) {
+        if (rc) break;
+        pr.opt.tile = best[0];
+        pr.opt.halo = best[1];
+        pr.opt.budget = bgt;
+        double ms = 0;
+        rc = time_problem(ctx, pr, reps, st, &ms);
+        if (rc) break;
+        if (ms < best_ms) { best_ms = ms; best[2] = bgt; }
+      }
+      if (rc) break;
+      hit = ctx->tuned.emplace(key, best).first;
+      save_tune_file(ctx);
     }
-  } else {
-    TLAUNCH(k_residual, dim3(G.D, G.B), dim3(256), 0, st, Q, observed, images_out, G.B,
-                       G.D, gscale, loss_part);
-    parts = G.D;
+    problems[i].opt.tile = hit->second[0];
+    problems[i].opt.halo = hit->second[1];
+    problems[i].opt.budget = hit->second[2];
   }
-  TLAUNCH(k_loss_reduce, dim3(G.B), dim3(256), 0, st, (const float *)loss_part, G.B, parts,
-          (float)scale, loss);
-  TLAUNCH(k_loss_total, dim3(1), dim3(256), 0, st, loss, G.B);
-  if (!grads) return CS_OK;
-  if (G.N == 0) return zero_grads(ctx, g, grads, st);
-  return launch_backward(ctx, g, v, G, L, ws, Q, grads, st);
+  ctx->timing = was_timing;
+  if (rc == CS_OK) HIPCHK(hipStreamSynchronize(st));
+  return rc;
 }
 
 int cs_adam_step(cs_ctx *ctx, float *params, const float *grads, float *m, float *v, int64_t count,
@@ -560,8 +879,9 @@ int cs_adam_step(cs_ctx *ctx, float *params, const float *grads, float *m, float
   HIPCHK(hipSetDevice(ctx->device));
   const float bc1 = (float)(1.0 - std::pow((double)b1, (double)step));
   const float bc2 = (float)(1.0 - std::pow((double)b2, (double)step));
-  TLAUNCH(k_adam, dim3(cdiv(count, kBlock)), dim3(kBlock), 0, (hipStream_t)stream, params,
-                     grads, m, v, count, lr, b1, b2, eps, bc1, bc2);
+  hipStream_t st = (hipStream_t)stream;
+  TLAUNCH(k_adam, dim3(cdiv(count, kBlock)), dim3(kBlock), 0, st, params, grads, m, v, count, lr,
+          b1, b2, eps, bc1, bc2);
   return CS_OK;
 }
 
@@ -573,8 +893,8 @@ int cs_pair_count(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const c
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const Geom G = make_geom(g, v, opt);
-  TLAUNCH(k_fill, dim3(cdiv(2 * (size_t)G.B, kBlock)), dim3(kBlock), 0, st, (float *)counts,
-                     (int64_t)(2 * G.B), 0.f);  // all-zero bits
+  rc = fill(ctx, (float *)counts, 2 * (size_t)G.B, st);  // all-zero bits
+  if (rc) return rc;
   if (G.N == 0) return CS_OK;
   const Layout L = make_layout(G, false, false, false);
   rc = ensure_ws(ctx, L.total, st);
@@ -583,8 +903,8 @@ int cs_pair_count(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const c
   float4 *gc = (float4 *)(ws + L.gc);
   TLAUNCH(k_build, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
           g->quats, g->amps, G, gc, (int *)nullptr, 0);
-  TLAUNCH(k_pair_count, dim3(cdiv(G.N, kBlock), G.B), dim3(kBlock), 0, st, gc, v->rot,
-                     v->shift, G, (unsigned long long *)counts);
+  TLAUNCH(k_pair_count, dim3(cdiv(G.N, kBlock), G.B), dim3(kBlock), 0, st, gc, v->rot, v->shift,
+          G, (unsigned long long *)counts);
   return CS_OK;
 }
 

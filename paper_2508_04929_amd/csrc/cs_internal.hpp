@@ -50,6 +50,26 @@ struct Geom {
   int amp_act;    // 0 identity, 1 softplus
 };
 
+// One problem (mixture + its images) as seen by the persistent splat
+// kernels, which drain the work queues of several problems in one launch.
+struct ProbDev {
+  Geom G;
+  const float4 *list;   // splat records
+  const int4 *items;    // work items
+  const int *n_items;   // [0] item count, [1] wide-record count
+  int *queue;           // [0] forward, [1] backward work-queue counter
+  float *partials;      // forward partial canvases
+  const float *GQ;      // dL/dQ (backward)
+  float *mom;           // pixel moments (backward)
+};
+
+constexpr int kMaxProblems = 16;
+
+struct MultiProb {
+  int count;
+  ProbDev p[kMaxProblems];
+};
+
 // Per-image CTF description for the Fourier-space kernels.
 struct CtfDev {
   const float *defocus_u, *defocus_v, *astig, *phase;  // [B] (astig/phase may be null)
@@ -144,8 +164,7 @@ __global__ void k_bin_scatter(const float4 *gc, const float *rot, const float *s
                               const int *key, const int *off, const int *blk, int nbx,
                               float4 *list);
 
-__global__ void k_splat_fwd(const float4 *list, const int4 *items, const int *n_items,
-                            int *queue, Geom G, float *partials);
+__global__ void k_splat_fwd(MultiProb MP);
 
 __global__ void k_canvas_reduce(const float *partials, const int *item_off, const int4 *items,
                                 Geom G, float *Q);
@@ -153,8 +172,7 @@ __global__ void k_canvas_reduce(const float *partials, const int *item_off, cons
 __global__ void k_big_fwd(const float4 *list, const int *off, const int *count,
                           const int *n_wide, Geom G, float *Q);
 
-__global__ void k_splat_bwd(const float4 *list, const int4 *items, const int *n_items,
-                            int *queue, Geom G, const float *GQ, float *mom);
+__global__ void k_splat_bwd(MultiProb MP);
 
 __global__ void k_big_bwd(const float4 *list, const int *off, const int *count,
                           const int *n_wide, Geom G, const float *GQ, float *mom);
@@ -189,5 +207,8 @@ __global__ void k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, i
 __global__ void k_loss_reduce(const float *loss_part, int B, int parts, float scale, float *loss);
 
 __global__ void k_loss_total(float *loss, int B);
+
+__global__ void k_residual(float *Q, const float *obs, float *images_out, int B, int D,
+                           float grad_scale, float *loss_part);
 
 }  // namespace cs

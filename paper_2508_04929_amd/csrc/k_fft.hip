@@ -340,4 +340,27 @@ __global__ void __launch_bounds__(256) k_loss_total(float *loss, int B) {
   if (threadIdx.x == 0) loss[B] = (float)(red[0] + red[1] + red[2] + red[3]);
 }
 
+// No-CTF residual (X = Q): loss partials per row, optional X output and
+// G_Q = grad_scale (X - Y) written in place over Q.
+__global__ void __launch_bounds__(256)
+k_residual(float *Q, const float *obs, float *images_out, int B, int D, float grad_scale,
+           float *loss_part) {
+  const int row = blockIdx.x, b = blockIdx.y;
+  const size_t o = ((size_t)b * D + row) * D;
+  float acc = 0.f;
+  for (int j = threadIdx.x; j < D; j += 256) {
+    const float x = Q[o + j];
+    if (images_out) images_out[o + j] = x;
+    const float r = x - obs[o + j];
+    acc += r * r;
+    Q[o + j] = grad_scale * r;
+  }
+  __shared__ float red[4];
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) acc += __shfl_xor(acc, s, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) loss_part[(size_t)b * D + row] = red[0] + red[1] + red[2] + red[3];
+}
+
 }  // namespace cs

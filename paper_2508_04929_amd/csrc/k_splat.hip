@@ -56,13 +56,18 @@ __device__ __forceinline__ int next_item(int *queue, int *slot) {
 // ---------------------------------------------------------------------------
 // Forward: partial canvas of one work item.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
-k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queue, Geom G,
-            float *partials) {
+__global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
   extern __shared__ int icanvas[];  // C rows of stride S (fixed point)
   __shared__ int slot;
   __shared__ float wsum[kBlock / 64];
-  const int nitems = *n_items;
+  // drain the problems' queues in order: blocks that find one exhausted move on
+  for (int p = 0; p < MP.count; ++p) {
+  const Geom G = MP.p[p].G;
+  const float4 *list = MP.p[p].list;
+  const int4 *items = MP.p[p].items;
+  float *partials = MP.p[p].partials;
+  int *queue = MP.p[p].queue;
+  const int nitems = *MP.p[p].n_items;
   const int CS = G.C * G.S;
   for (;;) {
     const int it = next_item(queue, &slot);
@@ -130,6 +135,7 @@ k_splat_fwd(const float4 *list, const int4 *items, const int *n_items, int *queu
       out[i] = (float)icanvas[r * G.S + c] * inv_scale;
     }
     __syncthreads();
+  }
   }
 }
 
@@ -242,12 +248,17 @@ k_big_fwd(const float4 *list, const int *off, const int *count, const int *n_wid
 //   m = sum G_Q e (1, dj, di, dj^2, dj di, di^2),  e = exp(-q/2),
 // with dj = j - u, di = i - v (pixels).  Written to mom[(b N + n) 6 + k].
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
-k_splat_bwd(const float4 *list, const int4 *items, const int *n_items, int *queue, Geom G,
-            const float *GQ, float *mom) {
+__global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
   extern __shared__ float gq[];  // C rows of stride S
   __shared__ int slot;
-  const int nitems = *n_items;
+  for (int p = 0; p < MP.count; ++p) {
+  const Geom G = MP.p[p].G;
+  const float4 *list = MP.p[p].list;
+  const int4 *items = MP.p[p].items;
+  const float *GQ = MP.p[p].GQ;
+  float *mom = MP.p[p].mom;
+  int *queue = MP.p[p].queue + 1;
+  const int nitems = *MP.p[p].n_items;
   for (;;) {
     const int it = next_item(queue, &slot);
     if (it >= nitems) break;
@@ -320,6 +331,7 @@ k_splat_bwd(const float4 *list, const int4 *items, const int *n_items, int *queu
       o[0] = m0; o[1] = m1; o[2] = m2; o[3] = m3; o[4] = m4; o[5] = m5;
     }
     __syncthreads();
+  }
   }
 }
 
