@@ -35,6 +35,35 @@ FMA_RATE = 256 * 128 * 2.4e9         # FP32 lane-ops per second (packed)
 PAIR_OPS = {"k_splat_fwd": 8, "k_splat_bwd": 20}
 
 
+def _source_digest(kernel: str) -> str:
+    """sha1 of the sources that define the splat kernels (counter validity)."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("k_splat.hip", "cs_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2508_04929_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, launches_per_step: int = 1):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size),
+    or None when the summary is missing or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "splat_hbm_traffic_c4.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-json: "):
+                rec = json.loads(line[len("traffic-json: "):])
+    if not rec or rec.get("source_sha1") != _source_digest(kernel):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
 def pair_peak(kernel: str) -> float:
     """Pairs per second at 100% of the nominal per-pair budget."""
     return 1.0 / (1.0 / EXP_RATE + PAIR_OPS[kernel] / FMA_RATE)
@@ -163,7 +192,7 @@ def run(args):
     achieved = pairs_step / (d["ms_per_launch"] * 1e-3)     # pairs per second
     peak = pair_peak(dom)
     roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
-            "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
+            "unit": "Gpair/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
             "pairs_per_launch": pairs_step,
             "ms_per_launch": d["ms_per_launch"]}
     other = "k_splat_bwd" if dom == "k_splat_fwd" else "k_splat_fwd"
@@ -201,6 +230,12 @@ def main():
                     help="run one device copy of this many MiB before warm-up (counter calibration)")
     ap.add_argument("--cpu-images", type=int, default=16,
                     help="images of the workload timed through the CPU oracle (0 = skip)")
+    ap.add_argument("--pose", action="store_true",
+                    help="also run the learned-pose experiment (training included) and add "
+                         "its results under \"pose\"")
+    ap.add_argument("--pose-train", type=int, default=200000)
+    ap.add_argument("--pose-epochs", type=int, default=4)
+    ap.add_argument("--pose-test", type=int, default=2048)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -213,6 +248,11 @@ def main():
               file=sys.stderr, flush=True)
     res = run(args)
     res["cpu_baseline"] = cpu
+    if args.pose:
+        from paper_2508_04929_amd import binding, pose
+        log = lambda m: print(f"[pose] {m}", file=sys.stderr, flush=True)
+        res["pose"] = pose.run_c5(binding.library(), n_train=args.pose_train,
+                                  epochs=args.pose_epochs, n_test=args.pose_test, log=log)
     print(json.dumps(res))
 
 

@@ -220,6 +220,210 @@ int cs_set_timing(cs_ctx *ctx, int enable);
  * enabled (synchronises the recorded events).  Unknown names give 0. */
 int cs_stage_time(cs_ctx *ctx, const char *name, double *total_ms, int64_t *launches);
 
+
+/* ======================================================================
+ * Learned pose proposal.  The paper assumes known poses and names pose
+ * estimation as future work (Sec. 3.3, Sec. 5); this part proposes a pose
+ * per particle image with a small CNN trained on images this renderer
+ * produces, and scores pose grids with the renderer's own image model.
+ *
+ * Network (cs_cnn): input a D x D image (D a multiple of 64, at most 512),
+ * standardised per image (zero mean, unit variance); six 3x3 stride-2
+ * pad-1 convolutions with 1 -> 32 -> 64 -> 128 -> 256 -> 256 -> 256
+ * channels, each followed by ReLU; flatten (NHWC order) to
+ * (D/64)^2 * 256 features; linear -> 256 + ReLU; linear -> 8 outputs:
+ * a 6-D rotation representation (a1, a2) and a 2-D shift.  The rotation
+ * is the Gram-Schmidt frame R = [b1 b2 b3] (columns), b1 = a1/|a1|,
+ * b2 = normalise(a2 - (b1.a2) b1), b3 = b1 x b2.  Weights and activations
+ * are BF16 (round to nearest even), accumulation is FP32 on MFMA, master
+ * weights and Adam moments are FP32.  Parameters form one flat FP32
+ * vector, per layer weight then bias; conv weights [Cout][3][3][Cin],
+ * linear weights [Out][In].
+ *
+ * Training loss over a batch of B (mean over the batch):
+ *   L = (1/B) sum_b ( ||R_b - R*_b||_F^2 + lambda ||t_b - t*_b||^2 ).
+ * ====================================================================== */
+typedef struct cs_cnn cs_cnn;
+
+/* Allocate a network for D x D inputs and batches up to max_batch;
+ * He-uniform initial weights from a SplitMix64 stream seeded by `seed`,
+ * zero biases.  Synchronous.  Errors: CS_ERR_UNSUPPORTED for D outside
+ * {64, 128, ..., 512}; CS_ERR_OOM. */
+int cs_cnn_create(cs_ctx *ctx, int32_t D, int32_t max_batch, uint64_t seed, cs_cnn **out);
+void cs_cnn_destroy(cs_cnn *net);
+/* Number of FP32 parameters (weights and biases of all layers). */
+int64_t cs_cnn_param_count(const cs_cnn *net);
+/* Copy the FP32 parameters out of / into the network (device buffers of
+ * cs_cnn_param_count floats); setting also refreshes the BF16 weights. */
+int cs_cnn_get_params(cs_cnn *net, float *dst, void *stream);
+int cs_cnn_set_params(cs_cnn *net, const float *src, void *stream);
+
+/* Inference on B <= max_batch images [B][D][D] (FP32): rot [B][3][3]
+ * row-major (the Gram-Schmidt frame), shift [B][2] (may be NULL), raw
+ * [B][8] FP32 network outputs (may be NULL). */
+int cs_cnn_forward(cs_cnn *net, const float *images, int32_t B, float *rot, float *shift,
+                   float *raw, void *stream);
+
+/* One training step: forward, loss (written to loss[0], device), backward
+ * through every layer, then (apply_update != 0) one Adam step with
+ * (beta1, beta2, eps) = (0.9, 0.999, 1e-8) and learning rate lr on all
+ * parameters.  grads_out (device, cs_cnn_param_count floats, may be NULL)
+ * receives the FP32 parameter gradient of this batch. */
+int cs_cnn_train_step(cs_cnn *net, const float *images, const float *rot_target,
+                      const float *shift_target, int32_t B, float lambda, float lr, float *loss,
+                      float *grads_out, int32_t apply_update, void *stream);
+
+/* Copy of a bfloat16 tensor the last forward / training step stored, for
+ * inspection: grad = 0: index 0 = standardised input [B][D][D], index l (1..7)
+ * = output of layer l-1 after ReLU (conv outputs NHWC, then the hidden
+ * vector); grad = 1: the gradient w.r.t. the pre-activation of layer
+ * index-1 (masked by its ReLU), index 8 = dL/d(outputs) [B][8] as stored.
+ * B is that of the last call; capacity in elements. */
+int cs_cnn_tensor(cs_cnn *net, int32_t index, int32_t grad, uint16_t *dst, int64_t capacity,
+                  void *stream);
+
+/* Single layers of the network (BF16 tensors passed as raw uint16 bits).
+ * conv: in NHWC [B][H][W][Cin], out [B][H/2][W/2][Cout], w [Cout][3][3][Cin],
+ * bias [Cout] FP32 (may be NULL), padding 1, stride 2; H, W even; Cout a
+ * multiple of 8; Cin a multiple of 8, or Cin = 1 (H = W) for the first
+ * layer.  out_f32 (may be NULL) receives the FP32 values before rounding.
+ * dgrad: din = conv^T(dout) with wt = w transposed to [Cin][3][3][Cout],
+ * zeroed where act_in <= 0 (act_in may be NULL: no mask); Cin % 8 == 0.
+ * wgrad: dw [Cout][3][3][Cin] FP32 = sum over batch and pixels. */
+int cs_bf16_conv3x3s2_forward(cs_ctx *ctx, const uint16_t *in, const uint16_t *w, const float *bias,
+                              int32_t B, int32_t H, int32_t W, int32_t Cin, int32_t Cout,
+                              int32_t relu, uint16_t *out, float *out_f32, void *stream);
+int cs_bf16_conv3x3s2_dgrad(cs_ctx *ctx, const uint16_t *dout, const uint16_t *wt,
+                            const uint16_t *act_in, int32_t B, int32_t H, int32_t W, int32_t Cin,
+                            int32_t Cout, uint16_t *din, float *din_f32, void *stream);
+int cs_bf16_conv3x3s2_wgrad(cs_ctx *ctx, const uint16_t *dout, const uint16_t *in, int32_t B,
+                            int32_t H, int32_t W, int32_t Cin, int32_t Cout, float *dw,
+                            void *stream);
+/* linear: y [B][Out] = x [B][In] w^T + bias, w [Out][In]; In, Out multiples
+ * of 8.  dgrad: dx [B][In] = dy wt^T with wt = w^T [In][Out], masked by
+ * x_act > 0 (may be NULL).  wgrad: dw [Out][In] FP32 = dy^T x. */
+int cs_bf16_linear_forward(cs_ctx *ctx, const uint16_t *x, const uint16_t *w, const float *bias,
+                           int32_t B, int32_t In, int32_t Out, int32_t relu, uint16_t *y,
+                           float *y_f32, void *stream);
+int cs_bf16_linear_dgrad(cs_ctx *ctx, const uint16_t *dy, const uint16_t *wt, const uint16_t *x_act,
+                         int32_t B, int32_t In, int32_t Out, uint16_t *dx, float *dx_f32,
+                         void *stream);
+int cs_bf16_linear_wgrad(cs_ctx *ctx, const uint16_t *dy, const uint16_t *x, int32_t B, int32_t In,
+                         int32_t Out, float *dw, void *stream);
+/* Pose head on raw outputs [B][8]: rot [B][3][3] and shift [B][2] (rot may
+ * be NULL to skip); with rot_target, shift_target, loss and d_raw all set,
+ * also the batch loss (loss[0]) and d_raw [B][8] = dL/draw (FP32). */
+int cs_pose_head(cs_ctx *ctx, const float *raw, int32_t B, float *rot, float *shift,
+                 const float *rot_target, const float *shift_target, float lambda, float *loss,
+                 float *d_raw, void *stream);
+
+
+/* ----------------------------------------------------------------------
+ * Pose scoring with the renderer's image model (Sec. 3.2, Eq. 1; App. A.2,
+ * Eq. 14; Sec. 3.3.5).  The score of rotation W and in-plane shift t for a
+ * particle image Y with CTF H is the squared error ||H (P_W V + t) - Y||^2
+ * of the splatted projection (Eq. 9, 13) shifted by t.  Shifts are whole
+ * pixels (dx, dy) in [-r, r]^2, t = (dx, dy) * pixel in Angstrom in the
+ * convention of the renderer (projected mean P mu + t), shift index
+ * s = (dy + r)(2r + 1) + (dx + r); a shift moves the projection circularly,
+ * which equals the rendered shift while the mixture stays r pixels away
+ * from the image border.
+ *
+ * A bank holds, per rotation, the projection (no CTF) and its power
+ * spectrum as bfloat16, rendered once by this library; searches score
+ * particles against the bank with FP32 accumulation on MFMA:
+ *   score = ||Y||^2 + ||H Q_W||^2 - 2 < shift_t(Q_W), H Y >.
+ * ---------------------------------------------------------------------- */
+typedef struct cs_pose_bank cs_pose_bank;
+
+/* Rotation grid on the host: HEALPix (ring scheme, Gorski et al. 2005)
+ * viewing directions with nside, times n_psi in-plane angles psi_m =
+ * 2 pi m / n_psi.  Rotation (d, m) has index d * n_psi + m and is
+ * W = Rz(psi_m) Ry(-theta_d) Rz(-phi_d) (row-major, world to view; its third
+ * row is the viewing direction).  *count = 12 nside^2 n_psi; rot (HOST
+ * memory, [count][9]) may be NULL to query the count. */
+int cs_pose_grid(int32_t nside, int32_t n_psi, float *rot, int64_t *count);
+
+/* Render the bank: rot device [K][9] (copied); n_psi > 0 declares that the
+ * rotations form a (direction, psi) grid with psi the fastest index, as
+ * cs_pose_grid builds (needed for proposal-driven refinement), 0 = no
+ * structure.  D a multiple of 16 with prime factors 2 and 3, at most 512.
+ * Memory: K (D^2 + D (D/2 + 1) rounded up to 128) * 2 bytes. */
+int cs_pose_bank_create(cs_ctx *ctx, const cs_gaussians *g, const float *rot, int64_t K,
+                        int32_t n_psi, int32_t D, float pixel, const cs_options *opt,
+                        cs_pose_bank **out, void *stream);
+void cs_pose_bank_destroy(cs_pose_bank *bank);
+int64_t cs_pose_bank_size(const cs_pose_bank *bank);
+/* Copy of the bank's rotations (device [K][9]). */
+int cs_pose_bank_rotations(const cs_pose_bank *bank, float *rot, void *stream);
+
+/* Exhaustive search: for each of P images [P][D][D] (device FP32, CTF
+ * parameters per image as in cs_ctf, or ctf NULL for none) the minimum
+ * score over all bank rotations and all (2r+1)^2 shifts, 0 <= r <= 4.
+ * Outputs (device, [P]): best_rot (bank index), best_shift (shift index,
+ * may be NULL), best_score (may be NULL); scores (may be NULL) receives
+ * every score [P][K][(2r+1)^2].  Ties go to the smaller rot * S + s. */
+int cs_pose_grid_search(cs_pose_bank *bank, const float *images, const cs_ctf *ctf, int32_t P,
+                        int32_t shift_radius, int32_t *best_rot, int32_t *best_shift,
+                        float *best_score, float *scores, void *stream);
+
+/* Local refinement: the same score over L = n_dir * n_psi_c candidate
+ * rotations per particle.  With a proposal (device [P][3][3] world-to-view
+ * rotations) the candidates are the n_dir bank directions nearest the
+ * proposal's viewing direction (largest dot product, ties to the smaller
+ * direction index; n_dir <= 64), and for each the n_psi_c consecutive psi
+ * indices around psi* = atan2(M01 - M10, M00 + M11), M = A_d W^T, which
+ * maximises trace(W^T Rz(psi) A_d) (A_d = the bank rotation of direction d
+ * at psi = 0); they are written to cand [P][L] when cand is not NULL.
+ * Without a proposal, cand [P][L] (L = n_dir * n_psi_c) is the input list
+ * of bank indices; entries outside [0, K) are skipped.  Outputs as for the
+ * grid search (scores [P][L][(2r+1)^2]). */
+int cs_pose_refine(cs_pose_bank *bank, const float *images, const cs_ctf *ctf, int32_t P,
+                   const float *proposal, int32_t n_dir, int32_t n_psi_c, int32_t shift_radius,
+                   int32_t *cand, int32_t *best_rot, int32_t *best_shift, float *best_score,
+                   float *scores, void *stream);
+
+
+/* Particle side of pose scoring, computed once per batch of particles and
+ * shared by every search and refinement stage on any bank of the same D:
+ * Z = H Y (the image filtered by its own CTF, the matched filter of the
+ * image model), the (2r+1)^2 circularly shifted copies of -2 Z (bfloat16),
+ * the energy weights w_f |H^|^2 / D^2 (bfloat16) and ||Y||^2.
+ * create: capacity particles of side D (multiple of 16, prime factors 2
+ * and 3, <= 512), shift radius 0 <= r <= 4; device memory about
+ * capacity * D^2 * (2 (2r+1)^2 + 16) bytes.  load: P <= capacity images
+ * [P][D][D] with per-particle CTF parameters (ctf NULL = no CTF); filtered
+ * (may be NULL) receives Z [P][D][D] FP32.  A batch is reused by later
+ * loads; searches use the last load. */
+typedef struct cs_pose_batch cs_pose_batch;
+int cs_pose_batch_create(cs_ctx *ctx, int32_t D, float pixel, int32_t capacity,
+                         int32_t shift_radius, cs_pose_batch **out);
+void cs_pose_batch_destroy(cs_pose_batch *batch);
+int cs_pose_batch_load(cs_pose_batch *batch, const float *images, const cs_ctf *ctf, int32_t P,
+                       float *filtered, void *stream);
+/* cs_pose_grid_search / cs_pose_refine on a loaded batch (same outputs;
+ * the batch's shift radius applies). */
+int cs_pose_batch_search(cs_pose_bank *bank, cs_pose_batch *batch, int32_t *best_rot,
+                         int32_t *best_shift, float *best_score, float *scores, void *stream);
+int cs_pose_batch_refine(cs_pose_bank *bank, cs_pose_batch *batch, const float *proposal,
+                         int32_t n_dir, int32_t n_psi_c, int32_t *cand, int32_t *best_rot,
+                         int32_t *best_shift, float *best_score, float *scores, void *stream);
+
+/* ApplyCTF of Alg. 1 for arbitrary images (App. A.2, Eq. 14):
+ * out = F^-1(H^ . F images) [B][D][D], per-image CTF (NULL = identity);
+ * D even with prime factors 2 and 3, at most 512; out may alias images. */
+int cs_ctf_filter(cs_ctx *ctx, const float *images, const cs_ctf *ctf, int32_t B, int32_t D,
+                  float pixel, float *out, void *stream);
+
+/* Synthetic data: add white Gaussian noise to B images [B][D][D] in place
+ * at a per-image SNR of snr_db (noise variance = image variance /
+ * 10^(snr_db/10)), the noise model of the paper's synthetic study
+ * (App. D.3).  Normals: Philox4x32-10 (Salmon et al. 2011) with key = seed
+ * and counter (b + offset, pixel / 4), Box-Muller transform; identical
+ * (seed, offset) give identical noise. */
+int cs_add_noise(cs_ctx *ctx, float *images, int32_t B, int32_t D, float snr_db, uint64_t seed,
+                 int64_t offset, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

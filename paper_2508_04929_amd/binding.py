@@ -61,7 +61,15 @@ class CsProblem(ctypes.Structure):
 #: Entry points declared in include/cryosplat.h.
 EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_backward",
            "cs_loss_and_grad", "cs_loss_and_grad_multi", "cs_autotune", "cs_adam_step",
-           "cs_pair_count", "cs_set_timing", "cs_stage_time")
+           "cs_pair_count", "cs_set_timing", "cs_stage_time",
+           "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_param_count", "cs_cnn_get_params",
+           "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_train_step",
+           "cs_bf16_conv3x3s2_forward", "cs_bf16_conv3x3s2_dgrad", "cs_bf16_conv3x3s2_wgrad",
+           "cs_bf16_linear_forward", "cs_bf16_linear_dgrad", "cs_bf16_linear_wgrad",
+           "cs_pose_head", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_destroy",
+           "cs_pose_bank_size", "cs_pose_bank_rotations", "cs_pose_grid_search", "cs_pose_refine", "cs_add_noise", "cs_cnn_tensor",
+           "cs_pose_batch_create", "cs_pose_batch_destroy", "cs_pose_batch_load",
+           "cs_pose_batch_search", "cs_pose_batch_refine", "cs_ctf_filter")
 
 
 class CryoSplatError(RuntimeError):
@@ -103,6 +111,52 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_set_timing.restype = ctypes.c_int
     lib.cs_stage_time.argtypes = [vp, ctypes.c_char_p, P(ctypes.c_double), P(i64)]
     lib.cs_stage_time.restype = ctypes.c_int
+    u64 = ctypes.c_uint64
+    lib.cs_cnn_create.argtypes = [vp, i32, i32, u64, P(vp)]
+    lib.cs_cnn_destroy.argtypes = [vp]
+    lib.cs_cnn_destroy.restype = None
+    lib.cs_cnn_param_count.argtypes = [vp]
+    lib.cs_cnn_param_count.restype = i64
+    lib.cs_cnn_get_params.argtypes = [vp, vp, vp]
+    lib.cs_cnn_set_params.argtypes = [vp, vp, vp]
+    lib.cs_cnn_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.cs_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, f32, f32, vp, vp, i32, vp]
+    lib.cs_bf16_conv3x3s2_forward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp,
+                                              vp]
+    lib.cs_bf16_conv3x3s2_dgrad.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp]
+    lib.cs_bf16_conv3x3s2_wgrad.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]
+    lib.cs_bf16_linear_forward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp]
+    lib.cs_bf16_linear_dgrad.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp, vp, vp]
+    lib.cs_bf16_linear_wgrad.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
+    lib.cs_pose_head.argtypes = [vp, vp, i32, vp, vp, vp, vp, f32, vp, vp, vp]
+    lib.cs_pose_grid.argtypes = [i32, i32, vp, P(i64)]
+    lib.cs_pose_bank_create.argtypes = [vp, P(CsGaussians), vp, i64, i32, i32, f32, P(CsOptions),
+                                        P(vp), vp]
+    lib.cs_pose_bank_destroy.argtypes = [vp]
+    lib.cs_pose_bank_destroy.restype = None
+    lib.cs_pose_bank_size.argtypes = [vp]
+    lib.cs_pose_bank_size.restype = i64
+    lib.cs_pose_bank_rotations.argtypes = [vp, vp, vp]
+    lib.cs_pose_grid_search.argtypes = [vp, vp, P(CsCtf), i32, i32, vp, vp, vp, vp, vp]
+    lib.cs_pose_refine.argtypes = [vp, vp, P(CsCtf), i32, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.cs_add_noise.argtypes = [vp, vp, i32, i32, f32, u64, i64, vp]
+    lib.cs_cnn_tensor.argtypes = [vp, i32, i32, vp, i64, vp]
+    lib.cs_pose_batch_create.argtypes = [vp, i32, f32, i32, i32, P(vp)]
+    lib.cs_pose_batch_destroy.argtypes = [vp]
+    lib.cs_pose_batch_destroy.restype = None
+    lib.cs_pose_batch_load.argtypes = [vp, vp, P(CsCtf), i32, vp, vp]
+    lib.cs_pose_batch_search.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.cs_pose_batch_refine.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
+    for name in ("cs_pose_batch_create", "cs_pose_batch_load", "cs_pose_batch_search",
+                 "cs_pose_batch_refine", "cs_ctf_filter", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
+                 "cs_pose_grid_search", "cs_pose_refine"):
+        getattr(lib, name).restype = ctypes.c_int
+    for name in ("cs_cnn_create", "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward",
+                 "cs_cnn_train_step", "cs_bf16_conv3x3s2_forward", "cs_bf16_conv3x3s2_dgrad",
+                 "cs_bf16_conv3x3s2_wgrad", "cs_bf16_linear_forward", "cs_bf16_linear_dgrad",
+                 "cs_bf16_linear_wgrad", "cs_pose_head"):
+        getattr(lib, name).restype = ctypes.c_int
     return lib
 
 
@@ -155,15 +209,15 @@ class Problem:
     amp_act: str = "identity"
 
 
-def _ptr(t: Optional[torch.Tensor], name: str, device, shape=None):
+def _ptr(t: Optional[torch.Tensor], name: str, device, shape=None, dtype=torch.float32):
     if t is None:
         return None
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
     if t.device != device:
         raise ValueError(f"{name} is on {t.device}, expected {device}")
-    if t.dtype != torch.float32:
-        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -376,6 +430,451 @@ class Library:
         self._check(ctx, self.lib.cs_stage_time(ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n)),
                     "cs_stage_time")
         return ms.value, n.value
+
+    def add_noise(self, images, snr_db, seed, offset=0):
+        """In place: images [B][D][D] += white noise at snr_db per image."""
+        dev = images.device
+        B, D = images.shape[0], images.shape[1]
+        _ptr(images, "images", dev, (B, D, D))
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_add_noise(ctx, images.data_ptr(), B, D, float(snr_db), int(seed),
+                                   int(offset), torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_add_noise")
+        return images
+
+    # -- pose scoring ------------------------------------------------------
+    def pose_grid(self, nside: int, n_psi: int):
+        """HEALPix x psi rotation grid (host float32 [K][3][3])."""
+        import numpy as np
+        n = ctypes.c_int64()
+        rc = self.lib.cs_pose_grid(int(nside), int(n_psi), None, ctypes.byref(n))
+        if rc != 0:
+            raise CryoSplatError(f"cs_pose_grid({nside}, {n_psi}) failed ({rc})")
+        out = np.empty((n.value, 3, 3), dtype=np.float32)
+        rc = self.lib.cs_pose_grid(int(nside), int(n_psi), out.ctypes.data, ctypes.byref(n))
+        if rc != 0:
+            raise CryoSplatError(f"cs_pose_grid failed ({rc})")
+        return out
+
+    def pose_bank(self, means, log_scales, quats, amps, rot, n_psi, D, pixel, options=None,
+                  scale_act="exp", amp_act="identity"):
+        K = rot.shape[0]
+        dev, n, b, g, v, c, o = self._pack(means, log_scales, quats, amps, rot, None, D, pixel,
+                                           None, options, scale_act, amp_act)
+        ctx = self.ctx(dev)
+        h = ctypes.c_void_p()
+        rc = self.lib.cs_pose_bank_create(ctx, ctypes.byref(g), rot.data_ptr(), K, int(n_psi),
+                                          int(D), float(pixel), self._ref(o), ctypes.byref(h),
+                                          torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_pose_bank_create")
+        return PoseBank(self, self._device(dev), h, K, D, pixel, n_psi)
+
+    def pose_batch(self, D: int, pixel: float, capacity: int, shift_radius: int = 2,
+                   device="cuda"):
+        return PoseBatch(self, self._device(device), D, pixel, capacity, shift_radius)
+
+    def ctf_filter(self, images, ctf, pixel, out=None):
+        """out = F^-1(H^ F images) per image (ApplyCTF); out may be images."""
+        dev = images.device
+        B, D = images.shape[0], images.shape[1]
+        _ptr(images, "images", dev, (B, D, D))
+        if out is None:
+            out = torch.empty_like(images)
+        _ptr(out, "out", dev, (B, D, D))
+        c = _ctf_struct(ctf, B, dev)
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_ctf_filter(ctx, images.data_ptr(), None if c is None else ctypes.byref(c),
+                                    B, D, float(pixel), out.data_ptr(),
+                                    torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_ctf_filter")
+        return out
+
+    # -- pose-proposal network -------------------------------------------
+    @staticmethod
+    def _device(device) -> torch.device:
+        d = torch.device(device)
+        return torch.device(d.type, d.index if d.index is not None else torch.cuda.current_device())
+
+    def network(self, D: int, max_batch: int, seed: int = 0, device="cuda"):
+        return Network(self, self._device(device), D, max_batch, seed)
+
+    def _stream(self, dev):
+        return torch.cuda.current_stream(dev).cuda_stream
+
+    def conv_forward(self, x, w, bias, relu=True, want_f32=False):
+        """x [B][H][W][Cin] bf16, w [Cout][3][3][Cin] bf16 -> (y bf16, y_f32 or None)."""
+        dev = x.device
+        B, H, W, Cin = x.shape
+        Cout = w.shape[0]
+        _ptr(x, "x", dev, dtype=torch.bfloat16)
+        _ptr(w, "w", dev, (Cout, 3, 3, Cin), dtype=torch.bfloat16)
+        _ptr(bias, "bias", dev, (Cout,))
+        y = torch.empty(B, H // 2, W // 2, Cout, device=dev, dtype=torch.bfloat16)
+        y32 = torch.empty(y.shape, device=dev) if want_f32 else None
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_bf16_conv3x3s2_forward(ctx, x.data_ptr(), w.data_ptr(),
+                                                 None if bias is None else bias.data_ptr(), B, H, W,
+                                                 Cin, Cout, int(relu), y.data_ptr(),
+                                                 None if y32 is None else y32.data_ptr(),
+                                                 self._stream(dev))
+        self._check(ctx, rc, "cs_bf16_conv3x3s2_forward")
+        return y, y32
+
+    def conv_dgrad(self, dy, wt, act_in, want_f32=False):
+        """dy [B][H/2][W/2][Cout], wt [Cin][3][3][Cout] -> dx [B][H][W][Cin] (bf16)."""
+        dev = dy.device
+        B, Ho, Wo, Cout = dy.shape
+        Cin = wt.shape[0]
+        H, W = 2 * Ho, 2 * Wo
+        _ptr(dy, "dy", dev, dtype=torch.bfloat16)
+        _ptr(wt, "wt", dev, (Cin, 3, 3, Cout), dtype=torch.bfloat16)
+        _ptr(act_in, "act_in", dev, (B, H, W, Cin), dtype=torch.bfloat16)
+        dx = torch.empty(B, H, W, Cin, device=dev, dtype=torch.bfloat16)
+        dx32 = torch.empty(dx.shape, device=dev) if want_f32 else None
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_bf16_conv3x3s2_dgrad(ctx, dy.data_ptr(), wt.data_ptr(),
+                                               None if act_in is None else act_in.data_ptr(), B, H,
+                                               W, Cin, Cout, dx.data_ptr(),
+                                               None if dx32 is None else dx32.data_ptr(),
+                                               self._stream(dev))
+        self._check(ctx, rc, "cs_bf16_conv3x3s2_dgrad")
+        return dx, dx32
+
+    def conv_wgrad(self, dy, x):
+        """dy [B][H/2][W/2][Cout], x [B][H][W][Cin] -> dw [Cout][3][3][Cin] FP32."""
+        dev = dy.device
+        B, H, W, Cin = x.shape
+        Cout = dy.shape[-1]
+        _ptr(dy, "dy", dev, (B, H // 2, W // 2, Cout), dtype=torch.bfloat16)
+        _ptr(x, "x", dev, dtype=torch.bfloat16)
+        dw = torch.empty(Cout, 3, 3, Cin, device=dev)
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_bf16_conv3x3s2_wgrad(ctx, dy.data_ptr(), x.data_ptr(), B, H, W, Cin, Cout,
+                                               dw.data_ptr(), self._stream(dev))
+        self._check(ctx, rc, "cs_bf16_conv3x3s2_wgrad")
+        return dw
+
+    def linear_forward(self, x, w, bias, relu=True, want_bf16=True):
+        """x [B][In] bf16, w [Out][In] bf16 -> (y bf16 or None, y FP32)."""
+        dev = x.device
+        B, In = x.shape
+        Out = w.shape[0]
+        _ptr(x, "x", dev, dtype=torch.bfloat16)
+        _ptr(w, "w", dev, (Out, In), dtype=torch.bfloat16)
+        _ptr(bias, "bias", dev, (Out,))
+        y = torch.empty(B, Out, device=dev, dtype=torch.bfloat16) if want_bf16 else None
+        y32 = torch.empty(B, Out, device=dev)
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_bf16_linear_forward(ctx, x.data_ptr(), w.data_ptr(),
+                                              None if bias is None else bias.data_ptr(), B, In, Out,
+                                              int(relu), None if y is None else y.data_ptr(),
+                                              y32.data_ptr(), self._stream(dev))
+        self._check(ctx, rc, "cs_bf16_linear_forward")
+        return y, y32
+
+    def linear_dgrad(self, dy, wt, x_act, want_f32=False):
+        dev = dy.device
+        B, Out = dy.shape
+        In = wt.shape[0]
+        _ptr(dy, "dy", dev, dtype=torch.bfloat16)
+        _ptr(wt, "wt", dev, (In, Out), dtype=torch.bfloat16)
+        _ptr(x_act, "x_act", dev, (B, In), dtype=torch.bfloat16)
+        dx = torch.empty(B, In, device=dev, dtype=torch.bfloat16)
+        dx32 = torch.empty(B, In, device=dev) if want_f32 else None
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_bf16_linear_dgrad(ctx, dy.data_ptr(), wt.data_ptr(),
+                                            None if x_act is None else x_act.data_ptr(), B, In, Out,
+                                            dx.data_ptr(), None if dx32 is None else dx32.data_ptr(),
+                                            self._stream(dev))
+        self._check(ctx, rc, "cs_bf16_linear_dgrad")
+        return dx, dx32
+
+    def linear_wgrad(self, dy, x):
+        dev = dy.device
+        B, Out = dy.shape
+        In = x.shape[1]
+        _ptr(dy, "dy", dev, dtype=torch.bfloat16)
+        _ptr(x, "x", dev, (B, In), dtype=torch.bfloat16)
+        dw = torch.empty(Out, In, device=dev)
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_bf16_linear_wgrad(ctx, dy.data_ptr(), x.data_ptr(), B, In, Out,
+                                            dw.data_ptr(), self._stream(dev))
+        self._check(ctx, rc, "cs_bf16_linear_wgrad")
+        return dw
+
+    def pose_head(self, raw, rot_target=None, shift_target=None, lam=1.0):
+        """raw [B][8] -> dict(rot [B][3][3], shift [B][2], and with targets loss, d_raw)."""
+        dev = raw.device
+        B = raw.shape[0]
+        _ptr(raw, "raw", dev, (B, 8))
+        rot = torch.empty(B, 3, 3, device=dev)
+        shift = torch.empty(B, 2, device=dev)
+        out = {"rot": rot, "shift": shift}
+        args = [None, None, None, None]
+        if rot_target is not None:
+            _ptr(rot_target, "rot_target", dev, (B, 3, 3))
+            _ptr(shift_target, "shift_target", dev, (B, 2))
+            out["loss"] = torch.empty(1, device=dev)
+            out["d_raw"] = torch.empty(B, 8, device=dev)
+            args = [rot_target.data_ptr(), shift_target.data_ptr(), out["loss"].data_ptr(),
+                    out["d_raw"].data_ptr()]
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_pose_head(ctx, raw.data_ptr(), B, rot.data_ptr(), shift.data_ptr(),
+                                   args[0], args[1], float(lam), args[2], args[3],
+                                   self._stream(dev))
+        self._check(ctx, rc, "cs_pose_head")
+        return out
+
+
+class PoseBank:
+    """Handle of a cs_pose_bank (projections + power spectra of a rotation set)."""
+
+    def __init__(self, owner: "Library", device: torch.device, h, K: int, D: int, pixel: float,
+                 n_psi: int):
+        self.owner, self.lib, self.device = owner, owner.lib, device
+        self.ctx = owner.ctx(device)
+        self.h, self.K, self.D, self.pixel, self.n_psi = h, K, D, pixel, n_psi
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.cs_pose_bank_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _s(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def rotations(self):
+        out = torch.empty(self.K, 3, 3, device=self.device)
+        self.owner._check(self.ctx, self.lib.cs_pose_bank_rotations(self.h, out.data_ptr(), self._s()),
+                          "cs_pose_bank_rotations")
+        return out
+
+    def _ctf(self, ctf, P):
+        if ctf is None:
+            return None
+        d = self.device
+        return CsCtf(_ptr(ctf.defocus_u, "defocus_u", d, (P,)), _ptr(ctf.defocus_v, "defocus_v", d, (P,)),
+                     _ptr(ctf.astig, "astig", d, (P,)), _ptr(ctf.phase, "phase", d, (P,)),
+                     float(ctf.voltage_kv), float(ctf.cs_mm), float(ctf.amp_contrast),
+                     float(ctf.bfactor))
+
+    def _outs(self, P, S, ncols, want_scores):
+        d = self.device
+        out = {"rot_idx": torch.empty(P, device=d, dtype=torch.int32),
+               "shift_idx": torch.empty(P, device=d, dtype=torch.int32),
+               "score": torch.empty(P, device=d)}
+        out["scores"] = torch.empty(P, ncols, S, device=d) if want_scores else None
+        return out
+
+    @staticmethod
+    def _p(t):
+        return None if t is None else t.data_ptr()
+
+    def grid_search(self, images, ctf=None, shift_radius=2, want_scores=False):
+        P = images.shape[0]
+        _ptr(images, "images", self.device, (P, self.D, self.D))
+        S = (2 * shift_radius + 1) ** 2
+        out = self._outs(P, S, self.K, want_scores)
+        c = self._ctf(ctf, P)
+        self.owner._check(self.ctx, self.lib.cs_pose_grid_search(
+            self.h, images.data_ptr(), None if c is None else ctypes.byref(c), P, int(shift_radius),
+            out["rot_idx"].data_ptr(), out["shift_idx"].data_ptr(), out["score"].data_ptr(),
+            self._p(out["scores"]), self._s()), "cs_pose_grid_search")
+        return out
+
+    def refine(self, images, ctf=None, proposal=None, cand=None, n_dir=8, n_psi_c=3,
+               shift_radius=2, want_scores=False):
+        P = images.shape[0]
+        _ptr(images, "images", self.device, (P, self.D, self.D))
+        S = (2 * shift_radius + 1) ** 2
+        if proposal is None:
+            if cand is None:
+                raise ValueError("need a proposal or candidate lists")
+            L = cand.shape[1]
+            n_dir, n_psi_c = L, 1
+        else:
+            _ptr(proposal, "proposal", self.device, (P, 3, 3))
+            L = n_dir * n_psi_c
+            if cand is None:
+                cand = torch.empty(P, L, device=self.device, dtype=torch.int32)
+        _ptr(cand, "cand", self.device, (P, L), dtype=torch.int32)
+        out = self._outs(P, S, L, want_scores)
+        out["cand"] = cand
+        c = self._ctf(ctf, P)
+        self.owner._check(self.ctx, self.lib.cs_pose_refine(
+            self.h, images.data_ptr(), None if c is None else ctypes.byref(c), P,
+            self._p(proposal), int(n_dir), int(n_psi_c), int(shift_radius), cand.data_ptr(),
+            out["rot_idx"].data_ptr(), out["shift_idx"].data_ptr(), out["score"].data_ptr(),
+            self._p(out["scores"]), self._s()), "cs_pose_refine")
+        return out
+
+
+def _ctf_struct(ctf, P, device):
+    if ctf is None:
+        return None
+    return CsCtf(_ptr(ctf.defocus_u, "defocus_u", device, (P,)),
+                 _ptr(ctf.defocus_v, "defocus_v", device, (P,)),
+                 _ptr(ctf.astig, "astig", device, (P,)), _ptr(ctf.phase, "phase", device, (P,)),
+                 float(ctf.voltage_kv), float(ctf.cs_mm), float(ctf.amp_contrast),
+                 float(ctf.bfactor))
+
+
+class PoseBatch:
+    """Handle of a cs_pose_batch: particle-side data shared by searches."""
+
+    def __init__(self, owner: "Library", device: torch.device, D: int, pixel: float,
+                 capacity: int, shift_radius: int):
+        self.owner, self.lib, self.device = owner, owner.lib, device
+        self.ctx = owner.ctx(device)
+        self.D, self.pixel, self.capacity, self.r = D, pixel, capacity, shift_radius
+        self.S = (2 * shift_radius + 1) ** 2
+        h = ctypes.c_void_p()
+        owner._check(self.ctx, self.lib.cs_pose_batch_create(self.ctx, D, float(pixel), capacity,
+                                                             shift_radius, ctypes.byref(h)),
+                     "cs_pose_batch_create")
+        self.h, self.P = h, 0
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.cs_pose_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _s(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def load(self, images, ctf=None, filtered=None):
+        """Prepare P images; filtered [P][D][D] (optional) receives Z = H Y."""
+        P = images.shape[0]
+        _ptr(images, "images", self.device, (P, self.D, self.D))
+        _ptr(filtered, "filtered", self.device, (P, self.D, self.D))
+        c = _ctf_struct(ctf, P, self.device)
+        self.owner._check(self.ctx, self.lib.cs_pose_batch_load(
+            self.h, images.data_ptr(), None if c is None else ctypes.byref(c), P,
+            None if filtered is None else filtered.data_ptr(), self._s()), "cs_pose_batch_load")
+        self.P = P
+        return filtered
+
+    def _outs(self, ncols, want_scores):
+        d, P = self.device, self.P
+        return {"rot_idx": torch.empty(P, device=d, dtype=torch.int32),
+                "shift_idx": torch.empty(P, device=d, dtype=torch.int32),
+                "score": torch.empty(P, device=d),
+                "scores": torch.empty(P, ncols, self.S, device=d) if want_scores else None}
+
+    def search(self, bank: "PoseBank", want_scores=False):
+        out = self._outs(bank.K, want_scores)
+        self.owner._check(self.ctx, self.lib.cs_pose_batch_search(
+            bank.h, self.h, out["rot_idx"].data_ptr(), out["shift_idx"].data_ptr(),
+            out["score"].data_ptr(), PoseBank._p(out["scores"]), self._s()),
+            "cs_pose_batch_search")
+        return out
+
+    def refine(self, bank: "PoseBank", proposal=None, cand=None, n_dir=8, n_psi_c=3,
+               want_scores=False):
+        P = self.P
+        if proposal is None:
+            if cand is None:
+                raise ValueError("need a proposal or candidate lists")
+            L = cand.shape[1]
+            n_dir, n_psi_c = L, 1
+        else:
+            _ptr(proposal, "proposal", self.device, (P, 3, 3))
+            L = n_dir * n_psi_c
+        if cand is not None:
+            _ptr(cand, "cand", self.device, (P, L), dtype=torch.int32)
+        out = self._outs(L, want_scores)
+        out["cand"] = cand
+        self.owner._check(self.ctx, self.lib.cs_pose_batch_refine(
+            bank.h, self.h, PoseBank._p(proposal), int(n_dir), int(n_psi_c), PoseBank._p(cand),
+            out["rot_idx"].data_ptr(), out["shift_idx"].data_ptr(), out["score"].data_ptr(),
+            PoseBank._p(out["scores"]), self._s()), "cs_pose_batch_refine")
+        return out
+
+
+class Network:
+    """Handle of a cs_cnn pose-proposal network (owned; freed on close/del)."""
+
+    def __init__(self, owner: Library, device: torch.device, D: int, max_batch: int, seed: int):
+        self.owner, self.lib, self.device = owner, owner.lib, device
+        self.D, self.max_batch = D, max_batch
+        self.ctx = owner.ctx(device)
+        h = ctypes.c_void_p()
+        owner._check(self.ctx, self.lib.cs_cnn_create(self.ctx, D, max_batch, int(seed),
+                                                      ctypes.byref(h)), "cs_cnn_create")
+        self.h = h
+        self.n_params = int(self.lib.cs_cnn_param_count(self.h))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.cs_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _s(self):
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def get_params(self):
+        out = torch.empty(self.n_params, device=self.device)
+        self.owner._check(self.ctx, self.lib.cs_cnn_get_params(self.h, out.data_ptr(), self._s()),
+                          "cs_cnn_get_params")
+        return out
+
+    def set_params(self, p):
+        _ptr(p, "params", self.device, (self.n_params,))
+        self.owner._check(self.ctx, self.lib.cs_cnn_set_params(self.h, p.data_ptr(), self._s()),
+                          "cs_cnn_set_params")
+
+    def forward(self, images):
+        B = images.shape[0]
+        _ptr(images, "images", self.device, (B, self.D, self.D))
+        rot = torch.empty(B, 3, 3, device=self.device)
+        shift = torch.empty(B, 2, device=self.device)
+        raw = torch.empty(B, 8, device=self.device)
+        self.owner._check(self.ctx, self.lib.cs_cnn_forward(self.h, images.data_ptr(), B,
+                                                            rot.data_ptr(), shift.data_ptr(),
+                                                            raw.data_ptr(), self._s()),
+                          "cs_cnn_forward")
+        return rot, shift, raw
+
+    def tensor(self, index: int, grad: bool, shape):
+        """Stored bfloat16 activation (grad=False) or gradient (grad=True) of the last call."""
+        out = torch.empty(shape, device=self.device, dtype=torch.bfloat16)
+        self.owner._check(self.ctx, self.lib.cs_cnn_tensor(self.h, int(index), int(grad),
+                                                           out.data_ptr(), out.numel(), self._s()),
+                          "cs_cnn_tensor")
+        return out
+
+    def train_step(self, images, rot_target, shift_target, lam=1.0, lr=1e-3, update=True,
+                   want_grads=False, loss=None):
+        B = images.shape[0]
+        _ptr(images, "images", self.device, (B, self.D, self.D))
+        _ptr(rot_target, "rot_target", self.device, (B, 3, 3))
+        _ptr(shift_target, "shift_target", self.device, (B, 2))
+        if loss is None:
+            loss = torch.empty(1, device=self.device)
+        grads = torch.empty(self.n_params, device=self.device) if want_grads else None
+        self.owner._check(self.ctx, self.lib.cs_cnn_train_step(
+            self.h, images.data_ptr(), rot_target.data_ptr(), shift_target.data_ptr(), B,
+            float(lam), float(lr), loss.data_ptr(), None if grads is None else grads.data_ptr(),
+            int(update), self._s()), "cs_cnn_train_step")
+        return loss, grads
 
 
 #: Kernel stages the library may launch (names reported by stage_time).

@@ -13,31 +13,10 @@
 #include <vector>
 
 #include "../../include/cryosplat.h"
+#include "cs_host.hpp"
 #include "cs_internal.hpp"
 
 using namespace cs;
-
-struct cs_ctx {
-  int device = 0;
-  std::string err;
-  void *ws = nullptr;
-  size_t ws_bytes = 0;
-  size_t ws_max = 0;  // 0 = unlimited
-  int n_cu = 256;
-  std::map<int, float2 *> twiddles;
-  // stage timing
-  bool timing = false;
-  struct Pending { const char *name; hipEvent_t a, b; };
-  std::vector<Pending> pending;
-  std::map<std::string, std::pair<double, int64_t>> stage_ms;
-  // graph capture
-  bool capturing = false;
-  hipStream_t cap_stream = nullptr;
-  std::map<std::string, hipGraphExec_t> graphs;
-  // autotuner cache: signature -> (tile, halo, budget)
-  std::map<std::string, std::vector<int>> tuned;
-  std::string tune_file;
-};
 
 namespace {
 
@@ -47,48 +26,12 @@ constexpr int kDefaultHalo = 16;
 constexpr int kDefaultBudget = 2048;
 constexpr int kMaxD = 512;
 
-int fail(cs_ctx *c, int code, const char *fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  if (c) c->err = buf;
-  return code;
-}
-
-#define HIPCHK(x)                                                                    \
-  do {                                                                               \
-    hipError_t e_ = (x);                                                             \
-    if (e_ != hipSuccess) return fail(ctx, CS_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
-  } while (0)
-
-#define LAUNCHCHK(name)                                                              \
-  do {                                                                               \
-    hipError_t e_ = hipGetLastError();                                               \
-    if (e_ != hipSuccess) return fail(ctx, CS_ERR_HIP, "launch %s: %s", name, hipGetErrorString(e_)); \
-  } while (0)
-
-// Launch with optional event bracketing (stage timing; off during capture).
-#define TLAUNCH(kernel, grid, block, lds, st, ...)                                   \
-  do {                                                                               \
-    hipEvent_t ea_ = nullptr, eb_ = nullptr;                                         \
-    const bool tm_ = ctx->timing && !ctx->capturing;                                 \
-    if (tm_) {                                                                       \
-      (void)hipEventCreate(&ea_);                                                    \
-      (void)hipEventCreate(&eb_);                                                    \
-      (void)hipEventRecord(ea_, st);                                                 \
-    }                                                                                \
-    hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);                   \
-    LAUNCHCHK(#kernel);                                                              \
-    if (tm_) {                                                                       \
-      (void)hipEventRecord(eb_, st);                                                 \
-      ctx->pending.push_back({#kernel, ea_, eb_});                                   \
-    }                                                                                \
-  } while (0)
-
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+namespace cs {
 
 bool fft_plan(int L, FftPlan &P) {
   if (L < 2 || L > kMaxD) return false;
@@ -101,11 +44,23 @@ bool fft_plan(int L, FftPlan &P) {
   return r == 1 && P.nst <= 12;
 }
 
+}  // namespace cs
+
+namespace {
+
+}  // namespace
+
+namespace cs {
+
 double electron_wavelength_A(double kv) {
   const double h = 6.62607015e-34, m0 = 9.1093837015e-31, e = 1.602176634e-19, c = 299792458.0;
   const double eV = e * kv * 1e3;
   return h / std::sqrt(2.0 * m0 * eV * (1.0 + eV / (2.0 * m0 * c * c))) * 1e10;
 }
+
+}  // namespace cs
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Per-problem plan
@@ -203,6 +158,10 @@ int ensure_ws(cs_ctx *ctx, size_t need, hipStream_t stream) {
   return CS_OK;
 }
 
+}  // namespace
+
+namespace cs {
+
 int get_twiddles(cs_ctx *ctx, int L, const float2 **out) {
   auto it = ctx->twiddles.find(L);
   if (it != ctx->twiddles.end()) { *out = it->second; return CS_OK; }
@@ -219,6 +178,10 @@ int get_twiddles(cs_ctx *ctx, int L, const float2 **out) {
   *out = d;
   return CS_OK;
 }
+
+}  // namespace cs
+
+namespace {
 
 int validate(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf *ctf,
              const cs_options *opt) {
@@ -279,6 +242,10 @@ Geom make_geom(const cs_gaussians *g, const cs_views *v, const cs_options *opt) 
   return G;
 }
 
+}  // namespace
+
+namespace cs {
+
 CtfDev make_ctf(const cs_ctf *ctf) {
   CtfDev c{};
   if (!ctf) return c;
@@ -293,6 +260,10 @@ CtfDev make_ctf(const cs_ctf *ctf) {
   c.bfactor = ctf->bfactor;
   return c;
 }
+
+}  // namespace cs
+
+namespace {
 
 bool has_grads(const cs_grads &g) { return g.means || g.log_scales || g.quats || g.amps; }
 
@@ -731,6 +702,7 @@ void cs_destroy(cs_ctx *ctx) {
     (void)hipEventDestroy(p.b);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->aux) (void)hipFree(ctx->aux);
   for (auto &kv : ctx->twiddles) (void)hipFree(kv.second);
   delete ctx;
 }

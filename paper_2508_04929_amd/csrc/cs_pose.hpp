@@ -1,0 +1,51 @@
+// Launchers of the pose-scoring kernels (k_pose.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cs {
+
+enum { kPoseStore = 0, kPoseScore = 1, kPoseRefine = 2 };
+
+// Operands of the pose GEMMs (bfloat16 as raw uint16, K contiguous).
+struct PoseGemmArgs {
+  const unsigned short *A = nullptr;   // rows of length >= K (lda elements apart)
+  int64_t lda = 0;
+  const unsigned short *A2 = nullptr;  // refine: second A segment (per particle), k >= ka_split
+  int64_t lda2 = 0;
+  int ka_split = 0;
+  const unsigned short *B = nullptr;   // row n (or cand[p][n]) at B + row * ldb + boff
+  int64_t ldb = 0, boff = 0;
+  const int *cand = nullptr;           // refine: [P][L] bank rows (out of [0, nrows): skipped)
+  int L = 0;
+  int64_t nrows = 0;                   // refine: rows of B
+  int M = 0, N = 0, K = 0;             // K a multiple of the kernel's K step (32 / 128)
+  int S = 1;                           // shifts per particle
+  float *C = nullptr;                  // store: [M][ldc]
+  int64_t ldc = 0;
+  const float *E = nullptr;            // score: energy [P][lde]
+  int64_t lde = 0;
+  const float *yy = nullptr;           // [P]
+  unsigned long long *best = nullptr;  // [P] packed (score, index) minima
+  float *scores = nullptr;             // optional [P][N][S]
+};
+
+hipError_t pose_prep(const float *Y, const float *Z, const float *table, int P, int D, int r,
+                     int F8, unsigned short *zs, unsigned short *w, float *yy, hipStream_t st);
+hipError_t rows_to_bf16(const float *src, int64_t rows, int len, unsigned short *dst, int64_t ld,
+                        hipStream_t st);
+hipError_t fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
+hipError_t fill_u16(unsigned short *p, int64_t n, hipStream_t st);
+hipError_t pose_decode(const unsigned long long *best, int P, int S, int *rot_idx, int *shift_idx,
+                       float *score, hipStream_t st);
+hipError_t pose_gemm_store(const PoseGemmArgs &a, hipStream_t st);
+hipError_t pose_gemm_score(const PoseGemmArgs &a, hipStream_t st);
+hipError_t pose_gemm_refine(const PoseGemmArgs &a, int P, hipStream_t st);
+hipError_t pose_candidates(const float *prop, int P, const float *bank_rot, int ndir, int n_psi,
+                           int n_dir, int n_psi_c, int *cand, hipStream_t st);
+
+hipError_t add_noise(float *img, int B, int npx, float snr_db, unsigned long long seed,
+                     long long offset, hipStream_t st);
+
+}  // namespace cs

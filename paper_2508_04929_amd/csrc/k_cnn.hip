@@ -1,0 +1,697 @@
+// Pose-proposal network kernels: BF16 MFMA GEMMs for 3x3 stride-2 convs
+// (forward, data gradient, weight gradient) and linear layers, a VALU kernel
+// for the single-channel first conv, the 6-D -> SO(3) head and its loss.
+//
+// Activations are NHWC BF16 ([B][H][W][C]); weights are [Cout][ky][kx][Cin]
+// BF16 with FP32 masters.  Every GEMM accumulates in FP32 with
+// v_mfma_f32_16x16x32_bf16 (gfx950): a 64x64 block tile, four waves of
+// 32x32, K steps of 32 staged through LDS.  Operand tiles are gathered
+// straight from the activations (implicit im2col), 16 bytes per thread.
+#include "cs_cnn.hpp"
+
+namespace cs {
+
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float((unsigned)v << 16); }
+
+// Round to nearest even (NaN kept quiet).
+__device__ __forceinline__ bf16 f2bf(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+
+constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // LDS rows padded to 80 bytes
+
+struct GemmTiles {
+  bf16 a[BM][LDK];
+  bf16 b[BN][LDK];
+};
+
+union Vec8 {
+  uint4 u;
+  bf16 h[8];
+};
+
+// ---------------------------------------------------------------------------
+// Generic split-K GEMM: C[m][n] = sum_k A[m][k] B[n][k] over k in this
+// block's K range.  Op supplies the gathers and the epilogue:
+//   Op::kATrans / kBTrans: false = 8 consecutive k of one row per 16-byte
+//   load (a_vec / b_vec); true = 8 consecutive rows of one k (a_vecT / b_vecT).
+// ---------------------------------------------------------------------------
+// One K step of an operand tile: each thread fetches 16 bytes into a
+// register (prefetched while the previous step computes), then stores them
+// into the LDS tile (non-transposed: 8 consecutive k of one row; transposed:
+// 8 consecutive rows of one k, scattered into 8 rows).
+template <class Op>
+__device__ __forceinline__ uint4 fetch_tile(const Op &op, bool isA, int r0, int k0, int R,
+                                            int Kend) {
+  const int t = threadIdx.x;
+  const bool trans = isA ? Op::kATrans : Op::kBTrans;
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (!trans) {
+    const int r = r0 + (t >> 2), k = k0 + (t & 3) * 8;
+    if (r < R && k < Kend) v = isA ? op.a_vec(r, k) : op.b_vec(r, k);
+  } else {
+    const int r = r0 + (t & 7) * 8, k = k0 + (t >> 3);
+    if (r < R && k < Kend) v = isA ? op.a_vecT(r, k) : op.b_vecT(r, k);
+  }
+  return v;
+}
+
+template <class Op>
+__device__ __forceinline__ void put_tile(bool isA, bf16 (*tile)[LDK], uint4 v) {
+  const int t = threadIdx.x;
+  const bool trans = isA ? Op::kATrans : Op::kBTrans;
+  if (!trans) {
+    *(uint4 *)&tile[t >> 2][(t & 3) * 8] = v;
+  } else {
+    Vec8 u;
+    u.u = v;
+    const int kk = t >> 3, rq = (t & 7) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) tile[rq + i][kk] = u.h[i];
+  }
+}
+
+template <class Op>
+__global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kchunk) {
+  __shared__ GemmTiles T[2];
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra = fetch_tile(op, true, m0, kb, M, ke);
+  uint4 rb = fetch_tile(op, false, n0, kb, N, ke);
+  put_tile<Op>(true, T[0].a, ra);
+  put_tile<Op>(false, T[0].b, rb);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) {
+      ra = fetch_tile(op, true, m0, k0 + BK, M, ke);
+      rb = fetch_tile(op, false, n0, k0 + BK, N, ke);
+    }
+    bf16x8 af[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      af[i] = *(const bf16x8 *)&T[cur].a[wm + i * 16 + (lane & 15)][(lane >> 4) * 8];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      bv[j] = *(const bf16x8 *)&T[cur].b[wn + j * 16 + (lane & 15)][(lane >> 4) * 8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bv[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      put_tile<Op>(true, T[cur ^ 1].a, ra);
+      put_tile<Op>(false, T[cur ^ 1].b, rb);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+        const int n = n0 + wn + j * 16 + (lane & 15);
+        if (m < M && n < N) op.store(m, n, acc[i][j][r], blockIdx.z);
+      }
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 stride-2 pad-1 convolution as GEMMs (NHWC, Cin and Cout multiples of 8)
+// ---------------------------------------------------------------------------
+struct ConvGeom {
+  int B, Hi, Wi, Cin, Ho, Wo, Cout;
+};
+
+// forward: M = B Ho Wo, N = Cout, K = 9 Cin (k = tap * Cin + ci)
+struct ConvFwdOp {
+  static constexpr bool kATrans = false, kBTrans = false;
+  ConvGeom g;
+  const bf16 *in, *w;
+  const float *bias;
+  bf16 *out;
+  float *out32;
+  int relu;
+  __device__ uint4 a_vec(int m, int k) const {
+    const int ox = m % g.Wo, t = m / g.Wo, oy = t % g.Ho, b = t / g.Ho;
+    const int tap = k / g.Cin, ci = k - tap * g.Cin;
+    const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+    if (iy < 0 || iy >= g.Hi || ix < 0 || ix >= g.Wi) return make_uint4(0, 0, 0, 0);
+    return *(const uint4 *)&in[(((size_t)b * g.Hi + iy) * g.Wi + ix) * g.Cin + ci];
+  }
+  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&w[(size_t)n * 9 * g.Cin + k]; }
+  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ void store(int m, int n, float v, int) const {
+    v += bias ? bias[n] : 0.f;
+    if (relu) v = fmaxf(v, 0.f);
+    const size_t o = (size_t)m * g.Cout + n;
+    if (out32) out32[o] = v;
+    out[o] = f2bf(v);
+  }
+};
+
+// data gradient: M = B Hi Wi, N = Cin, K = 9 Cout (k = tap * Cout + co);
+// wt is the weight transposed to [Cin][tap][Cout]; the epilogue applies
+// the ReLU mask of the layer's input activation (act_in > 0).
+struct ConvDgradOp {
+  static constexpr bool kATrans = false, kBTrans = false;
+  ConvGeom g;
+  const bf16 *dout, *wt, *act_in;
+  bf16 *din;
+  float *din32;
+  __device__ uint4 a_vec(int m, int k) const {
+    const int ix = m % g.Wi, t = m / g.Wi, iy = t % g.Hi, b = t / g.Hi;
+    const int tap = k / g.Cout, co = k - tap * g.Cout;
+    const int oy2 = iy + 1 - tap / 3, ox2 = ix + 1 - tap % 3;
+    if (oy2 < 0 || ox2 < 0 || (oy2 & 1) || (ox2 & 1)) return make_uint4(0, 0, 0, 0);
+    const int oy = oy2 >> 1, ox = ox2 >> 1;
+    if (oy >= g.Ho || ox >= g.Wo) return make_uint4(0, 0, 0, 0);
+    return *(const uint4 *)&dout[(((size_t)b * g.Ho + oy) * g.Wo + ox) * g.Cout + co];
+  }
+  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&wt[(size_t)n * 9 * g.Cout + k]; }
+  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ void store(int m, int n, float v, int) const {
+    const size_t o = (size_t)m * g.Cin + n;
+    if (act_in && !(bf2f(act_in[o]) > 0.f)) v = 0.f;
+    if (din32) din32[o] = v;
+    din[o] = f2bf(v);
+  }
+};
+
+// weight gradient: M = Cout, N = 9 Cin (n = tap * Cin + ci), K = B Ho Wo
+// pixels; split-K partials part[z][M][N] (FP32).
+struct ConvWgradOp {
+  static constexpr bool kATrans = true, kBTrans = true;
+  ConvGeom g;
+  const bf16 *dout, *in;
+  float *part;
+  __device__ uint4 a_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 b_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
+  // 8 consecutive output channels of pixel p
+  __device__ uint4 a_vecT(int m, int p) const { return *(const uint4 *)&dout[(size_t)p * g.Cout + m]; }
+  // 8 consecutive (tap, ci) columns of the im2col row of pixel p
+  __device__ uint4 b_vecT(int n, int p) const {
+    const int ox = p % g.Wo, t = p / g.Wo, oy = t % g.Ho, b = t / g.Ho;
+    const int tap = n / g.Cin, ci = n - tap * g.Cin;
+    const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+    if (iy < 0 || iy >= g.Hi || ix < 0 || ix >= g.Wi) return make_uint4(0, 0, 0, 0);
+    return *(const uint4 *)&in[(((size_t)b * g.Hi + iy) * g.Wi + ix) * g.Cin + ci];
+  }
+  __device__ void store(int m, int n, float v, int z) const {
+    part[((size_t)z * g.Cout + m) * 9 * g.Cin + n] = v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Linear layers: y[b][o] = sum_i W[o][i] x[b][i] + bias[o]
+// ---------------------------------------------------------------------------
+struct LinGeom {
+  int B, In, Out;
+};
+
+struct LinFwdOp {  // M = B, N = Out, K = In
+  static constexpr bool kATrans = false, kBTrans = false;
+  LinGeom g;
+  const bf16 *x, *w;
+  const float *bias;
+  bf16 *y;
+  float *y32;
+  int relu;
+  __device__ uint4 a_vec(int m, int k) const { return *(const uint4 *)&x[(size_t)m * g.In + k]; }
+  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&w[(size_t)n * g.In + k]; }
+  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ void store(int m, int n, float v, int) const {
+    v += bias ? bias[n] : 0.f;
+    if (relu) v = fmaxf(v, 0.f);
+    const size_t o = (size_t)m * g.Out + n;
+    if (y32) y32[o] = v;
+    if (y) y[o] = f2bf(v);
+  }
+};
+
+struct LinDgradOp {  // M = B, N = In, K = Out; wt = W^T [In][Out]
+  static constexpr bool kATrans = false, kBTrans = false;
+  LinGeom g;
+  const bf16 *dy, *wt, *x_act;
+  bf16 *dx;
+  float *dx32;
+  __device__ uint4 a_vec(int m, int k) const { return *(const uint4 *)&dy[(size_t)m * g.Out + k]; }
+  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&wt[(size_t)n * g.Out + k]; }
+  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ void store(int m, int n, float v, int) const {
+    const size_t o = (size_t)m * g.In + n;
+    if (x_act && !(bf2f(x_act[o]) > 0.f)) v = 0.f;
+    if (dx32) dx32[o] = v;
+    dx[o] = f2bf(v);
+  }
+};
+
+struct LinWgradOp {  // M = Out, N = In, K = B; split-K partials
+  static constexpr bool kATrans = true, kBTrans = true;
+  LinGeom g;
+  const bf16 *dy, *x;
+  float *part;
+  __device__ uint4 a_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 b_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 a_vecT(int m, int b) const { return *(const uint4 *)&dy[(size_t)b * g.Out + m]; }
+  __device__ uint4 b_vecT(int n, int b) const { return *(const uint4 *)&x[(size_t)b * g.In + n]; }
+  __device__ void store(int m, int n, float v, int z) const {
+    part[((size_t)z * g.Out + m) * g.In + n] = v;
+  }
+};
+
+// Sum of split-K partials in a fixed order: out[i] = sum_z part[z][i].
+__global__ void __launch_bounds__(256)
+k_splitk_reduce(const float *part, int splits, int64_t n, float *out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + i];
+  out[i] = s;
+}
+
+// Column sums of an [M][N] BF16 gradient (bias gradients): partials over
+// row chunks part[chunk][N], then a fixed-order reduce.
+__global__ void __launch_bounds__(256)
+k_colsum(const bf16 *g, int M, int N, int rows_per_chunk, float *part) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int r0 = blockIdx.y * rows_per_chunk, r1 = min(M, r0 + rows_per_chunk);
+  float s = 0.f;
+  for (int m = r0; m < r1; ++m) s += bf2f(g[(size_t)m * N + n]);
+  part[(size_t)blockIdx.y * N + n] = s;
+}
+
+// out[0] = sum of n partials (fixed order).
+__global__ void k_sum_into(const float *part, int n, float *out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    out[0] = (float)s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First conv (Cin = 1): VALU.  One thread per (output pixel, 32 channels).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_conv1_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int Hi, int Wi, int Cout,
+            int relu, bf16 *out, float *out32) {
+  const int Ho = Hi / 2, Wo = Wi / 2;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (int64_t)B * Ho * Wo) return;
+  const int ox = (int)(p % Wo), t = (int)(p / Wo), oy = t % Ho, b = t / Ho;
+  float x[9];
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+    x[tap] = (iy >= 0 && iy < Hi && ix >= 0 && ix < Wi) ? bf2f(in[((size_t)b * Hi + iy) * Wi + ix]) : 0.f;
+  }
+  // 8 channels per 16-byte store (Cout is a multiple of 8)
+  for (int c0 = 0; c0 < Cout; c0 += 8) {
+    Vec8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int co = c0 + e;
+      float s = bias ? bias[co] : 0.f;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) s += bf2f(w[co * 9 + tap]) * x[tap];
+      if (relu) s = fmaxf(s, 0.f);
+      if (out32) out32[p * Cout + co] = s;
+      o.h[e] = f2bf(s);
+    }
+    *(uint4 *)&out[p * Cout + c0] = o.u;
+  }
+}
+
+// First-conv weight gradient partials: part[blk][co][tap] over a pixel chunk.
+__global__ void __launch_bounds__(256)
+k_conv1_wgrad(const bf16 *in, const bf16 *dpre, int B, int Hi, int Wi, int Cout,
+              int pix_per_block, float *part) {
+  const int Ho = Hi / 2, Wo = Wi / 2;
+  const int64_t npix = (int64_t)B * Ho * Wo;
+  const int64_t p0 = (int64_t)blockIdx.x * pix_per_block;
+  const int64_t p1 = min(npix, p0 + pix_per_block);
+  // thread -> (co, tap) pairs, strided
+  for (int q = 0; q < Cout * 9; q += 256) {
+    const int ct = q + threadIdx.x;
+    float s = 0.f;
+    if (ct < Cout * 9) {
+      const int co = ct / 9, tap = ct % 9;
+      for (int64_t p = p0; p < p1; ++p) {
+        const int ox = (int)(p % Wo), t = (int)(p / Wo), oy = t % Ho, b = t / Ho;
+        const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+        if (iy < 0 || iy >= Hi || ix < 0 || ix >= Wi) continue;
+        s += bf2f(dpre[p * Cout + co]) * bf2f(in[((size_t)b * Hi + iy) * Wi + ix]);
+      }
+      part[(size_t)blockIdx.x * Cout * 9 + ct] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Input standardisation: x = (img - mean) / std per image, to BF16.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_standardize(const float *img, int npx, bf16 *out) {
+  __shared__ double red[2][4];
+  const int b = blockIdx.x;
+  const float *x = img + (size_t)b * npx;
+  double s = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < npx; i += 256) {
+    const double v = x[i];
+    s += v;
+    s2 += v * v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s;
+    red[1][threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  const double m = (red[0][0] + red[0][1] + red[0][2] + red[0][3]) / npx;
+  const double var = (red[1][0] + red[1][1] + red[1][2] + red[1][3]) / npx - m * m;
+  const float inv = var > 0.0 ? (float)(1.0 / sqrt(var)) : 1.f;
+  for (int i = threadIdx.x; i < npx; i += 256) out[(size_t)b * npx + i] = f2bf((x[i] - (float)m) * inv);
+}
+
+// ---------------------------------------------------------------------------
+// Head: 6-D representation -> rotation by Gram-Schmidt (columns b1, b2,
+// b1 x b2), 2-D shift; loss ||R^ - R||_F^2 + lambda ||t^ - t||^2 averaged
+// over the batch, and its gradient w.r.t. the 8 network outputs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cross3(const float a[3], const float b[3], float c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ float dot3(const float a[3], const float b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+__device__ void gram_schmidt(const float *o, float b1[3], float b2[3], float b3[3], float &n1,
+                             float &n2, float u2[3]) {
+  const float a1[3] = {o[0], o[1], o[2]}, a2[3] = {o[3], o[4], o[5]};
+  n1 = fmaxf(sqrtf(dot3(a1, a1)), 1e-12f);
+  for (int k = 0; k < 3; ++k) b1[k] = a1[k] / n1;
+  const float d = dot3(b1, a2);
+  for (int k = 0; k < 3; ++k) u2[k] = a2[k] - d * b1[k];
+  n2 = fmaxf(sqrtf(dot3(u2, u2)), 1e-12f);
+  for (int k = 0; k < 3; ++k) b2[k] = u2[k] / n2;
+  cross3(b1, b2, b3);
+}
+
+__global__ void __launch_bounds__(256)
+k_head(const float *out8, int B, float *rot, float *shift) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  float b1[3], b2[3], b3[3], u2[3], n1, n2;
+  gram_schmidt(out8 + 8 * b, b1, b2, b3, n1, n2, u2);
+  for (int r = 0; r < 3; ++r) {
+    rot[9 * b + 3 * r + 0] = b1[r];
+    rot[9 * b + 3 * r + 1] = b2[r];
+    rot[9 * b + 3 * r + 2] = b3[r];
+  }
+  if (shift) {
+    shift[2 * b] = out8[8 * b + 6];
+    shift[2 * b + 1] = out8[8 * b + 7];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_head_loss(const float *out8, const float *rot_t, const float *shift_t, int B, float lambda,
+            float *loss_part, bf16 *dout8, float *dout32) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  float l = 0.f;
+  if (b < B) {
+    const float *o = out8 + 8 * b;
+    float b1[3], b2[3], b3[3], u2[3], n1, n2;
+    gram_schmidt(o, b1, b2, b3, n1, n2, u2);
+    const float *R = rot_t + 9 * b;
+    const float inv_b = 1.f / (float)B;
+    float g1[3], g2[3], g3[3];
+    for (int r = 0; r < 3; ++r) {
+      const float e1 = b1[r] - R[3 * r], e2 = b2[r] - R[3 * r + 1], e3 = b3[r] - R[3 * r + 2];
+      l += e1 * e1 + e2 * e2 + e3 * e3;
+      g1[r] = 2.f * e1 * inv_b;
+      g2[r] = 2.f * e2 * inv_b;
+      g3[r] = 2.f * e3 * inv_b;
+    }
+    // b3 = b1 x b2
+    float t[3];
+    cross3(b2, g3, t);
+    for (int k = 0; k < 3; ++k) g1[k] += t[k];
+    cross3(g3, b1, t);
+    for (int k = 0; k < 3; ++k) g2[k] += t[k];
+    // b2 = u2 / |u2|
+    float gu[3];
+    const float p2 = dot3(b2, g2);
+    for (int k = 0; k < 3; ++k) gu[k] = (g2[k] - b2[k] * p2) / n2;
+    // u2 = a2 - (b1 . a2) b1
+    const float a2[3] = {o[3], o[4], o[5]};
+    const float bu = dot3(b1, gu), ba = dot3(b1, a2);
+    float ga2[3];
+    for (int k = 0; k < 3; ++k) {
+      ga2[k] = gu[k] - b1[k] * bu;
+      g1[k] -= ba * gu[k] + bu * a2[k];
+    }
+    // b1 = a1 / |a1|
+    float ga1[3];
+    const float p1 = dot3(b1, g1);
+    for (int k = 0; k < 3; ++k) ga1[k] = (g1[k] - b1[k] * p1) / n1;
+    float d[8];
+    for (int k = 0; k < 3; ++k) {
+      d[k] = ga1[k];
+      d[3 + k] = ga2[k];
+    }
+    for (int k = 0; k < 2; ++k) {
+      const float e = o[6 + k] - shift_t[2 * b + k];
+      l += lambda * e * e;
+      d[6 + k] = 2.f * lambda * e * inv_b;
+    }
+    for (int k = 0; k < 8; ++k) {
+      dout8[8 * b + k] = f2bf(d[k]);
+      if (dout32) dout32[8 * b + k] = d[k];
+    }
+  }
+  // per-block partial of the batch loss (fixed order)
+  __shared__ float red[4];
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) l += __shfl_xor(l, s, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) / (float)B;
+}
+
+// FP32 master weights -> BF16 weights and, optionally, the BF16 transpose
+// [Cin][tap][Cout] (from [Cout][tap][Cin]; taps = 1 for linear layers).
+__global__ void __launch_bounds__(256)
+k_to_bf16(const float *w, int Cout, int taps, int Cin, bf16 *wb, bf16 *wt) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)Cout * taps * Cin;
+  if (i >= n) return;
+  const bf16 v = f2bf(w[i]);
+  wb[i] = v;
+  if (wt) {
+    const int ci = (int)(i % Cin), tap = (int)((i / Cin) % taps), co = (int)(i / ((int64_t)Cin * taps));
+    wt[((size_t)ci * taps + tap) * Cout + co] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_f32_to_bf16(const float *x, int64_t n, bf16 *y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = f2bf(x[i]);
+}
+
+__global__ void __launch_bounds__(256) k_bf16_to_f32(const bf16 *x, int64_t n, float *y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = bf2f(x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (declared in cs_cnn.hpp)
+// ---------------------------------------------------------------------------
+static unsigned cdiv_(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <class Op>
+static hipError_t launch_gemm(const Op &op, int M, int N, int K, int splits, hipStream_t st) {
+  int kchunk = K;
+  if (splits > 1) {
+    kchunk = (int)(((int64_t)K + splits - 1) / splits);
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    splits = (K + kchunk - 1) / kchunk;
+  }
+  hipLaunchKernelGGL(k_gemm<Op>, dim3(cdiv_(M, BM), cdiv_(N, BN), splits), dim3(256), 0, st, op,
+                     M, N, K, kchunk);
+  return hipGetLastError();
+}
+
+int wgrad_splits(int M, int N, int K) {
+  const int tiles = (int)(cdiv_(M, BM) * cdiv_(N, BN));
+  int s = (512 + tiles - 1) / tiles;
+  s = std::max(1, std::min(s, K / BK));
+  return s;
+}
+
+hipError_t conv_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int Hi, int Wi,
+                    int Cin, int Cout, int relu, bf16 *out, float *out32, hipStream_t st) {
+  if (Cin == 1) {
+    const int64_t np = (int64_t)B * (Hi / 2) * (Wi / 2);
+    hipLaunchKernelGGL(k_conv1_fwd, dim3(cdiv_(np, 256)), dim3(256), 0, st, in, w, bias, B, Hi, Wi,
+                       Cout, relu, out, out32);
+    return hipGetLastError();
+  }
+  ConvFwdOp op;
+  op.g = {B, Hi, Wi, Cin, Hi / 2, Wi / 2, Cout};
+  op.in = in; op.w = w; op.bias = bias; op.out = out; op.out32 = out32; op.relu = relu;
+  return launch_gemm(op, B * (Hi / 2) * (Wi / 2), Cout, 9 * Cin, 1, st);
+}
+
+hipError_t conv_dgrad(const bf16 *dout, const bf16 *wt, const bf16 *act_in, int B, int Hi, int Wi,
+                      int Cin, int Cout, bf16 *din, float *din32, hipStream_t st) {
+  ConvDgradOp op;
+  op.g = {B, Hi, Wi, Cin, Hi / 2, Wi / 2, Cout};
+  op.dout = dout; op.wt = wt; op.act_in = act_in; op.din = din; op.din32 = din32;
+  return launch_gemm(op, B * Hi * Wi, Cin, 9 * Cout, 1, st);
+}
+
+hipError_t conv_wgrad(const bf16 *dout, const bf16 *in, int B, int Hi, int Wi, int Cin, int Cout,
+                      float *part, size_t part_cap, float *dw, hipStream_t st) {
+  const int64_t npix = (int64_t)B * (Hi / 2) * (Wi / 2);
+  if (Cin == 1) {
+    const int ppb = 256;
+    const unsigned blocks = cdiv_(npix, ppb);
+    if ((size_t)blocks * Cout * 9 > part_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_conv1_wgrad, dim3(blocks), dim3(256), 0, st, in, dout, B, Hi, Wi, Cout,
+                       ppb, part);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv_(Cout * 9, 256)), dim3(256), 0, st, part,
+                       (int)blocks, (int64_t)Cout * 9, dw);
+    return hipGetLastError();
+  }
+  ConvWgradOp op;
+  op.g = {B, Hi, Wi, Cin, Hi / 2, Wi / 2, Cout};
+  op.dout = dout; op.in = in; op.part = part;
+  const int M = Cout, N = 9 * Cin, K = (int)npix;
+  int s = wgrad_splits(M, N, K);
+  while ((size_t)s * M * N > part_cap && s > 1) --s;
+  if ((size_t)s * M * N > part_cap) return hipErrorInvalidValue;
+  int kchunk = (K + s - 1) / s;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  s = (K + kchunk - 1) / kchunk;
+  hipError_t e = launch_gemm(op, M, N, K, s, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv_((int64_t)M * N, 256)), dim3(256), 0, st, part, s,
+                     (int64_t)M * N, dw);
+  return hipGetLastError();
+}
+
+hipError_t lin_fwd(const bf16 *x, const bf16 *w, const float *bias, int B, int In, int Out,
+                   int relu, bf16 *y, float *y32, hipStream_t st) {
+  LinFwdOp op;
+  op.g = {B, In, Out};
+  op.x = x; op.w = w; op.bias = bias; op.y = y; op.y32 = y32; op.relu = relu;
+  return launch_gemm(op, B, Out, In, 1, st);
+}
+
+hipError_t lin_dgrad(const bf16 *dy, const bf16 *wt, const bf16 *x_act, int B, int In, int Out,
+                     bf16 *dx, float *dx32, hipStream_t st) {
+  LinDgradOp op;
+  op.g = {B, In, Out};
+  op.dy = dy; op.wt = wt; op.x_act = x_act; op.dx = dx; op.dx32 = dx32;
+  return launch_gemm(op, B, In, Out, 1, st);
+}
+
+hipError_t lin_wgrad(const bf16 *dy, const bf16 *x, int B, int In, int Out, float *part,
+                     size_t part_cap, float *dw, hipStream_t st) {
+  LinWgradOp op;
+  op.g = {B, In, Out};
+  op.dy = dy; op.x = x; op.part = part;
+  const int M = Out, N = In, K = B;
+  int s = wgrad_splits(M, N, K);
+  while ((size_t)s * M * N > part_cap && s > 1) --s;
+  if ((size_t)s * M * N > part_cap) return hipErrorInvalidValue;
+  int kchunk = (K + s - 1) / s;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  s = (K + kchunk - 1) / kchunk;
+  hipError_t e = launch_gemm(op, M, N, K, s, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv_((int64_t)M * N, 256)), dim3(256), 0, st, part, s,
+                     (int64_t)M * N, dw);
+  return hipGetLastError();
+}
+
+hipError_t colsum(const bf16 *g, int M, int N, float *part, size_t part_cap, float *out,
+                  hipStream_t st) {
+  int chunks = std::max(1, std::min(1024, M / 256));
+  while ((size_t)chunks * N > part_cap && chunks > 1) chunks /= 2;
+  if ((size_t)chunks * N > part_cap) return hipErrorInvalidValue;
+  const int rpc = (M + chunks - 1) / chunks;
+  hipLaunchKernelGGL(k_colsum, dim3(cdiv_(N, 256), chunks), dim3(256), 0, st, g, M, N, rpc, part);
+  hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv_(N, 256)), dim3(256), 0, st, part, chunks,
+                     (int64_t)N, out);
+  return hipGetLastError();
+}
+
+hipError_t sum_into(const float *part, int n, float *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, st, part, n, out);
+  return hipGetLastError();
+}
+
+hipError_t standardize(const float *img, int B, int npx, bf16 *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_standardize, dim3(B), dim3(256), 0, st, img, npx, out);
+  return hipGetLastError();
+}
+
+hipError_t head(const float *out8, int B, float *rot, float *shift, hipStream_t st) {
+  hipLaunchKernelGGL(k_head, dim3(cdiv_(B, 256)), dim3(256), 0, st, out8, B, rot, shift);
+  return hipGetLastError();
+}
+
+hipError_t head_loss(const float *out8, const float *rot_t, const float *shift_t, int B,
+                     float lambda, float *loss_part, bf16 *dout8, float *dout32, hipStream_t st) {
+  hipLaunchKernelGGL(k_head_loss, dim3(cdiv_(B, 256)), dim3(256), 0, st, out8, rot_t, shift_t, B,
+                     lambda, loss_part, dout8, dout32);
+  return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *w, int Cout, int taps, int Cin, bf16 *wb, bf16 *wt, hipStream_t st) {
+  const int64_t n = (int64_t)Cout * taps * Cin;
+  hipLaunchKernelGGL(k_to_bf16, dim3(cdiv_(n, 256)), dim3(256), 0, st, w, Cout, taps, Cin, wb, wt);
+  return hipGetLastError();
+}
+
+hipError_t f32_to_bf16(const float *x, int64_t n, bf16 *y, hipStream_t st) {
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3(cdiv_(n, 256)), dim3(256), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+hipError_t bf16_to_f32(const bf16 *x, int64_t n, float *y, hipStream_t st) {
+  hipLaunchKernelGGL(k_bf16_to_f32, dim3(cdiv_(n, 256)), dim3(256), 0, st, x, n, y);
+  return hipGetLastError();
+}
+
+}  // namespace cs

@@ -363,4 +363,47 @@ k_residual(float *Q, const float *obs, float *images_out, int B, int D, float gr
   if (threadIdx.x == 0) loss_part[(size_t)b * D + row] = red[0] + red[1] + red[2] + red[3];
 }
 
+
+// ---------------------------------------------------------------------------
+// Column pass for power spectra: for cpw adjacent half-spectrum columns per
+// block, forward FFT over rows and |.|^2 stored as bfloat16 (nearest even)
+// at out[b * ld + ky * (D/2+1) + kx].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned short f2bf_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__global__ void __launch_bounds__(256)
+k_fft_cols_power(const float2 *spec, FftPlan P, const float2 *tw, int B, int cpw,
+                 unsigned short *out, size_t ld) {
+  extern __shared__ float2 lds[];
+  const int L = P.L, Dh = L / 2 + 1;
+  const int b = blockIdx.y;
+  const int kx0 = blockIdx.x * cpw;
+  const int ts = 256 / cpw;
+  const int team = threadIdx.x / ts, t = threadIdx.x % ts;
+  const float2 *img = spec + (size_t)b * L * Dh;
+  float2 *twl = lds + (size_t)cpw * 2 * L;
+  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
+  for (int q = threadIdx.x; q < cpw * L; q += 256) {
+    const int c = q % cpw, r = q / cpw;
+    const int kx = kx0 + c;
+    lds[c * 2 * L + r] = (kx < Dh) ? img[(size_t)r * Dh + kx] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2 *x = lds + team * 2 * L, *y = x + L;
+  const float2 *res = fft_team(x, y, P, twl, t, ts, false);
+  const int kx = kx0 + team;
+  if (kx < Dh) {
+    unsigned short *o = out + (size_t)b * ld + kx;
+    for (int ky = t; ky < L; ky += ts) {
+      const float2 z = res[ky];
+      o[(size_t)ky * Dh] = f2bf_rne(z.x * z.x + z.y * z.y);
+    }
+  }
+}
+
 }  // namespace cs

@@ -214,3 +214,48 @@ def c4(seed: int = 4, b: int = 64, n: int = 200000):
     gt.amps = _f32(gt.amps * (0.5 / float(gt.amps.astype(np.float64).sum())))
     v = views(rv, b, D, p, defocus_um=(0.5, 2.5))
     return g, v, gt, rn
+
+
+def mixture_domains(rng, n, n_domains=6, radius=40.0, extent=(6.0, 16.0),
+                    scale_mu=np.log(1.5), scale_sd=0.3):
+    """Random mixture with domain structure (an asymmetric, protein-like mass).
+
+    Domain centres are uniform in a ball of `radius` A; each domain is an
+    anisotropic normal cloud of Gaussian means with axis standard deviations
+    U(extent) A in a Haar-random frame and a density weight U(0.5, 1.5);
+    every Gaussian picks a domain uniformly.  Log-scales, quaternions and
+    lognormal amplitudes as in mixture_anisotropic.
+    """
+    centres = uniform_ball(rng, n_domains, radius)
+    frames = haar_rotations(rng, n_domains)
+    sds = rng.uniform(extent[0], extent[1], size=(n_domains, 3))
+    weight = rng.uniform(0.5, 1.5, size=n_domains)
+    dom = rng.integers(0, n_domains, size=n)
+    local = rng.standard_normal((n, 3)) * sds[dom]
+    means = centres[dom] + np.einsum("nij,nj->ni", frames[dom], local)
+    return Mixture(
+        means=_f32(means),
+        log_scales=_f32(scale_mu + scale_sd * rng.standard_normal((n, 3))),
+        quats=_f32(haar_quaternions(rng, n)),
+        amps=_f32(np.exp(0.5 * rng.standard_normal(n)) * weight[dom]),
+    )
+
+
+def pose_views(rng, b, D, pixel, defocus_um=(0.8, 2.5), shift_px_max=2.0):
+    """Particle poses for pose search: Haar rotations, in-plane shifts
+    uniform in [-shift_px_max, shift_px_max]^2 pixels, defocus U(defocus_um)."""
+    v = views(rng, b, D, pixel, defocus_um=defocus_um)
+    v.shift = _f32(rng.uniform(-shift_px_max, shift_px_max, size=(b, 2)) * pixel)
+    return v
+
+
+def c5(seed: int = 5, n_train: int = 200000, n_test: int = 2048, n: int = 20000, D: int = 128):
+    """Learned pose proposal: a fixed N=20,000 random mixture (domain
+    structure, radius 40 A domains), D=128, p=1.5 A; training and test
+    particles at Haar poses, shifts U(-2, 2) px, defocus U(0.8, 2.5) um,
+    white noise at SNR -20 dB added on the device per image."""
+    rg, rtr, rte = streams(seed, 3)
+    g = mixture_domains(rg, n)
+    train = pose_views(rtr, n_train, D, 1.5)
+    test = pose_views(rte, n_test, D, 1.5)
+    return g, train, test

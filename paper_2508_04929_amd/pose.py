@@ -1,0 +1,268 @@
+"""Learned pose proposal: data, training and evaluation driven through the library.
+
+Every numerical step runs in libcryosplat: the splatter renders the
+training and test particles (with CTF), the library adds the noise, the
+network trains with the library's BF16-MFMA forward/backward kernels and
+Adam, and poses are scored by the library's grid search and refinement.
+This module only sequences those calls, slices batches and times them.
+
+Pipeline of the learned path for a batch of particles:
+  1. network forward -> rotation proposal W0 (6-D -> Gram-Schmidt)
+  2. refinement stages, each scoring the candidates of one pose bank around
+     the current estimate (nearest bank directions x in-plane angles x
+     (2r+1)^2 shifts) with the renderer's squared-error score; the best
+     candidate seeds the next stage.
+The exhaustive grid search over the coarse bank is the fallback and the
+judge of angular error.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import binding, inputs
+
+
+@dataclasses.dataclass
+class PoseSet:
+    """Particle poses and CTF parameters resident on the device."""
+    rot: torch.Tensor        # [n][3][3] world -> view
+    shift: torch.Tensor      # [n][2] Angstrom
+    shift_px: torch.Tensor   # [n][2] pixels (network target)
+    defocus: torch.Tensor    # [n] Angstrom
+    zeros: torch.Tensor      # [n] (astigmatism angle, phase shift)
+    D: int
+    pixel: float
+
+    @staticmethod
+    def from_views(v: inputs.Views, device="cuda") -> "PoseSet":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        return PoseSet(rot=t(v.rot), shift=t(v.shift), shift_px=t(v.shift / v.pixel),
+                       defocus=t(v.defocus_u), zeros=t(np.zeros(len(v.rot))), D=v.D,
+                       pixel=v.pixel)
+
+    def __len__(self):
+        return self.rot.shape[0]
+
+    def ctf(self, a: int, b: int) -> binding.Ctf:
+        return binding.Ctf(defocus_u=self.defocus[a:b], defocus_v=self.defocus[a:b],
+                           astig=self.zeros[a:b], phase=self.zeros[a:b])
+
+
+def mixture_on_device(g: inputs.Mixture, device="cuda"):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+    return dict(means=t(g.means), log_scales=t(g.log_scales), quats=t(g.quats), amps=t(g.amps))
+
+
+def render_particles(lib, gd, ps: PoseSet, a: int, b: int, snr_db: float, seed: int,
+                     out: Optional[torch.Tensor] = None, noise_offset: int = 0):
+    """Noisy CTF-modulated particle images a..b-1 (noise counter a + noise_offset)."""
+    imgs = lib.render(**gd, rot=ps.rot[a:b], shift=ps.shift[a:b], D=ps.D, pixel=ps.pixel,
+                      ctf=ps.ctf(a, b), out=out)
+    lib.add_noise(imgs, snr_db, seed, offset=a + noise_offset)
+    return imgs
+
+
+def train(lib, net: binding.Network, gd, ps: PoseSet, *, epochs: int, batch: int, lr: float,
+          gamma: float = 0.7, lam: float = 0.1, snr_db: float = -20.0, seed: int = 1,
+          matched_filter: bool = True, log=None) -> List[Tuple[int, float]]:
+    """Train on ps (re-rendered with fresh noise every epoch); returns (step, loss) samples.
+
+    With matched_filter the network sees Z = H Y, each particle filtered by
+    its own CTF (the same Z the pose scores correlate with)."""
+    n = len(ps)
+    buf = torch.empty(batch, ps.D, ps.D, device=ps.rot.device)
+    loss = torch.empty(1, device=ps.rot.device)
+    hist, step = [], 0
+    for ep in range(epochs):
+        lr_ep = lr * gamma ** ep
+        for a in range(0, n - batch + 1, batch):
+            b = a + batch
+            render_particles(lib, gd, ps, a, b, snr_db, seed, out=buf, noise_offset=ep * n)
+            if matched_filter:
+                lib.ctf_filter(buf, ps.ctf(a, b), ps.pixel, out=buf)
+            net.train_step(buf, ps.rot[a:b], ps.shift_px[a:b], lam=lam, lr=lr_ep, loss=loss)
+            step += 1
+            if step % 50 == 0:
+                hist.append((step, float(loss.item())))
+                if log:
+                    log(f"epoch {ep} step {step} loss {hist[-1][1]:.4f}")
+    return hist
+
+
+def angular_error_deg(R_est: torch.Tensor, R_true: torch.Tensor) -> np.ndarray:
+    """Rotation angle between estimated and true world-to-view rotations."""
+    tr = torch.einsum("bji,bji->b", R_est.double(), R_true.double())
+    return torch.rad2deg(torch.arccos(torch.clamp((tr - 1) / 2, -1, 1))).cpu().numpy()
+
+
+@dataclasses.dataclass
+class Stage:
+    bank: binding.PoseBank
+    n_dir: int
+    n_psi_c: int
+
+
+def learned_poses(lib, net: binding.Network, batch: binding.PoseBatch, images, ctf: binding.Ctf,
+                  stages: Sequence[Stage], rots: Sequence[torch.Tensor], zbuf: torch.Tensor,
+                  matched_filter: bool = True):
+    """Prepare the particles once, network proposal (on Z = H Y with
+    matched_filter), then the refinement stages on the prepared batch.
+    Returns (rot [P][3][3], shift index [P], proposal [P][3][3])."""
+    batch.load(images, ctf, filtered=zbuf if matched_filter else None)
+    W0, _, _ = net.forward(zbuf if matched_filter else images)
+    W, out = W0, None
+    for i, st in enumerate(stages):
+        out = batch.refine(st.bank, proposal=W, n_dir=st.n_dir, n_psi_c=st.n_psi_c)
+        W = rots[i][out["rot_idx"].long()].contiguous()
+    return W, (out["shift_idx"] if out is not None else None), W0
+
+
+def grid_poses(batch: binding.PoseBatch, bank: binding.PoseBank, images, ctf: binding.Ctf,
+               rot: torch.Tensor):
+    """Exhaustive search of one bank: (rot [P][3][3], shift index [P])."""
+    batch.load(images, ctf)
+    out = batch.search(bank)
+    return rot[out["rot_idx"].long()].contiguous(), out["shift_idx"]
+
+
+def timed(fn, reps: int = 3):
+    """(result, median seconds) of a GPU call sequence."""
+    res, ts = None, []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return res, float(np.median(ts))
+
+
+def literal_grid_search(lib, gd, image, ctf_one: binding.Ctf, grid_rot: torch.Tensor, D: int,
+                        pixel: float, shift_radius: int = 2, chunk: int = 4608):
+    """Reference: render every (rotation, shift) candidate with the particle's
+    CTF and score it by the library's squared-error loss (no shared templates).
+    Returns (best rotation index, best shift index, best score)."""
+    K = grid_rot.shape[0]
+    side = 2 * shift_radius + 1
+    best = (None, None, float("inf"))
+    obs = image.expand(chunk, D, D).contiguous()
+    rep = lambda t: t.expand(chunk).contiguous()
+    ctf = binding.Ctf(defocus_u=rep(ctf_one.defocus_u), defocus_v=rep(ctf_one.defocus_v),
+                      astig=rep(ctf_one.astig), phase=rep(ctf_one.phase))
+    shift = torch.empty(chunk, 2, device=image.device)
+    for s in range(side * side):
+        dx, dy = s % side - shift_radius, s // side - shift_radius
+        shift[:, 0], shift[:, 1] = dx * pixel, dy * pixel
+        for k0 in range(0, K, chunk):
+            kc = min(chunk, K - k0)
+            c = ctf if kc == chunk else binding.Ctf(
+                defocus_u=ctf.defocus_u[:kc], defocus_v=ctf.defocus_v[:kc],
+                astig=ctf.astig[:kc], phase=ctf.phase[:kc])
+            loss, _, _ = lib.loss_and_grad(**gd, rot=grid_rot[k0:k0 + kc].contiguous(),
+                                           shift=shift[:kc].contiguous(), D=D, pixel=pixel,
+                                           observed=obs[:kc], ctf=c, want_grads=False)
+            v, i = torch.min(loss[:kc], dim=0)
+            if float(v) < best[2]:
+                best = (k0 + int(i), s, float(v))
+    return best
+
+
+def run_c5(lib, *, n_train=200000, n_test=2048, epochs=4, batch=256, lr=1e-3, gamma=0.7,
+           lam=0.1, snr_db=-20.0, seed=5, coarse=(4, 24), fine=(8, 48), shift_radius=2,
+           stages=((0, 4, 3), (1, 6, 3)), matched_filter=True, chunk=2048,
+           literal_particles=2, log=print):
+    """The learned-pose experiment: returns angular errors and throughputs.
+
+    stages: (bank 0 = coarse / 1 = fine, n_dir, n_psi_c) per refinement stage.
+    Both paths are timed from particle images in device memory to poses,
+    particle preparation (CTF filtering, shifted copies) included."""
+    dev = torch.device("cuda")
+    g, tr, te = inputs.c5(seed, n_train, n_test)
+    gd = mixture_on_device(g)
+    ps_tr, ps_te = PoseSet.from_views(tr), PoseSet.from_views(te)
+    D, pixel = ps_te.D, ps_te.pixel
+    res = {"n_train": n_train, "n_test": n_test, "D": D, "pixel": pixel, "N": int(len(g.amps)),
+           "snr_db": snr_db, "shift_radius": shift_radius, "matched_filter": matched_filter}
+    rots = [torch.from_numpy(lib.pose_grid(*coarse)).to(dev),
+            torch.from_numpy(lib.pose_grid(*fine)).to(dev)]
+    t0 = time.perf_counter()
+    banks = [lib.pose_bank(**gd, rot=rots[0], n_psi=coarse[1], D=D, pixel=pixel),
+             lib.pose_bank(**gd, rot=rots[1], n_psi=fine[1], D=D, pixel=pixel)]
+    torch.cuda.synchronize()
+    res["bank_build_s"] = time.perf_counter() - t0
+    res["bank_sizes"] = [int(r.shape[0]) for r in rots]
+    imgs = render_particles(lib, gd, ps_te, 0, n_test, snr_db, seed + 1000)
+    chunk = min(chunk, n_test)
+    pb = lib.pose_batch(D, pixel, chunk, shift_radius)
+    zbuf = torch.empty(chunk, D, D, device=dev)
+
+    def grid_all():
+        return torch.cat([grid_poses(pb, banks[0], imgs[a:min(n_test, a + chunk)],
+                                     ps_te.ctf(a, min(n_test, a + chunk)), rots[0])[0]
+                          for a in range(0, n_test, chunk)])
+
+    W_gs, t_gs = timed(grid_all)
+    err_gs = angular_error_deg(W_gs, ps_te.rot)
+    res["grid_search"] = {"median_deg": float(np.median(err_gs)), "mean_deg": float(err_gs.mean()),
+                          "images_per_s": n_test / t_gs, "seconds": t_gs}
+    log(f"grid search: median {np.median(err_gs):.2f} deg, {n_test / t_gs:.0f} img/s")
+    st = [Stage(banks[b], nd, npc) for b, nd, npc in stages]
+    st_rots = [rots[b] for b, _, _ in stages]
+    net = lib.network(D, max_batch=max(batch, chunk), seed=seed)
+
+    def learned():
+        Ws, W0s = [], []
+        for a in range(0, n_test, chunk):
+            b = min(n_test, a + chunk)
+            W, _, W0 = learned_poses(lib, net, pb, imgs[a:b], ps_te.ctf(a, b), st, st_rots,
+                                     zbuf[:b - a], matched_filter)
+            Ws.append(W)
+            W0s.append(W0)
+        return torch.cat(Ws), torch.cat(W0s)
+
+    W_u, W0_u = learned()
+    err_u = angular_error_deg(W_u, ps_te.rot)
+    err_pu = angular_error_deg(W0_u, ps_te.rot)
+    res["untrained"] = {"median_deg": float(np.median(err_u)),
+                        "proposal_median_deg": float(np.median(err_pu))}
+    log(f"untrained: proposal {np.median(err_pu):.1f} deg, refined {np.median(err_u):.1f} deg")
+    t0 = time.perf_counter()
+    hist = train(lib, net, gd, ps_tr, epochs=epochs, batch=batch, lr=lr, gamma=gamma, lam=lam,
+                 snr_db=snr_db, seed=seed, matched_filter=matched_filter, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res["training"] = {"epochs": epochs, "batch": batch,
+                       "steps": len(range(0, n_train - batch + 1, batch)) * epochs,
+                       "seconds": t_train, "images_per_s": epochs * n_train / t_train,
+                       "loss_first": hist[0][1] if hist else None,
+                       "loss_last": hist[-1][1] if hist else None}
+    (W_t, W0_t), t_l = timed(learned)
+    err_t = angular_error_deg(W_t, ps_te.rot)
+    err_pt = angular_error_deg(W0_t, ps_te.rot)
+    res["learned"] = {"median_deg": float(np.median(err_t)), "mean_deg": float(err_t.mean()),
+                      "proposal_median_deg": float(np.median(err_pt)),
+                      "images_per_s": n_test / t_l, "seconds": t_l,
+                      "stages": [list(s) for s in stages]}
+    log(f"learned: proposal {np.median(err_pt):.1f} deg, refined {np.median(err_t):.2f} deg, "
+        f"{n_test / t_l:.0f} img/s")
+    res["speedup_vs_grid_search"] = t_gs / t_l
+    res["reaches_grid_search_error"] = bool(np.median(err_t) <= np.median(err_gs))
+    if literal_particles > 0:
+        t0 = time.perf_counter()
+        for p in range(literal_particles):
+            literal_grid_search(lib, gd, imgs[p], ps_te.ctf(p, p + 1), rots[0], D, pixel,
+                                shift_radius)
+        torch.cuda.synchronize()
+        t_lit = (time.perf_counter() - t0) / literal_particles
+        res["literal_grid_search_images_per_s"] = 1.0 / t_lit
+        res["speedup_vs_literal_grid_search"] = (n_test / t_l) * t_lit
+    for b in banks:
+        b.close()
+    pb.close()
+    net.close()
+    return res

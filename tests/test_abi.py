@@ -16,7 +16,7 @@ LIB = os.path.join(ROOT, "paper_2508_04929_amd", "libcryosplat.so")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(cs_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(cs_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_entry_points():
