@@ -285,8 +285,8 @@ int cs_cnn_tensor(cs_cnn *net, int32_t index, int32_t grad, uint16_t *dst, int64
 /* Single layers of the network (BF16 tensors passed as raw uint16 bits).
  * conv: in NHWC [B][H][W][Cin], out [B][H/2][W/2][Cout], w [Cout][3][3][Cin],
  * bias [Cout] FP32 (may be NULL), padding 1, stride 2; H, W even; Cout a
- * multiple of 8; Cin a multiple of 8, or Cin = 1 (H = W) for the first
- * layer.  out_f32 (may be NULL) receives the FP32 values before rounding.
+ * multiple of 8; Cin a multiple of 8, or Cin = 1 (H = W, Cout <= 256) for
+ * the first layer.  out_f32 (may be NULL) receives the FP32 values before rounding.
  * dgrad: din = conv^T(dout) with wt = w transposed to [Cin][3][3][Cout],
  * zeroed where act_in <= 0 (act_in may be NULL: no mask); Cin % 8 == 0.
  * wgrad: dw [Cout][3][3][Cin] FP32 = sum over batch and pixels. */
@@ -391,7 +391,7 @@ int cs_pose_refine(cs_pose_bank *bank, const float *images, const cs_ctf *ctf, i
  * the energy weights w_f |H^|^2 / D^2 (bfloat16) and ||Y||^2.
  * create: capacity particles of side D (multiple of 16, prime factors 2
  * and 3, <= 512), shift radius 0 <= r <= 4; device memory about
- * capacity * D^2 * (2 (2r+1)^2 + 16) bytes.  load: P <= capacity images
+ * capacity * D^2 * (2 (2r+1)^2 + 18) bytes.  load: P <= capacity images
  * [P][D][D] with per-particle CTF parameters (ctf NULL = no CTF); filtered
  * (may be NULL) receives Z [P][D][D] FP32.  A batch is reused by later
  * loads; searches use the last load. */

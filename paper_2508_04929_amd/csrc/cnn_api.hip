@@ -326,7 +326,8 @@ int cs_bf16_conv3x3s2_forward(cs_ctx *ctx, const uint16_t *in, const uint16_t *w
   if (!in || !w || !out || B < 1 || H < 2 || W < 2 || H % 2 || W % 2 || Cout % 8 ||
       (Cin != 1 && Cin % 8))
     return fail(ctx, CS_ERR_INVALID_ARG, "bad conv forward arguments");
-  if (Cin == 1 && H != W) return fail(ctx, CS_ERR_INVALID_ARG, "first-layer conv needs H == W");
+  if (Cin == 1 && (H != W || Cout > 256))
+    return fail(ctx, CS_ERR_INVALID_ARG, "first-layer conv needs H == W and Cout <= 256");
   HIPCHK(hipSetDevice(ctx->device));
   HIPCHK(conv_fwd((const bf16 *)in, (const bf16 *)w, bias, B, H, W, Cin, Cout, relu, (bf16 *)out,
                   out_f32, (hipStream_t)stream));

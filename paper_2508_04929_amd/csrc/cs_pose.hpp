@@ -31,8 +31,27 @@ struct PoseGemmArgs {
   float *scores = nullptr;             // optional [P][N][S]
 };
 
-hipError_t pose_prep(const float *Y, const float *Z, const float *table, int P, int D, int r,
-                     int F8, unsigned short *zs, unsigned short *w, float *yy, hipStream_t st);
+// Gathered refinement with the particle in LDS (k_pose_refine_z).
+struct PoseRefineArgs {
+  const unsigned short *zb = nullptr;    // [P][D][D+16] bfloat16 -2 Z, wrap-padded rows
+  const unsigned short *w = nullptr;     // [P][F8] energy weights
+  const unsigned short *bank = nullptr;  // rows of ldb elements: D^2 pixels, then F8 spectrum
+  int64_t ldb = 0;
+  const int *cand = nullptr;             // [P][L] bank rows (out of [0, nrows): skipped)
+  int L = 0;
+  int64_t nrows = 0;
+  int D = 0, r = 0, S = 1, F8 = 0, npx = 0;
+  const float *yy = nullptr;
+  unsigned long long *best = nullptr;
+  float *scores = nullptr;               // optional [P][L][S]
+};
+
+hipError_t pose_prep(const float *Y, const float *Z, const float *table, int P, int D, int F8,
+                     unsigned short *zb, unsigned short *w, float *yy, hipStream_t st);
+hipError_t pose_shifts(const unsigned short *zb, int P, int D, int r, unsigned short *zs,
+                       hipStream_t st);
+hipError_t pose_refine_z(const PoseRefineArgs &a, int P, hipStream_t st);
+size_t pose_refine_z_lds(int D, int F8);
 hipError_t rows_to_bf16(const float *src, int64_t rows, int len, unsigned short *dst, int64_t ld,
                         hipStream_t st);
 hipError_t fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);

@@ -24,12 +24,7 @@ __device__ __forceinline__ bf16 f2bf(float x) {
   return (bf16)(u >> 16);
 }
 
-constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // LDS rows padded to 80 bytes
-
-struct GemmTiles {
-  bf16 a[BM][LDK];
-  bf16 b[BN][LDK];
-};
+constexpr int BK = 32, LDK = BK + 8;  // LDS rows padded to 80 bytes
 
 union Vec8 {
   uint4 u;
@@ -46,84 +41,102 @@ union Vec8 {
 // register (prefetched while the previous step computes), then stores them
 // into the LDS tile (non-transposed: 8 consecutive k of one row; transposed:
 // 8 consecutive rows of one k, scattered into 8 rows).
-template <class Op>
-__device__ __forceinline__ uint4 fetch_tile(const Op &op, bool isA, int r0, int k0, int R,
+template <class Op, int TB>
+__device__ __forceinline__ uint4 fetch_tile(const Op &op, bool isA, int idx, int r0, int k0, int R,
                                             int Kend) {
-  const int t = threadIdx.x;
   const bool trans = isA ? Op::kATrans : Op::kBTrans;
   uint4 v = make_uint4(0, 0, 0, 0);
   if (!trans) {
-    const int r = r0 + (t >> 2), k = k0 + (t & 3) * 8;
+    const int r = r0 + (idx >> 2), k = k0 + (idx & 3) * 8;
     if (r < R && k < Kend) v = isA ? op.a_vec(r, k) : op.b_vec(r, k);
   } else {
-    const int r = r0 + (t & 7) * 8, k = k0 + (t >> 3);
+    const int r = r0 + (idx % (TB / 8)) * 8, k = k0 + idx / (TB / 8);
     if (r < R && k < Kend) v = isA ? op.a_vecT(r, k) : op.b_vecT(r, k);
   }
   return v;
 }
 
-template <class Op>
-__device__ __forceinline__ void put_tile(bool isA, bf16 (*tile)[LDK], uint4 v) {
-  const int t = threadIdx.x;
+template <class Op, int TB>
+__device__ __forceinline__ void put_tile(bool isA, bf16 (*tile)[LDK], int idx, uint4 v) {
   const bool trans = isA ? Op::kATrans : Op::kBTrans;
   if (!trans) {
-    *(uint4 *)&tile[t >> 2][(t & 3) * 8] = v;
+    *(uint4 *)&tile[idx >> 2][(idx & 3) * 8] = v;
   } else {
     Vec8 u;
     u.u = v;
-    const int kk = t >> 3, rq = (t & 7) * 8;
+    const int kk = idx / (TB / 8), rq = (idx % (TB / 8)) * 8;
 #pragma unroll
     for (int i = 0; i < 8; ++i) tile[rq + i][kk] = u.h[i];
   }
 }
 
-template <class Op>
+// TBM x TBN block tile, four waves in 2 x 2, each wave (TBM/2) x (TBN/2) as
+// 16 x 16 MFMA tiles; K steps of 32 double-buffered through LDS (operands
+// prefetched into registers while the current step computes).  The tile
+// shape changes only the partition: every output accumulates its K steps in
+// the same order, so results do not depend on it.
+template <class Op, int TBM, int TBN>
 __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kchunk) {
-  __shared__ GemmTiles T[2];
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  constexpr int TI = TBM / 32, TJ = TBN / 32;
+  constexpr int NA = TBM * BK / 8 / 256, NB = TBN * BK / 8 / 256;
+  static_assert(NA >= 1 && NB >= 1, "tile");
+  __shared__ bf16 sA[2][TBM][LDK];
+  __shared__ bf16 sB[2][TBN][LDK];
+  const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  f32x4 acc[2][2];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * (TBM / 2), wn = (w & 1) * (TBN / 2);
+  f32x4 acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  uint4 ra = fetch_tile(op, true, m0, kb, M, ke);
-  uint4 rb = fetch_tile(op, false, n0, kb, N, ke);
-  put_tile<Op>(true, T[0].a, ra);
-  put_tile<Op>(false, T[0].b, rb);
+    for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra[NA], rb[NB];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) ra[q] = fetch_tile<Op, TBM>(op, true, tid + 256 * q, m0, kb, M, ke);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) rb[q] = fetch_tile<Op, TBN>(op, false, tid + 256 * q, n0, kb, N, ke);
+#pragma unroll
+  for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[0], tid + 256 * q, ra[q]);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[0], tid + 256 * q, rb[q]);
   __syncthreads();
   int cur = 0;
   for (int k0 = kb; k0 < ke; k0 += BK) {
     const bool more = k0 + BK < ke;
     if (more) {
-      ra = fetch_tile(op, true, m0, k0 + BK, M, ke);
-      rb = fetch_tile(op, false, n0, k0 + BK, N, ke);
+#pragma unroll
+      for (int q = 0; q < NA; ++q)
+        ra[q] = fetch_tile<Op, TBM>(op, true, tid + 256 * q, m0, k0 + BK, M, ke);
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+        rb[q] = fetch_tile<Op, TBN>(op, false, tid + 256 * q, n0, k0 + BK, N, ke);
     }
-    bf16x8 af[2], bv[2];
+    bf16x8 af[TI], bv[TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-      af[i] = *(const bf16x8 *)&T[cur].a[wm + i * 16 + (lane & 15)][(lane >> 4) * 8];
+    for (int i = 0; i < TI; ++i)
+      af[i] = *(const bf16x8 *)&sA[cur][wm + i * 16 + (lane & 15)][(lane >> 4) * 8];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      bv[j] = *(const bf16x8 *)&T[cur].b[wn + j * 16 + (lane & 15)][(lane >> 4) * 8];
+    for (int j = 0; j < TJ; ++j)
+      bv[j] = *(const bf16x8 *)&sB[cur][wn + j * 16 + (lane & 15)][(lane >> 4) * 8];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < TJ; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bv[j], acc[i][j], 0, 0, 0);
     if (more) {
-      put_tile<Op>(true, T[cur ^ 1].a, ra);
-      put_tile<Op>(false, T[cur ^ 1].b, rb);
+#pragma unroll
+      for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[cur ^ 1], tid + 256 * q, ra[q]);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[cur ^ 1], tid + 256 * q, rb[q]);
     }
     __syncthreads();
     cur ^= 1;
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
@@ -317,6 +330,10 @@ __global__ void k_sum_into(const float *part, int n, float *out) {
 __global__ void __launch_bounds__(256)
 k_conv1_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int Hi, int Wi, int Cout,
             int relu, bf16 *out, float *out32) {
+  __shared__ float ws[256 * 9 + 256];  // weights [Cout][9] and biases (Cout <= 256)
+  for (int q = threadIdx.x; q < Cout * 9; q += 256) ws[q] = bf2f(w[q]);
+  for (int q = threadIdx.x; q < Cout; q += 256) ws[Cout * 9 + q] = bias ? bias[q] : 0.f;
+  __syncthreads();
   const int Ho = Hi / 2, Wo = Wi / 2;
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= (int64_t)B * Ho * Wo) return;
@@ -333,9 +350,9 @@ k_conv1_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int Hi, int
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int co = c0 + e;
-      float s = bias ? bias[co] : 0.f;
+      float s = ws[Cout * 9 + co];
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap) s += bf2f(w[co * 9 + tap]) * x[tap];
+      for (int tap = 0; tap < 9; ++tap) s = __fmaf_rn(ws[co * 9 + tap], x[tap], s);
       if (relu) s = fmaxf(s, 0.f);
       if (out32) out32[p * Cout + co] = s;
       o.h[e] = f2bf(s);
@@ -545,13 +562,22 @@ static hipError_t launch_gemm(const Op &op, int M, int N, int K, int splits, hip
     kchunk = (kchunk + BK - 1) / BK * BK;
     splits = (K + kchunk - 1) / kchunk;
   }
-  hipLaunchKernelGGL(k_gemm<Op>, dim3(cdiv_(M, BM), cdiv_(N, BN), splits), dim3(256), 0, st, op,
-                     M, N, K, kchunk);
+  // larger tiles where there are enough of them to fill the chip
+  if (splits == 1 && M >= 16384 && N >= 128) {
+    hipLaunchKernelGGL((k_gemm<Op, 128, 128>), dim3(cdiv_(M, 128), cdiv_(N, 128), 1), dim3(256), 0,
+                       st, op, M, N, K, kchunk);
+  } else if (splits == 1 && M >= 16384 && N >= 64) {
+    hipLaunchKernelGGL((k_gemm<Op, 128, 64>), dim3(cdiv_(M, 128), cdiv_(N, 64), 1), dim3(256), 0,
+                       st, op, M, N, K, kchunk);
+  } else {
+    hipLaunchKernelGGL((k_gemm<Op, 64, 64>), dim3(cdiv_(M, 64), cdiv_(N, 64), splits), dim3(256), 0,
+                       st, op, M, N, K, kchunk);
+  }
   return hipGetLastError();
 }
 
 int wgrad_splits(int M, int N, int K) {
-  const int tiles = (int)(cdiv_(M, BM) * cdiv_(N, BN));
+  const int tiles = (int)(cdiv_(M, 64) * cdiv_(N, 64));
   int s = (512 + tiles - 1) / tiles;
   s = std::max(1, std::min(s, K / BK));
   return s;

@@ -139,9 +139,13 @@ __device__ double ctf_at(double sx, double sy, const CtfDev &c, double du, doubl
     df += 0.5 * (du - dv) * (cos2 * c2a + sin2 * s2a);
   }
   const double chi = M_PI * c.lam * df * s2 - 0.5 * M_PI * c.cs * c.lam * c.lam * c.lam * s2 * s2 - ph;
-  double sn, cs;
-  sincos(chi, &sn, &cs);
-  double h = -(sqrt(1.0 - c.w * c.w) * sn + c.w * cs);
+  // phase in FP64, reduced to [-pi, pi] in FP64, then one FP32 sincos (about
+  // 1e-7 absolute in the CTF)
+  const double turns = chi * (0.5 / M_PI);
+  const float red = (float)((turns - rint(turns)) * (2.0 * M_PI));
+  float sn, cs;
+  sincosf(red, &sn, &cs);
+  double h = -(sqrt(1.0 - c.w * c.w) * (double)sn + c.w * (double)cs);
   if (c.bfactor != 0.0) h *= exp(-0.25 * c.bfactor * s2);
   return h;
 }
@@ -150,7 +154,9 @@ __device__ float ctf_grid_value(int ky, int kx, int L, float pixel, const CtfDev
   const double du = c.defocus_u[b], dv = c.defocus_v[b];
   const double a = c.astig ? (double)c.astig[b] : 0.0;
   const double ph = c.phase ? (double)c.phase[b] : 0.0;
-  const double c2a = cos(2.0 * a), s2a = sin(2.0 * a);
+  float s2f, c2f;
+  sincosf((float)(2.0 * a), &s2f, &c2f);
+  const double c2a = c2f, s2a = s2f;
   const int half = L / 2;
   const double inv = 1.0 / ((double)L * (double)pixel);
   const int fkx = (kx < (L + 1) / 2) ? kx : kx - L;

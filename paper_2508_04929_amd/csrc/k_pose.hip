@@ -12,6 +12,8 @@
 // per-particle rows and per-rotation rows, done here as BF16 MFMA GEMMs with
 // FP32 accumulation; the energy term is a GEMM of its own for the full
 // grid and is fused into the K dimension for gathered candidate lists.
+#include <algorithm>
+
 #include "cs_pose.hpp"
 
 namespace cs {
@@ -39,7 +41,8 @@ __device__ __forceinline__ float ord_float(unsigned o) {
 
 // ---------------------------------------------------------------------------
 // Particle preparation.
-//   k_pose_shifts  (block = (particle, shift s)):
+//   k_pose_zpad    (block = particle): -2 Z as bfloat16 rows with wrap padding
+//   k_pose_shifts  (block = (particle, shift s)), from the padded rows:
 //     zs[p][s][i][j] = -2 Z[p][(i - dy) mod D][(j + dx) mod D]   (bfloat16)
 //     shift s = (dy + r)(2r + 1) + (dx + r); 8 outputs (16 bytes) per lane
 //   k_pose_weights (block = particle):
@@ -47,12 +50,39 @@ __device__ __forceinline__ float ord_float(unsigned o) {
 //     yy[p]   = sum Y^2
 // where Z = H Y and table = H^ / D^2 (the CTF table of the FFT kernels).
 // ---------------------------------------------------------------------------
+// 8 consecutive bfloat16 starting at element c of a dword-aligned row.
+__device__ __forceinline__ uint4 load8_at(const unsigned *row, int c) {
+  const int d = c >> 1;
+  const unsigned w0 = row[d], w1 = row[d + 1], w2 = row[d + 2], w3 = row[d + 3], w4 = row[d + 4];
+  if (c & 1)
+    return make_uint4(__builtin_amdgcn_alignbit(w1, w0, 16), __builtin_amdgcn_alignbit(w2, w1, 16),
+                      __builtin_amdgcn_alignbit(w3, w2, 16), __builtin_amdgcn_alignbit(w4, w3, 16));
+  return make_uint4(w0, w1, w2, w3);
+}
+
+// zb[p][i][t] = bfloat16(-2 Z[p][i][(t - 8) mod D]), rows of D + 16 (8 columns
+// of wrap-around on each side), so that a shift |dx| <= 4 is a plain offset.
 __global__ void __launch_bounds__(256)
-k_pose_shifts(const float *Z, int D, int r, unsigned short *zs) {
+k_pose_zpad(const float *Z, int D, unsigned short *zb) {
+  const int p = blockIdx.x, RS = D + 16;
+  const float *z = Z + (size_t)p * D * D;
+  unsigned short *o = zb + (size_t)p * D * RS;
+  for (int e = threadIdx.x; e < D * RS; e += 256) {
+    const int i = e / RS, t = e - i * RS;
+    int c = t - 8;
+    c += (c < 0) ? D : 0;
+    c -= (c >= D) ? D : 0;
+    o[e] = pf2bf(-2.f * z[(size_t)i * D + c]);
+  }
+}
+
+// zs[p][s][i][j] = zb[p][(i - dy) mod D][j + dx + 8]  (block = (particle, shift))
+__global__ void __launch_bounds__(256)
+k_pose_shifts(const unsigned short *zb, int D, int r, unsigned short *zs) {
   const int p = blockIdx.x, s = blockIdx.y;
-  const int side = 2 * r + 1, S = side * side, npx = D * D;
+  const int side = 2 * r + 1, S = side * side, npx = D * D, RS = D + 16;
   const int dy = s / side - r, dx = s % side - r;
-  const float *z = Z + (size_t)p * npx;
+  const unsigned short *zp = zb + (size_t)p * D * RS;
   uint4 *o = (uint4 *)(zs + ((size_t)p * S + s) * npx);
   const int per_row = D / 8;
   for (int v = threadIdx.x; v < npx / 8; v += 256) {
@@ -60,17 +90,7 @@ k_pose_shifts(const float *Z, int D, int r, unsigned short *zs) {
     int si = i - dy;
     si += (si < 0) ? D : 0;
     si -= (si >= D) ? D : 0;
-    const float *zr = z + (size_t)si * D;
-    unsigned short h[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      int sj = j0 + e + dx;
-      sj += (sj < 0) ? D : 0;
-      sj -= (sj >= D) ? D : 0;
-      h[e] = pf2bf(-2.f * zr[sj]);
-    }
-    o[v] = make_uint4(h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16),
-                      h[4] | ((unsigned)h[5] << 16), h[6] | ((unsigned)h[7] << 16));
+    o[v] = load8_at((const unsigned *)(zp + (size_t)si * RS), j0 + dx + 8);
   }
 }
 
@@ -337,6 +357,150 @@ __global__ void __launch_bounds__(256) k_pose_gemm(PoseGemmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Gathered refinement with the particle resident in LDS (block = particle x
+// 64 candidates, one wave per 16 candidates).  K runs over the bank row:
+// D^2 pixels, then the power spectrum.  MFMA A rows are the shifts s; their
+// pixel fragments are assembled from the padded -2 Z rows in LDS (a shift is
+// a row / column offset), their spectrum fragments are the particle's energy
+// weights (equal for every shift).  B fragments are 16 bytes per lane straight
+// from the gathered bank row into registers, PF slices ahead; waves never
+// synchronise after the LDS fill.  Value = acc + ||Y||^2; 64-bit atomicMin of
+// (score, bank row x S + s) per particle.
+// ---------------------------------------------------------------------------
+template <int PF, int KSPLIT>
+__global__ void __launch_bounds__(256) k_pose_refine_z(PoseRefineArgs a) {
+  extern __shared__ unsigned lz[];
+  constexpr int NG = 4 / KSPLIT;  // candidate groups of 16 per block
+  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int cg = wv / KSPLIT, kp = wv % KSPLIT;
+  const int D = a.D, RS = D + 16;
+  const int zdw = D * RS / 2, wdw = a.F8 / 2;
+  const uint4 *gz = (const uint4 *)(a.zb + (size_t)p * D * RS);
+  for (int q = tid; q < zdw / 4; q += 256) ((uint4 *)lz)[q] = gz[q];
+  const uint4 *gw = (const uint4 *)(a.w + (size_t)p * a.F8);
+  for (int q = tid; q < wdw / 4; q += 256) ((uint4 *)(lz + zdw))[q] = gw[q];
+  __syncthreads();
+
+  const int n = blockIdx.y * (16 * NG) + cg * 16 + (lane & 15);
+  int64_t brow = -1;
+  if (n < a.L) {
+    brow = a.cand[(int64_t)p * a.L + n];
+    if (brow < 0 || brow >= a.nrows) brow = -1;
+  }
+  const int kq = (lane >> 4) * 8;
+  const unsigned short *bp = a.bank + (brow < 0 ? 0 : brow * a.ldb) + kq;
+  const int side = 2 * a.r + 1;
+  int dx[2], dy[2];
+  bool rv[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const int s = f * 16 + (lane & 15);
+    rv[f] = s < a.S;
+    dy[f] = rv[f] ? s / side - a.r : 0;
+    dx[f] = rv[f] ? s % side - a.r : 0;
+  }
+  const int nsl_all = (a.npx + a.F8) / 32, npsl = a.npx / 32;
+  // this wave's part of the K slices
+  const int ks0 = (int)((int64_t)nsl_all * kp / KSPLIT), ks1 = (int)((int64_t)nsl_all * (kp + 1) / KSPLIT);
+  const uint4 zero = make_uint4(0, 0, 0, 0);
+  uint4 q[PF];
+#pragma unroll
+  for (int u = 0; u < PF; ++u)
+    q[u] = (brow >= 0 && ks0 + u < ks1) ? *(const uint4 *)(bp + (size_t)(ks0 + u) * 32) : zero;
+  f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
+  const int e0 = ks0 * 32 + kq;
+  int i = e0 / D, j = e0 - (e0 / D) * D;  // image row / column of this lane's 8 pixels
+  for (int k0 = ks0; k0 < ks1; k0 += PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int ks = k0 + u;
+      if (ks < ks1) {
+        const uint4 b = q[u];
+        if (ks + PF < ks1) q[u] = (brow >= 0) ? *(const uint4 *)(bp + (size_t)(ks + PF) * 32) : zero;
+        uint4 av[2];
+        if (ks < npsl) {
+#pragma unroll
+          for (int f = 0; f < 2; ++f) {
+            av[f] = zero;
+            if (rv[f]) {
+              int si = i - dy[f];
+              si += (si < 0) ? D : 0;
+              si -= (si >= D) ? D : 0;
+              av[f] = load8_at(lz + (size_t)si * (RS / 2), j + dx[f] + 8);
+            }
+          }
+          j += 32;
+          while (j >= D) {
+            j -= D;
+            ++i;
+          }
+        } else {
+          const int e2 = (ks - npsl) * 32 + kq;
+          av[0] = av[1] = ((const uint4 *)(lz + zdw))[e2 >> 3];
+        }
+        bf16x8_t bb, a0, a1;
+        __builtin_memcpy(&bb, &b, 16);
+        __builtin_memcpy(&a0, &av[0], 16);
+        __builtin_memcpy(&a1, &av[1], 16);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb, acc[1], 0, 0, 0);
+      }
+    }
+  }
+  if (KSPLIT > 1) {
+    // partial sums of the K parts, added in part order (deterministic); the
+    // particle's LDS rows are no longer read after this barrier
+    __syncthreads();
+    float *red = (float *)lz;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[((wv * 2 + f) * 4 + r) * 64 + lane] = acc[f][r];
+    __syncthreads();
+    if (kp != 0) return;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = 0.f;
+        for (int t = 0; t < KSPLIT; ++t) v += red[(((cg * KSPLIT + t) * 2 + f) * 4 + r) * 64 + lane];
+        acc[f][r] = v;
+      }
+  }
+  // acc[f][r] = C[shift f*16 + 4*(lane/16) + r][candidate lane % 16]
+  unsigned long long key = ~0ull;
+  if (brow >= 0) {
+    const float base = a.yy[p];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int s = f * 16 + (lane >> 4) * 4 + r;
+        if (s < a.S) {
+          const float v = acc[f][r] + base;
+          if (a.scores) a.scores[((int64_t)p * a.L + n) * a.S + s] = v;
+          const unsigned long long k2 =
+              ((unsigned long long)ord_bits(v) << 32) | (unsigned)(brow * a.S + s);
+          key = k2 < key ? k2 : key;
+        }
+      }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned lo = __shfl_xor((unsigned)(key & 0xffffffffu), o, 64);
+    const unsigned hi = __shfl_xor((unsigned)(key >> 32), o, 64);
+    const unsigned long long k2 = ((unsigned long long)hi << 32) | lo;
+    key = k2 < key ? k2 : key;
+  }
+  if (lane == 0 && key != ~0ull) atomicMin(a.best + p, key);
+}
+
+size_t pose_refine_z_lds(int D, int F8) {
+  // particle rows + energy weights; the K-split reduction (8 KiB) reuses them
+  return std::max<size_t>((size_t)D * (D + 16) * 2 + (size_t)F8 * 2, 8192);
+}
+
+// ---------------------------------------------------------------------------
 // Refinement candidates (one wave per particle): the n_dir bank directions
 // nearest the proposal's viewing direction (third row of the proposal W),
 // and for each the n_psi_c in-plane indices around the angle psi* that
@@ -395,11 +559,26 @@ k_pose_candidates(const float *prop, int P, const float *bank_rot, int ndir, int
 // ---------------------------------------------------------------------------
 static unsigned pcdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-hipError_t pose_prep(const float *Y, const float *Z, const float *table, int P, int D, int r,
-                     int F8, unsigned short *zs, unsigned short *w, float *yy, hipStream_t st) {
-  const int S = (2 * r + 1) * (2 * r + 1);
-  hipLaunchKernelGGL(k_pose_shifts, dim3(P, S), dim3(256), 0, st, Z, D, r, zs);
+hipError_t pose_prep(const float *Y, const float *Z, const float *table, int P, int D, int F8,
+                     unsigned short *zb, unsigned short *w, float *yy, hipStream_t st) {
+  hipLaunchKernelGGL(k_pose_zpad, dim3(P), dim3(256), 0, st, Z, D, zb);
   hipLaunchKernelGGL(k_pose_weights, dim3(P), dim3(256), 0, st, Y, table, D, F8, w, yy);
+  return hipGetLastError();
+}
+
+hipError_t pose_shifts(const unsigned short *zb, int P, int D, int r, unsigned short *zs,
+                       hipStream_t st) {
+  const int S = (2 * r + 1) * (2 * r + 1);
+  hipLaunchKernelGGL(k_pose_shifts, dim3(P, S), dim3(256), 0, st, zb, D, r, zs);
+  return hipGetLastError();
+}
+
+hipError_t pose_refine_z(const PoseRefineArgs &a, int P, hipStream_t st) {
+  // one block per particle and 16 candidates, its four waves splitting the K
+  // range: the gathered rows are the traffic, and four independent streams
+  // per block keep more of them in flight
+  const size_t lds = pose_refine_z_lds(a.D, a.F8);
+  hipLaunchKernelGGL((k_pose_refine_z<16, 4>), dim3(P, pcdiv(a.L, 16)), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 

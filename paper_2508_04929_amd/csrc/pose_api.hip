@@ -23,7 +23,8 @@ struct cs_pose_batch {
   void *mem = nullptr;              // fixed buffers below, sized for cap particles
   float *table = nullptr, *Z = nullptr, *yy = nullptr;
   float2 *spec = nullptr;
-  unsigned short *zs = nullptr, *w = nullptr;
+  unsigned short *zs = nullptr, *w = nullptr, *zb = nullptr;
+  bool zs_valid = false;            // shifted copies are built on first use after a load
   unsigned long long *best = nullptr;
   void *E = nullptr;                // energy matrix [P][K] of a grid search (grown on demand)
   size_t E_bytes = 0;
@@ -309,6 +310,7 @@ int cs_pose_batch_create(cs_ctx *ctx, int32_t D, float pixel, int32_t capacity,
   const size_t o_spec = o;  o += al256(C * D * Dh * 8);
   const size_t o_Z = o;     o += al256(C * q->npx * 4);
   const size_t o_zs = o;    o += al256(C * q->S * q->npx * 2);
+  const size_t o_zb = o;    o += al256(C * D * (D + 16) * 2);
   const size_t o_w = o;     o += al256(C * q->F8 * 2);
   const size_t o_yy = o;    o += al256(C * 4);
   const size_t o_best = o;  o += al256(C * 8);
@@ -322,6 +324,7 @@ int cs_pose_batch_create(cs_ctx *ctx, int32_t D, float pixel, int32_t capacity,
   q->spec = (float2 *)(m + o_spec);
   q->Z = (float *)(m + o_Z);
   q->zs = (unsigned short *)(m + o_zs);
+  q->zb = (unsigned short *)(m + o_zb);
   q->w = (unsigned short *)(m + o_w);
   q->yy = (float *)(m + o_yy);
   q->best = (unsigned long long *)(m + o_best);
@@ -349,7 +352,8 @@ int cs_pose_batch_load(cs_pose_batch *q, const float *images, const cs_ctf *ctf,
   hipStream_t st = (hipStream_t)stream;
   int rc = ctf_filter_into(ctx, q->D, q->pixel, images, ctf, P, q->table, q->spec, q->Z, st);
   if (rc) return rc;
-  HIPCHK(pose_prep(images, q->Z, q->table, P, q->D, q->r, q->F8, q->zs, q->w, q->yy, st));
+  HIPCHK(pose_prep(images, q->Z, q->table, P, q->D, q->F8, q->zb, q->w, q->yy, st));
+  q->zs_valid = false;
   if (filtered)
     HIPCHK(hipMemcpyAsync(filtered, q->Z, (size_t)P * q->npx * 4, hipMemcpyDeviceToDevice, st));
   q->P = P;
@@ -370,6 +374,10 @@ int cs_pose_batch_search(cs_pose_bank *b, cs_pose_batch *q, int32_t *best_rot, i
   rc = grow(ctx, &q->E, &q->E_bytes, (size_t)q->P * b->K * 4);
   if (rc) return rc;
   float *E = (float *)q->E;
+  if (!q->zs_valid) {
+    HIPCHK(pose_shifts(q->zb, q->P, q->D, q->r, q->zs, st));
+    q->zs_valid = true;
+  }
   PoseGemmArgs e;
   e.A = q->w; e.lda = q->F8;
   e.B = b->data; e.ldb = b->Kext; e.boff = b->npx;
@@ -417,6 +425,20 @@ int cs_pose_batch_refine(cs_pose_bank *b, cs_pose_batch *q, const float *proposa
   if (proposal)
     HIPCHK(pose_candidates(proposal, q->P, b->rot, b->ndir, b->n_psi, n_dir, n_psi_c, cl, st));
   HIPCHK(fill_u64(q->best, q->P, ~0ull, st));
+  if (pose_refine_z_lds(q->D, q->F8) <= 65536) {
+    PoseRefineArgs z;
+    z.zb = q->zb; z.w = q->w; z.bank = b->data; z.ldb = b->Kext;
+    z.cand = cl; z.L = L; z.nrows = b->K;
+    z.D = q->D; z.r = q->r; z.S = q->S; z.F8 = q->F8; z.npx = q->npx;
+    z.yy = q->yy; z.best = q->best; z.scores = scores;
+    HIPCHK(pose_refine_z(z, q->P, st));
+    HIPCHK(pose_decode(q->best, q->P, q->S, best_rot, best_shift, best_score, st));
+    return CS_OK;
+  }
+  if (!q->zs_valid) {  // particles too large for LDS: gathered GEMM over the shifted copies
+    HIPCHK(pose_shifts(q->zb, q->P, q->D, q->r, q->zs, st));
+    q->zs_valid = true;
+  }
   PoseGemmArgs a;
   a.A = q->zs; a.lda = q->npx;
   a.A2 = q->w; a.lda2 = q->F8; a.ka_split = q->npx;

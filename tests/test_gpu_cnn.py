@@ -55,7 +55,9 @@ def check_bf16_rounding(got_bf16, ref64, max_frac=1e-3):
 
 
 @pytest.mark.parametrize("B,H,W,Cin,Cout", [(3, 34, 34, 40, 72), (2, 66, 66, 1, 32),
-                                            (5, 8, 6, 256, 256)])
+                                            (5, 8, 6, 256, 256),
+                                            # M >= 16384: 128 x 128 and 128 x 64 tiles, ragged
+                                            (20, 64, 64, 32, 128), (17, 66, 66, 8, 64)])
 def test_conv_forward(gpu_lib, B, H, W, Cin, Cout):
     announce(f"conv forward B={B} H={H} W={W} Cin={Cin} Cout={Cout}")
     rng = np.random.default_rng(100 + Cin)
@@ -68,7 +70,8 @@ def test_conv_forward(gpu_lib, B, H, W, Cin, Cout):
     check_bf16_rounding(y, ref)
 
 
-@pytest.mark.parametrize("B,H,W,Cin,Cout", [(3, 34, 34, 40, 72), (4, 16, 16, 256, 256)])
+@pytest.mark.parametrize("B,H,W,Cin,Cout", [(3, 34, 34, 40, 72), (4, 16, 16, 256, 256),
+                                            (5, 64, 64, 64, 128), (4, 66, 66, 128, 64)])
 def test_conv_dgrad(gpu_lib, B, H, W, Cin, Cout):
     announce(f"conv dgrad B={B} H={H} W={W} Cin={Cin} Cout={Cout}")
     rng = np.random.default_rng(200 + Cin)
@@ -208,12 +211,32 @@ def test_network_layers_teacher_forced(gpu_lib, D, B):
         if l > 0:
             ref = cnn.conv3x3s2_dgrad(G[l + 1], wq[l][0], A[l].shape[1], A[l].shape[2]) * (A[l] > 0)
             check_bf16_rounding(net.tensor(l, True, shapes[l]), ref)
+    # inference stores the same activations as the training step, bitwise
+    net.forward(dev(img))
+    for i in range(8):
+        assert torch.equal(net.tensor(i, False, shapes[i]), bf(A[i]).to(torch.bfloat16)), i
     # free-running: the loss of the whole bfloat16 network agrees with the
     # oracle's (per-layer rounding flips move it by far less than 1e-3)
     l16, _, _ = cnn.loss_and_grad(layers, img, Rt, tt, lam=0.5, bf16=True)
     assert abs(host(loss)[0] - l16) <= 1e-3 * abs(l16)
     # no update was applied
     assert torch.equal(net.get_params(), dev(theta))
+    net.close()
+
+
+def test_inference_equals_training_forward_large_batch(gpu_lib):
+    """B=20 at D=128 puts the convolutions on 128 x 128 and 128 x 64 tiles."""
+    announce("inference vs training forward, D=128 B=20")
+    D, B = 128, 20
+    net, layers, theta, img, Rt, tt = _net_and_batch(gpu_lib, D, B, seed=650)
+    net.train_step(dev(img), dev(Rt), dev(tt), update=False)
+    shapes = _act_shapes(D, B)
+    ref = [net.tensor(i, False, shapes[i]).clone() for i in range(8)]
+    _, _, raw = net.forward(dev(img))
+    for i in range(8):
+        assert torch.equal(net.tensor(i, False, shapes[i]), ref[i]), i
+    wq = cnn.round_bf16(layers[7][0])
+    assert normwise(host(raw), hb(ref[7]) @ wq.T + layers[7][1]) <= 1e-5
     net.close()
 
 
