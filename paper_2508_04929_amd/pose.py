@@ -172,7 +172,7 @@ def literal_grid_search(lib, gd, image, ctf_one: binding.Ctf, grid_rot: torch.Te
     return best
 
 
-def run_c5(lib, *, n_train=200000, n_test=2048, epochs=4, batch=256, lr=1e-3, gamma=0.7,
+def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, gamma=0.85,
            lam=0.1, snr_db=-20.0, seed=5, coarse=(4, 24), fine=(8, 48), shift_radius=2,
            stages=((0, 5, 3), (1, 5, 3)), matched_filter=True, chunk=2048,
            literal_particles=2, log=print):
