@@ -278,7 +278,9 @@ int cs_cnn_train_step(cs_cnn *net, const float *images, const float *rot_target,
  * = output of layer l-1 after ReLU (conv outputs NHWC, then the hidden
  * vector); grad = 1: the gradient w.r.t. the pre-activation of layer
  * index-1 (masked by its ReLU), index 8 = dL/d(outputs) [B][8] as stored.
- * B is that of the last call; capacity in elements. */
+ * B is that of the last call; capacity in elements.  cs_cnn_forward runs
+ * the first two convolutions as one kernel and does not store index 1 (an
+ * error after it); its other tensors equal those of a training step. */
 int cs_cnn_tensor(cs_cnn *net, int32_t index, int32_t grad, uint16_t *dst, int64_t capacity,
                   void *stream);
 
@@ -289,7 +291,8 @@ int cs_cnn_tensor(cs_cnn *net, int32_t index, int32_t grad, uint16_t *dst, int64
  * the first layer.  out_f32 (may be NULL) receives the FP32 values before rounding.
  * dgrad: din = conv^T(dout) with wt = w transposed to [Cin][3][3][Cout],
  * zeroed where act_in <= 0 (act_in may be NULL: no mask); Cin % 8 == 0.
- * wgrad: dw [Cout][3][3][Cin] FP32 = sum over batch and pixels. */
+ * wgrad: dw [Cout][3][3][Cin] FP32 = sum over batch and pixels (Cin = 1
+ * needs Cout <= 32). */
 int cs_bf16_conv3x3s2_forward(cs_ctx *ctx, const uint16_t *in, const uint16_t *w, const float *bias,
                               int32_t B, int32_t H, int32_t W, int32_t Cin, int32_t Cout,
                               int32_t relu, uint16_t *out, float *out_f32, void *stream);

@@ -46,6 +46,7 @@ struct cs_cnn {
   float *loss_part = nullptr;
   int64_t step = 0;
   int last_B = 0;
+  bool act1_valid = false;  // the first layer's activation is stored by training steps only
   std::vector<size_t> elems;  // per-image elements of act[i] / dact[i]
   std::vector<void *> allocs;
 };
@@ -87,10 +88,19 @@ int refresh_bf16(cs_cnn *net, hipStream_t st) {
   return CS_OK;
 }
 
-int forward_layers(cs_cnn *net, const float *images, int B, hipStream_t st) {
+// fused: inference, the first two convolutions in one kernel (the first
+// layer's activation is not stored; training steps need it and run unfused)
+int forward_layers(cs_cnn *net, const float *images, int B, hipStream_t st, bool fused = false) {
   cs_ctx *ctx = net->ctx;
   HIPCHK(standardize(images, B, net->D * net->D, net->act[0], st));
-  for (size_t l = 0; l < net->layers.size(); ++l) {
+  size_t l0 = 0;
+  if (fused) {
+    const Layer &L1 = net->layers[0], &L2 = net->layers[1];
+    HIPCHK(conv12_fwd(net->act[0], net->wbuf + L1.wb_off, net->param + L1.b_off,
+                      net->wbuf + L2.wb_off, net->param + L2.b_off, B, net->D, net->act[2], st));
+    l0 = 2;
+  }
+  for (size_t l = l0; l < net->layers.size(); ++l) {
     const Layer &L = net->layers[l];
     const bf16 *w = net->wbuf + L.wb_off;
     const float *b = net->param + L.b_off;
@@ -246,9 +256,10 @@ int cs_cnn_forward(cs_cnn *net, const float *images, int32_t B, float *rot, floa
   if (B < 1 || B > net->max_batch) return fail(ctx, CS_ERR_INVALID_ARG, "batch must be in [1, max_batch]");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  int rc = forward_layers(net, images, B, st);
+  int rc = forward_layers(net, images, B, st, true);
   if (rc) return rc;
   net->last_B = B;
+  net->act1_valid = false;
   HIPCHK(head(net->out8, B, rot, shift, st));
   if (raw) HIPCHK(hipMemcpyAsync(raw, net->out8, (size_t)B * 8 * 4, hipMemcpyDeviceToDevice, st));
   return CS_OK;
@@ -267,6 +278,7 @@ int cs_cnn_train_step(cs_cnn *net, const float *images, const float *rot_target,
   int rc = forward_layers(net, images, B, st);
   if (rc) return rc;
   net->last_B = B;
+  net->act1_valid = true;
   const int nl = (int)net->layers.size();
   // head: loss and d(out8)
   HIPCHK(head_loss(net->out8, rot_target, shift_target, B, lambda, net->loss_part,
@@ -311,6 +323,8 @@ int cs_cnn_tensor(cs_cnn *net, int32_t index, int32_t grad, uint16_t *dst, int64
     return fail(ctx, CS_ERR_INVALID_ARG, "bad tensor index");
   const int64_t n = (int64_t)net->last_B * (int64_t)net->elems[index];
   if (n == 0) return fail(ctx, CS_ERR_INVALID_ARG, "no forward pass yet");
+  if (index == 1 && !grad && !net->act1_valid)
+    return fail(ctx, CS_ERR_INVALID_ARG, "inference does not store the first layer's activation");
   if (capacity < n) return fail(ctx, CS_ERR_INVALID_ARG, "capacity %lld < %lld", (long long)capacity, (long long)n);
   HIPCHK(hipMemcpyAsync(dst, grad ? net->dact[index] : net->act[index], n * 2, hipMemcpyDeviceToDevice,
                         (hipStream_t)stream));
@@ -351,7 +365,7 @@ int cs_bf16_conv3x3s2_wgrad(cs_ctx *ctx, const uint16_t *dout, const uint16_t *i
                             void *stream) {
   if (!ctx) return CS_ERR_INVALID_ARG;
   if (!dout || !in || !dw || B < 1 || H < 2 || W < 2 || H % 2 || W % 2 || Cout % 8 ||
-      (Cin != 1 && Cin % 8))
+      (Cin != 1 && Cin % 8) || (Cin == 1 && Cout > 32))
     return fail(ctx, CS_ERR_INVALID_ARG, "bad conv wgrad arguments");
   HIPCHK(hipSetDevice(ctx->device));
   const size_t cap = (size_t)1 << 23;

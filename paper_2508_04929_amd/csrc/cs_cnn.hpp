@@ -15,6 +15,10 @@ typedef unsigned short bf16;  // raw bfloat16 bits
 // (forward and weight gradient only); otherwise Cin, Cout are multiples of 8.
 hipError_t conv_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int Hi, int Wi,
                     int Cin, int Cout, int relu, bf16 *out, float *out32, hipStream_t st);
+// Inference: the first (1 -> 32) and second (32 -> 64) convolutions fused,
+// ReLU after both; in0 [B][H0][H0] (H0 % 64 == 0) -> out [B][H0/4][H0/4][64].
+hipError_t conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2,
+                      const float *b2, int B, int H0, bf16 *out, hipStream_t st);
 hipError_t conv_dgrad(const bf16 *dout, const bf16 *wt, const bf16 *act_in, int B, int Hi, int Wi,
                       int Cin, int Cout, bf16 *din, float *din32, hipStream_t st);
 hipError_t conv_wgrad(const bf16 *dout, const bf16 *in, int B, int Hi, int Wi, int Cin, int Cout,

@@ -298,8 +298,17 @@ __global__ void __launch_bounds__(256)
 k_splitk_reduce(const float *part, int splits, int64_t n, float *out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
+  // loads issued 8 ahead, added in split order
   float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[(size_t)z * n + i];
+  int z = 0;
+  for (; z + 8 <= splits; z += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(z + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; z < splits; ++z) s += part[(size_t)z * n + i];
   out[i] = s;
 }
 
@@ -311,7 +320,15 @@ k_colsum(const bf16 *g, int M, int N, int rows_per_chunk, float *part) {
   if (n >= N) return;
   const int r0 = blockIdx.y * rows_per_chunk, r1 = min(M, r0 + rows_per_chunk);
   float s = 0.f;
-  for (int m = r0; m < r1; ++m) s += bf2f(g[(size_t)m * N + n]);
+  int m = r0;
+  for (; m + 8 <= r1; m += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = bf2f(g[(size_t)(m + u) * N + n]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; m < r1; ++m) s += bf2f(g[(size_t)m * N + n]);
   part[(size_t)blockIdx.y * N + n] = s;
 }
 
@@ -361,29 +378,125 @@ k_conv1_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int Hi, int
   }
 }
 
-// First-conv weight gradient partials: part[blk][co][tap] over a pixel chunk.
+// First-conv weight gradient partials: part[blk][co][tap] over a chunk of
+// pix_per_block (<= 256) output pixels.  The chunk's 3x3 input patches and
+// gradient rows are staged in LDS once; each (co, tap) then sums over the
+// chunk's pixels in pixel order.
 __global__ void __launch_bounds__(256)
 k_conv1_wgrad(const bf16 *in, const bf16 *dpre, int B, int Hi, int Wi, int Cout,
               int pix_per_block, float *part) {
+  __shared__ float xs[256][9];
+  __shared__ float gs[256 * 32];  // Cout <= 32 gradient values per pixel
   const int Ho = Hi / 2, Wo = Wi / 2;
   const int64_t npix = (int64_t)B * Ho * Wo;
   const int64_t p0 = (int64_t)blockIdx.x * pix_per_block;
-  const int64_t p1 = min(npix, p0 + pix_per_block);
-  // thread -> (co, tap) pairs, strided
-  for (int q = 0; q < Cout * 9; q += 256) {
-    const int ct = q + threadIdx.x;
+  const int np = (int)min((int64_t)pix_per_block, npix - p0);
+  for (int q = threadIdx.x; q < np * 9; q += 256) {
+    const int pl = q / 9, tap = q - pl * 9;
+    const int64_t p = p0 + pl;
+    const int ox = (int)(p % Wo), t = (int)(p / Wo), oy = t % Ho, b = t / Ho;
+    const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+    xs[pl][tap] = (iy >= 0 && iy < Hi && ix >= 0 && ix < Wi) ? bf2f(in[((size_t)b * Hi + iy) * Wi + ix]) : 0.f;
+  }
+  for (int q = threadIdx.x; q < np * Cout; q += 256) gs[q] = bf2f(dpre[p0 * Cout + q]);
+  __syncthreads();
+  for (int ct = threadIdx.x; ct < Cout * 9; ct += 256) {
+    const int co = ct / 9, tap = ct % 9;
     float s = 0.f;
-    if (ct < Cout * 9) {
-      const int co = ct / 9, tap = ct % 9;
-      for (int64_t p = p0; p < p1; ++p) {
-        const int ox = (int)(p % Wo), t = (int)(p / Wo), oy = t % Ho, b = t / Ho;
-        const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
-        if (iy < 0 || iy >= Hi || ix < 0 || ix >= Wi) continue;
-        s += bf2f(dpre[p * Cout + co]) * bf2f(in[((size_t)b * Hi + iy) * Wi + ix]);
+    for (int pl = 0; pl < np; ++pl) s += gs[pl * Cout + co] * xs[pl][tap];
+    part[(size_t)blockIdx.x * Cout * 9 + ct] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference: the first two convolutions fused (C1 = 32 first-layer channels,
+// C2 = 64 second-layer channels).  A block owns 8 x 16 second-layer output
+// pixels of one image: it stages the 35 x 67 input patch, computes the
+// 17 x 33 x 32 first-layer patch once into LDS (same fma order and bfloat16
+// rounding as k_conv1_fwd, so the values are identical), then runs the second
+// layer on MFMA with A fragments read from the LDS patch (im2col addressing,
+// one tap per K slice of 32 channels) and B fragments (weights) loaded from
+// global memory straight into registers.  The first layer's activation never
+// goes to HBM.
+// ---------------------------------------------------------------------------
+constexpr int C12_PY = 17, C12_PX = 33, C12_IY = 35, C12_IX = 67;
+
+__global__ void __launch_bounds__(256)
+k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, const float *b2,
+             int H0, bf16 *out) {
+  __shared__ float xin[C12_IY * C12_IX];
+  __shared__ float wl[9 * 32 + 32];               // [tap][c] then biases
+  __shared__ __attribute__((aligned(16))) bf16 a1[C12_PY * C12_PX * 32];  // [y][x][c]
+  const int H1 = H0 / 2, H2 = H1 / 2;
+  const int tiles_x = H2 / 16;
+  const int b = blockIdx.y;
+  const int oy0 = (blockIdx.x / tiles_x) * 8, ox0 = (blockIdx.x % tiles_x) * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int cq = (lane >> 4) * 8;
+  // wave wv computes output channels [16 wv, 16 wv + 16) for all 128 pixels;
+  // its weight fragments for the 9 taps are requested now and arrive while
+  // the first layer is computed
+  bf16x8 bw[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+    bw[t] = *(const bf16x8 *)&w2[(size_t)(wv * 16 + (lane & 15)) * 288 + t * 32 + cq];
+  // input patch rows 4 oy0 - 3 .., columns 4 ox0 - 3 ..
+  const int iy0 = 4 * oy0 - 3, ix0 = 4 * ox0 - 3;
+  for (int q = tid; q < C12_IY * C12_IX; q += 256) {
+    const int yy = iy0 + q / C12_IX, xx = ix0 + q % C12_IX;
+    xin[q] = (yy >= 0 && yy < H0 && xx >= 0 && xx < H0) ? bf2f(in0[((size_t)b * H0 + yy) * H0 + xx]) : 0.f;
+  }
+  for (int q = tid; q < 9 * 32; q += 256) wl[(q % 9) * 32 + q / 9] = bf2f(w1[q]);  // w1 [c][tap]
+  for (int q = tid; q < 32; q += 256) wl[9 * 32 + q] = b1 ? b1[q] : 0.f;
+  __syncthreads();
+  // first layer at patch positions (y, x) = first-layer rows 2 oy0 - 1 + y, columns 2 ox0 - 1 + x
+  for (int task = tid; task < C12_PY * C12_PX * 4; task += 256) {
+    const int pos = task >> 2, c0 = (task & 3) * 8;
+    const int y = pos / C12_PX, x = pos - y * C12_PX;
+    const int y1 = 2 * oy0 - 1 + y, x1 = 2 * ox0 - 1 + x;
+    Vec8 o;
+    if (y1 < 0 || y1 >= H1 || x1 < 0 || x1 >= H1) {
+      o.u = make_uint4(0, 0, 0, 0);
+    } else {
+      float xv[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) xv[t] = xin[(2 * y + t / 3) * C12_IX + 2 * x + t % 3];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float acc = wl[9 * 32 + c0 + e];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc = __fmaf_rn(wl[t * 32 + c0 + e], xv[t], acc);
+        o.h[e] = f2bf(fmaxf(acc, 0.f));
       }
-      part[(size_t)blockIdx.x * Cout * 9 + ct] = s;
+    }
+    *(uint4 *)&a1[pos * 32 + c0] = o.u;
+  }
+  __syncthreads();
+  // second layer: MFMA row tiles i = pixels [16 i, 16 i + 16) of the 8 x 16
+  // tile (one output row each), columns = this wave's 16 channels
+  f32x4 acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int tap = 0; tap < 9; ++tap) {
+    const int ky = tap / 3, kx = tap % 3;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int y = 2 * i + ky, x = 2 * (lane & 15) + kx;
+      const bf16x8 af = *(const bf16x8 *)&a1[(y * C12_PX + x) * 32 + cq];
+      acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bw[tap], acc[i], 0, 0, 0);
     }
   }
+  const int n = wv * 16 + (lane & 15);
+  const float bn = b2 ? b2[n] : 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = i * 16 + (lane >> 4) * 4 + r;
+      const int oy = oy0 + (m >> 4), ox = ox0 + (m & 15);
+      out[(((size_t)b * H2 + oy) * H2 + ox) * 64 + n] = f2bf(fmaxf(acc[i][r] + bn, 0.f));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -597,6 +710,15 @@ hipError_t conv_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int
   return launch_gemm(op, B * (Hi / 2) * (Wi / 2), Cout, 9 * Cin, 1, st);
 }
 
+hipError_t conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2,
+                      const float *b2, int B, int H0, bf16 *out, hipStream_t st) {
+  if (H0 % 64 != 0) return hipErrorInvalidValue;
+  const int H2 = H0 / 4;
+  hipLaunchKernelGGL(k_conv12_fwd, dim3((H2 / 8) * (H2 / 16), B), dim3(256), 0, st, in0, w1, b1, w2,
+                     b2, H0, out);
+  return hipGetLastError();
+}
+
 hipError_t conv_dgrad(const bf16 *dout, const bf16 *wt, const bf16 *act_in, int B, int Hi, int Wi,
                       int Cin, int Cout, bf16 *din, float *din32, hipStream_t st) {
   ConvDgradOp op;
@@ -611,7 +733,7 @@ hipError_t conv_wgrad(const bf16 *dout, const bf16 *in, int B, int Hi, int Wi, i
   if (Cin == 1) {
     const int ppb = 256;
     const unsigned blocks = cdiv_(npix, ppb);
-    if ((size_t)blocks * Cout * 9 > part_cap) return hipErrorInvalidValue;
+    if (Cout > 32 || (size_t)blocks * Cout * 9 > part_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_conv1_wgrad, dim3(blocks), dim3(256), 0, st, in, dout, B, Hi, Wi, Cout,
                        ppb, part);
     hipLaunchKernelGGL(k_splitk_reduce, dim3(cdiv_(Cout * 9, 256)), dim3(256), 0, st, part,
