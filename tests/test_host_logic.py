@@ -1,0 +1,48 @@
+"""Host-side library logic that runs without a GPU.
+
+`cs_pose_grid` is plain host code (HEALPix pixel centres and the view
+rotations): it is checked here against the independent oracle grid, and the
+argument checks of the entry points that fail before touching a device.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pose as o_pose
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2508_04929_amd", "libcryosplat.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libcryosplat.so not built")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2508_04929_amd import binding
+    return binding.Library(binding.load_library())
+
+
+@pytest.mark.parametrize("nside,n_psi", [(1, 1), (1, 8), (2, 12), (4, 24), (8, 48)])
+def test_pose_grid_matches_oracle(lib, nside, n_psi):
+    got = lib.pose_grid(nside, n_psi)
+    assert got.shape == (12 * nside * nside * n_psi, 3, 3)
+    np.testing.assert_allclose(got, o_pose.grid(nside, n_psi), atol=2e-6)
+
+
+def test_pose_grid_count_query_and_bad_arguments(lib):
+    n = ctypes.c_int64()
+    assert lib.lib.cs_pose_grid(4, 24, None, ctypes.byref(n)) == 0 and n.value == 4608
+    for bad in ((0, 24), (4, 0), (2000, 1), (1, 5000)):
+        assert lib.lib.cs_pose_grid(bad[0], bad[1], None, ctypes.byref(n)) == -1
+    assert lib.lib.cs_pose_grid(1, 1, None, None) == -1
+
+
+def test_null_context_arguments_are_rejected(lib):
+    L = lib.lib
+    assert L.cs_render(None, None, None, None, None, None, None) == -1
+    assert L.cs_adam_step(None, None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.cs_cnn_forward(None, None, 1, None, None, None, None) == -1
+    assert L.cs_pose_batch_load(None, None, None, 1, None, None) == -1
+    assert L.cs_pose_grid_search(None, None, None, 1, 2, None, None, None, None, None) == -1
+    assert L.cs_cnn_param_count(None) == -1 and L.cs_pose_bank_size(None) == -1
