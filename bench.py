@@ -229,6 +229,63 @@ def run(args):
     return result
 
 
+def run_batched(reps: int = 10, autotune: bool = True):
+    """Uneven batching: 8 mixtures (N = 5k ... 150k) x 128 images, D in
+    {128, 192, 256}, fwd + adjoint of all problems in one persistent launch
+    per pass (replayed graph), against the same problems as 8 calls."""
+    import numpy as np
+    import torch
+
+    from paper_2508_04929_amd import binding, inputs
+
+    lib = binding.library()
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    probs, n_img, pairs = [], 0, 0
+    for g, v, gt, rn in inputs.c3():
+        rot, shift = t(v.rot), t(v.shift)
+        ctf = binding.Ctf(t(v.defocus_u), t(v.defocus_v), t(v.astig), t(v.phase),
+                          v.voltage_kv, v.cs_mm, v.amp_contrast, v.bfactor)
+        X = lib.render(t(gt.means), t(gt.log_scales), t(gt.quats), t(gt.amps), rot, shift, v.D,
+                       v.pixel, ctf=ctf)
+        sd = torch.sqrt(X.double().var() / 10 ** (-20 / 10)).float()
+        gen = torch.Generator(device=dev).manual_seed(3)
+        Y = (X + sd * torch.randn(X.shape, device=dev, generator=gen)).contiguous()
+        prm = [t(g.means), t(g.log_scales), t(g.quats), t(g.amps)]
+        probs.append(lib.make_problem(*prm, rot, shift, v.D, v.pixel, Y, ctf=ctf,
+                                      reduction="mean"))
+        pairs += int(lib.pair_count(*prm, rot, shift, v.D, v.pixel).sum().item())
+        n_img += v.b
+    if autotune:
+        lib.autotune(probs, reps=2)
+
+    def batched():
+        lib.loss_and_grad_multi(probs, use_graph=True)
+
+    def separate():
+        for pr in probs:
+            lib.loss_and_grad(pr.means, pr.log_scales, pr.quats, pr.amps, pr.rot, pr.shift, pr.D,
+                              pr.pixel, pr.observed, ctf=pr.ctf, options=pr.options,
+                              reduction="mean", grads=pr.grads, loss=pr.loss)
+
+    out = {}
+    for name, fn in (("batched", batched), ("separate", separate)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"ms": dt * 1e3, "images_per_s": n_img / dt, "pairs_per_s": pairs / dt}
+    out["workload"] = ("uneven batching: 8 mixtures, N = 5k...150k, 128 images each at D in "
+                       "{128,192,256}, CTF, fwd + adjoint, autotuned tile/halo/budget")
+    out["images"] = n_img
+    out["pairs"] = pairs
+    out["options"] = [[pr.options.tile, pr.options.halo, pr.options.budget] for pr in probs]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +302,8 @@ def main():
     ap.add_argument("--no-pose", dest="pose", action="store_false",
                     help="skip the learned-pose experiment (network trained on 200k renders, "
                          "then learned proposal + refinement vs grid search; about a minute)")
+    ap.add_argument("--no-batched", dest="batched", action="store_false",
+                    help="skip the uneven-batching measurement (8 mixtures in one launch)")
     ap.add_argument("--pose-train", type=int, default=200000)
     ap.add_argument("--pose-epochs", type=int, default=12)
     ap.add_argument("--pose-test", type=int, default=2048)
@@ -260,6 +319,11 @@ def main():
               file=sys.stderr, flush=True)
     res = run(args)
     res["cpu_baseline"] = cpu
+    if args.batched:
+        res["batched"] = run_batched()
+        print(f"[bench] batched: {res['batched']['batched']['images_per_s']:.0f} images/s "
+              f"(separate calls {res['batched']['separate']['images_per_s']:.0f})",
+              file=sys.stderr, flush=True)
     if args.pose:
         from paper_2508_04929_amd import binding, pose
         log = lambda m: print(f"[pose] {m}", file=sys.stderr, flush=True)

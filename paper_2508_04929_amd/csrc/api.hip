@@ -316,10 +316,25 @@ ProbDev prob_dev(const Plan &P) {
   return d;
 }
 
-// One persistent launch of the forward or adjoint splat over the given
-// problems (chunks of kMaxProblems per launch).
-int launch_persistent(cs_ctx *ctx, bool forward, const std::vector<const Plan *> &ps,
+// Persistent launches of the forward or adjoint splat over the given
+// problems: problems with the same canvas size share one launch (up to
+// kMaxProblems each), so that no problem runs at the occupancy of a larger
+// canvas; groups keep the problems' order.
+int launch_persistent(cs_ctx *ctx, bool forward, const std::vector<const Plan *> &all,
                       hipStream_t st) {
+  std::vector<std::vector<const Plan *>> groups;
+  std::vector<int> sizes;
+  for (const Plan *pl : all) {
+    const int cs = pl->G.C * pl->G.S;
+    size_t g = 0;
+    while (g < sizes.size() && sizes[g] != cs) ++g;
+    if (g == sizes.size()) {
+      sizes.push_back(cs);
+      groups.emplace_back();
+    }
+    groups[g].push_back(pl);
+  }
+  for (const auto &ps : groups)
   for (size_t c0 = 0; c0 < ps.size(); c0 += kMaxProblems) {
     MultiProb MP{};
     size_t lds = 0;
