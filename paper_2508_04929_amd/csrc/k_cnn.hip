@@ -16,15 +16,12 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 __device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float((unsigned)v << 16); }
 
-// Round to nearest even (NaN kept quiet).
-__device__ __forceinline__ bf16 f2bf(float x) {
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16)(u >> 16);
-}
+// Round to nearest even (the hardware conversion, v_cvt_pk_bf16_f32).
+__device__ __forceinline__ bf16 f2bf(float x) { return __builtin_bit_cast(bf16, (__bf16)x); }
 
-constexpr int BK = 32, LDK = BK + 8;  // LDS rows padded to 80 bytes
+// MK: K of one MFMA (and the granularity of split-K ranges); BK: K staged
+// per LDS step; LDS rows padded to 80 bytes (conflict-free 16-byte reads)
+constexpr int MK = 32, BK = 32, LDK = BK + 8;
 
 union Vec8 {
   uint4 u;
@@ -40,19 +37,25 @@ union Vec8 {
 // One K step of an operand tile: each thread fetches 16 bytes into a
 // register (prefetched while the previous step computes), then stores them
 // into the LDS tile (non-transposed: 8 consecutive k of one row; transposed:
-// 8 consecutive rows of one k, scattered into 8 rows).
-template <class Op, int TB>
-__device__ __forceinline__ uint4 fetch_tile(const Op &op, bool isA, int idx, int r0, int k0, int R,
-                                            int Kend) {
-  const bool trans = isA ? Op::kATrans : Op::kBTrans;
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if (!trans) {
-    const int r = r0 + (idx >> 2), k = k0 + (idx & 3) * 8;
-    if (r < R && k < Kend) v = isA ? op.a_vec(r, k) : op.b_vec(r, k);
-  } else {
-    const int r = r0 + (idx % (TB / 8)) * 8, k = k0 + idx / (TB / 8);
-    if (r < R && k < Kend) v = isA ? op.a_vecT(r, k) : op.b_vecT(r, k);
+// 8 consecutive rows of one k, scattered into 8 rows).  A non-transposed
+// operand keeps the same rows for the whole K loop, so each thread decodes
+// its rows once (Op::row_a / row_b) and gathers with the step's base k
+// (uniform across the block) plus its own offset (Op::vec_a / vec_b).
+template <class Op, bool IS_A>
+struct Gather {
+  typedef typename Op::Row Row;
+  __device__ static Row row(const Op &op, int r) { return IS_A ? op.row_a(r) : op.row_b(r); }
+  __device__ static uint4 vec(const Op &op, const Row &w, int k0, int koff) {
+    return IS_A ? op.vec_a(w, k0, koff) : op.vec_b(w, k0, koff);
   }
+};
+
+template <class Op, int TB>
+__device__ __forceinline__ uint4 fetch_trans(const Op &op, bool isA, int idx, int r0, int k0, int R,
+                                             int Kend) {
+  uint4 v = make_uint4(0, 0, 0, 0);
+  const int r = r0 + (idx % (TB / 8)) * 8, k = k0 + idx / (TB / 8);
+  if (r < R && k < Kend) v = isA ? op.a_vecT(r, k) : op.b_vecT(r, k);
   return v;
 }
 
@@ -60,7 +63,7 @@ template <class Op, int TB>
 __device__ __forceinline__ void put_tile(bool isA, bf16 (*tile)[LDK], int idx, uint4 v) {
   const bool trans = isA ? Op::kATrans : Op::kBTrans;
   if (!trans) {
-    *(uint4 *)&tile[idx >> 2][(idx & 3) * 8] = v;
+    *(uint4 *)&tile[idx / (BK / 8)][(idx % (BK / 8)) * 8] = v;
   } else {
     Vec8 u;
     u.u = v;
@@ -69,6 +72,34 @@ __device__ __forceinline__ void put_tile(bool isA, bf16 (*tile)[LDK], int idx, u
     for (int i = 0; i < 8; ++i) tile[rq + i][kk] = u.h[i];
   }
 }
+
+// Per-thread operand fetch state of one side of the GEMM.
+template <class Op, int TB, int NQ, bool IS_A>
+struct Side {
+  static constexpr bool kTrans = IS_A ? Op::kATrans : Op::kBTrans;
+  typename Op::Row row[NQ];
+  bool ok[NQ];
+  int koff[NQ];
+  __device__ void init(const Op &op, int tid, int r0, int R) {
+    if constexpr (!kTrans) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int idx = tid + 256 * q, r = r0 + idx / (BK / 8);
+        ok[q] = r < R;
+        koff[q] = (idx % (BK / 8)) * 8;
+        row[q] = Gather<Op, IS_A>::row(op, ok[q] ? r : r0);
+      }
+    }
+  }
+  __device__ uint4 fetch(const Op &op, int q, int tid, int r0, int k0, int R, int Kend) const {
+    if constexpr (kTrans) {
+      return fetch_trans<Op, TB>(op, IS_A, tid + 256 * q, r0, k0, R, Kend);
+    } else {
+      if (!ok[q] || k0 + koff[q] >= Kend) return make_uint4(0, 0, 0, 0);
+      return Gather<Op, IS_A>::vec(op, row[q], k0, koff[q]);
+    }
+  }
+};
 
 // TBM x TBN block tile, four waves in 2 x 2, each wave (TBM/2) x (TBN/2) as
 // 16 x 16 MFMA tiles; K steps of 32 double-buffered through LDS (operands
@@ -91,11 +122,15 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  Side<Op, TBM, NA, true> sa;
+  Side<Op, TBN, NB, false> sb;
+  sa.init(op, tid, m0, M);
+  sb.init(op, tid, n0, N);
   uint4 ra[NA], rb[NB];
 #pragma unroll
-  for (int q = 0; q < NA; ++q) ra[q] = fetch_tile<Op, TBM>(op, true, tid + 256 * q, m0, kb, M, ke);
+  for (int q = 0; q < NA; ++q) ra[q] = sa.fetch(op, q, tid, m0, kb, M, ke);
 #pragma unroll
-  for (int q = 0; q < NB; ++q) rb[q] = fetch_tile<Op, TBN>(op, false, tid + 256 * q, n0, kb, N, ke);
+  for (int q = 0; q < NB; ++q) rb[q] = sb.fetch(op, q, tid, n0, kb, N, ke);
 #pragma unroll
   for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[0], tid + 256 * q, ra[q]);
 #pragma unroll
@@ -106,24 +141,26 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
     const bool more = k0 + BK < ke;
     if (more) {
 #pragma unroll
-      for (int q = 0; q < NA; ++q)
-        ra[q] = fetch_tile<Op, TBM>(op, true, tid + 256 * q, m0, k0 + BK, M, ke);
+      for (int q = 0; q < NA; ++q) ra[q] = sa.fetch(op, q, tid, m0, k0 + BK, M, ke);
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        rb[q] = fetch_tile<Op, TBN>(op, false, tid + 256 * q, n0, k0 + BK, N, ke);
+      for (int q = 0; q < NB; ++q) rb[q] = sb.fetch(op, q, tid, n0, k0 + BK, N, ke);
     }
-    bf16x8 af[TI], bv[TJ];
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
-      af[i] = *(const bf16x8 *)&sA[cur][wm + i * 16 + (lane & 15)][(lane >> 4) * 8];
+    for (int ks = 0; ks < BK / MK; ++ks) {
+      if (k0 + ks * MK >= ke) break;  // past the end of this K range: nothing to add
+      bf16x8 af[TI], bv[TJ];
 #pragma unroll
-    for (int j = 0; j < TJ; ++j)
-      bv[j] = *(const bf16x8 *)&sB[cur][wn + j * 16 + (lane & 15)][(lane >> 4) * 8];
-#pragma unroll
-    for (int i = 0; i < TI; ++i)
+      for (int i = 0; i < TI; ++i)
+        af[i] = *(const bf16x8 *)&sA[cur][wm + i * 16 + (lane & 15)][ks * MK + (lane >> 4) * 8];
 #pragma unroll
       for (int j = 0; j < TJ; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bv[j], acc[i][j], 0, 0, 0);
+        bv[j] = *(const bf16x8 *)&sB[cur][wn + j * 16 + (lane & 15)][ks * MK + (lane >> 4) * 8];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bv[j], acc[i][j], 0, 0, 0);
+    }
     if (more) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[cur ^ 1], tid + 256 * q, ra[q]);
@@ -156,21 +193,44 @@ struct ConvGeom {
 struct ConvFwdOp {
   static constexpr bool kATrans = false, kBTrans = false;
   ConvGeom g;
+  int tap_uniform;  // Cin % BK == 0: a K step stays within one tap
   const bf16 *in, *w;
   const float *bias;
   bf16 *out;
   float *out32;
   int relu;
-  __device__ uint4 a_vec(int m, int k) const {
+  struct Row {
+    int64_t off;
+    int y, x;
+  };
+  // output pixel m = (b, oy, ox): the top-left input corner of its window
+  __device__ Row row_a(int m) const {
     const int ox = m % g.Wo, t = m / g.Wo, oy = t % g.Ho, b = t / g.Ho;
-    const int tap = k / g.Cin, ci = k - tap * g.Cin;
-    const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
-    if (iy < 0 || iy >= g.Hi || ix < 0 || ix >= g.Wi) return make_uint4(0, 0, 0, 0);
-    return *(const uint4 *)&in[(((size_t)b * g.Hi + iy) * g.Wi + ix) * g.Cin + ci];
+    Row r;
+    r.y = 2 * oy - 1;
+    r.x = 2 * ox - 1;
+    r.off = (((int64_t)b * g.Hi + r.y) * g.Wi + r.x) * g.Cin;
+    return r;
   }
-  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&w[(size_t)n * 9 * g.Cin + k]; }
-  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
-  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ uint4 vec_a(const Row &r, int k0, int koff) const {
+    int tap, ci;
+    if (tap_uniform) {
+      tap = k0 / g.Cin;
+      ci = k0 - tap * g.Cin + koff;
+    } else {
+      const int k = k0 + koff;
+      tap = k / g.Cin;
+      ci = k - tap * g.Cin;
+    }
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    const int iy = r.y + dy, ix = r.x + dx;
+    if ((unsigned)iy >= (unsigned)g.Hi || (unsigned)ix >= (unsigned)g.Wi) return make_uint4(0, 0, 0, 0);
+    return *(const uint4 *)&in[r.off + ((int64_t)dy * g.Wi + dx) * g.Cin + ci];
+  }
+  __device__ Row row_b(int n) const { return Row{(int64_t)n * 9 * g.Cin, 0, 0}; }
+  __device__ uint4 vec_b(const Row &r, int k0, int koff) const {
+    return *(const uint4 *)&w[r.off + k0 + koff];
+  }
   __device__ void store(int m, int n, float v, int) const {
     v += bias ? bias[n] : 0.f;
     if (relu) v = fmaxf(v, 0.f);
@@ -186,21 +246,40 @@ struct ConvFwdOp {
 struct ConvDgradOp {
   static constexpr bool kATrans = false, kBTrans = false;
   ConvGeom g;
+  int tap_uniform;  // Cout % BK == 0
   const bf16 *dout, *wt, *act_in;
   bf16 *din;
   float *din32;
-  __device__ uint4 a_vec(int m, int k) const {
+  struct Row {
+    int64_t off;
+    int y, x;
+  };
+  // input pixel m = (b, iy, ix)
+  __device__ Row row_a(int m) const {
     const int ix = m % g.Wi, t = m / g.Wi, iy = t % g.Hi, b = t / g.Hi;
-    const int tap = k / g.Cout, co = k - tap * g.Cout;
-    const int oy2 = iy + 1 - tap / 3, ox2 = ix + 1 - tap % 3;
+    return Row{(int64_t)b * g.Ho * g.Wo * g.Cout, iy, ix};
+  }
+  __device__ uint4 vec_a(const Row &r, int k0, int koff) const {
+    int tap, co;
+    if (tap_uniform) {
+      tap = k0 / g.Cout;
+      co = k0 - tap * g.Cout + koff;
+    } else {
+      const int k = k0 + koff;
+      tap = k / g.Cout;
+      co = k - tap * g.Cout;
+    }
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    const int oy2 = r.y + 1 - dy, ox2 = r.x + 1 - dx;
     if (oy2 < 0 || ox2 < 0 || (oy2 & 1) || (ox2 & 1)) return make_uint4(0, 0, 0, 0);
     const int oy = oy2 >> 1, ox = ox2 >> 1;
     if (oy >= g.Ho || ox >= g.Wo) return make_uint4(0, 0, 0, 0);
-    return *(const uint4 *)&dout[(((size_t)b * g.Ho + oy) * g.Wo + ox) * g.Cout + co];
+    return *(const uint4 *)&dout[r.off + ((int64_t)oy * g.Wo + ox) * g.Cout + co];
   }
-  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&wt[(size_t)n * 9 * g.Cout + k]; }
-  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
-  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  __device__ Row row_b(int n) const { return Row{(int64_t)n * 9 * g.Cout, 0, 0}; }
+  __device__ uint4 vec_b(const Row &r, int k0, int koff) const {
+    return *(const uint4 *)&wt[r.off + k0 + koff];
+  }
   __device__ void store(int m, int n, float v, int) const {
     const size_t o = (size_t)m * g.Cin + n;
     if (act_in && !(bf2f(act_in[o]) > 0.f)) v = 0.f;
@@ -216,8 +295,7 @@ struct ConvWgradOp {
   ConvGeom g;
   const bf16 *dout, *in;
   float *part;
-  __device__ uint4 a_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
-  __device__ uint4 b_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
+  struct Row {};
   // 8 consecutive output channels of pixel p
   __device__ uint4 a_vecT(int m, int p) const { return *(const uint4 *)&dout[(size_t)p * g.Cout + m]; }
   // 8 consecutive (tap, ci) columns of the im2col row of pixel p
@@ -240,6 +318,10 @@ struct LinGeom {
   int B, In, Out;
 };
 
+struct LinRow {
+  int64_t off;
+};
+
 struct LinFwdOp {  // M = B, N = Out, K = In
   static constexpr bool kATrans = false, kBTrans = false;
   LinGeom g;
@@ -248,10 +330,11 @@ struct LinFwdOp {  // M = B, N = Out, K = In
   bf16 *y;
   float *y32;
   int relu;
-  __device__ uint4 a_vec(int m, int k) const { return *(const uint4 *)&x[(size_t)m * g.In + k]; }
-  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&w[(size_t)n * g.In + k]; }
-  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
-  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  typedef LinRow Row;
+  __device__ Row row_a(int m) const { return Row{(int64_t)m * g.In}; }
+  __device__ Row row_b(int n) const { return Row{(int64_t)n * g.In}; }
+  __device__ uint4 vec_a(const Row &r, int k0, int koff) const { return *(const uint4 *)&x[r.off + k0 + koff]; }
+  __device__ uint4 vec_b(const Row &r, int k0, int koff) const { return *(const uint4 *)&w[r.off + k0 + koff]; }
   __device__ void store(int m, int n, float v, int) const {
     v += bias ? bias[n] : 0.f;
     if (relu) v = fmaxf(v, 0.f);
@@ -267,10 +350,11 @@ struct LinDgradOp {  // M = B, N = In, K = Out; wt = W^T [In][Out]
   const bf16 *dy, *wt, *x_act;
   bf16 *dx;
   float *dx32;
-  __device__ uint4 a_vec(int m, int k) const { return *(const uint4 *)&dy[(size_t)m * g.Out + k]; }
-  __device__ uint4 b_vec(int n, int k) const { return *(const uint4 *)&wt[(size_t)n * g.Out + k]; }
-  __device__ uint4 a_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
-  __device__ uint4 b_vecT(int, int) const { return make_uint4(0, 0, 0, 0); }
+  typedef LinRow Row;
+  __device__ Row row_a(int m) const { return Row{(int64_t)m * g.Out}; }
+  __device__ Row row_b(int n) const { return Row{(int64_t)n * g.Out}; }
+  __device__ uint4 vec_a(const Row &r, int k0, int koff) const { return *(const uint4 *)&dy[r.off + k0 + koff]; }
+  __device__ uint4 vec_b(const Row &r, int k0, int koff) const { return *(const uint4 *)&wt[r.off + k0 + koff]; }
   __device__ void store(int m, int n, float v, int) const {
     const size_t o = (size_t)m * g.In + n;
     if (x_act && !(bf2f(x_act[o]) > 0.f)) v = 0.f;
@@ -284,8 +368,7 @@ struct LinWgradOp {  // M = Out, N = In, K = B; split-K partials
   LinGeom g;
   const bf16 *dy, *x;
   float *part;
-  __device__ uint4 a_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
-  __device__ uint4 b_vec(int, int) const { return make_uint4(0, 0, 0, 0); }
+  struct Row {};
   __device__ uint4 a_vecT(int m, int b) const { return *(const uint4 *)&dy[(size_t)b * g.Out + m]; }
   __device__ uint4 b_vecT(int n, int b) const { return *(const uint4 *)&x[(size_t)b * g.In + n]; }
   __device__ void store(int m, int n, float v, int z) const {
@@ -419,14 +502,15 @@ k_conv1_wgrad(const bf16 *in, const bf16 *dpre, int B, int Hi, int Wi, int Cout,
 // global memory straight into registers.  The first layer's activation never
 // goes to HBM.
 // ---------------------------------------------------------------------------
-constexpr int C12_PY = 17, C12_PX = 33, C12_IY = 35, C12_IX = 67;
+constexpr int C12_PY = 17, C12_PX = 33, C12_IY = 35, C12_IX = 67, C12_PS = 36;
 
 __global__ void __launch_bounds__(256)
 k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, const float *b2,
              int H0, bf16 *out) {
   __shared__ float xin[C12_IY * C12_IX];
-  __shared__ float wl[9 * 32 + 32];               // [tap][c] then biases
-  __shared__ __attribute__((aligned(16))) bf16 a1[C12_PY * C12_PX * 32];  // [y][x][c]
+  // first-layer outputs [y][x][c], pixels C12_PS bf16 apart: 8 consecutive
+  // lanes read pixels 2 apart, which then fall on different banks
+  __shared__ __attribute__((aligned(16))) bf16 a1[C12_PY * C12_PX * C12_PS];
   const int H1 = H0 / 2, H2 = H1 / 2;
   const int tiles_x = H2 / 16;
   const int b = blockIdx.y;
@@ -440,18 +524,25 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
 #pragma unroll
   for (int t = 0; t < 9; ++t)
     bw[t] = *(const bf16x8 *)&w2[(size_t)(wv * 16 + (lane & 15)) * 288 + t * 32 + cq];
+  // a thread always computes first-layer channels [c0, c0 + 8): their
+  // weights and biases stay in registers
+  const int c0 = (tid & 3) * 8;
+  float wr[8][9], br[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    br[e] = b1 ? b1[c0 + e] : 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) wr[e][t] = bf2f(w1[(c0 + e) * 9 + t]);  // w1 [c][tap]
+  }
   // input patch rows 4 oy0 - 3 .., columns 4 ox0 - 3 ..
   const int iy0 = 4 * oy0 - 3, ix0 = 4 * ox0 - 3;
   for (int q = tid; q < C12_IY * C12_IX; q += 256) {
     const int yy = iy0 + q / C12_IX, xx = ix0 + q % C12_IX;
     xin[q] = (yy >= 0 && yy < H0 && xx >= 0 && xx < H0) ? bf2f(in0[((size_t)b * H0 + yy) * H0 + xx]) : 0.f;
   }
-  for (int q = tid; q < 9 * 32; q += 256) wl[(q % 9) * 32 + q / 9] = bf2f(w1[q]);  // w1 [c][tap]
-  for (int q = tid; q < 32; q += 256) wl[9 * 32 + q] = b1 ? b1[q] : 0.f;
   __syncthreads();
   // first layer at patch positions (y, x) = first-layer rows 2 oy0 - 1 + y, columns 2 ox0 - 1 + x
-  for (int task = tid; task < C12_PY * C12_PX * 4; task += 256) {
-    const int pos = task >> 2, c0 = (task & 3) * 8;
+  for (int pos = tid >> 2; pos < C12_PY * C12_PX; pos += 64) {
     const int y = pos / C12_PX, x = pos - y * C12_PX;
     const int y1 = 2 * oy0 - 1 + y, x1 = 2 * ox0 - 1 + x;
     Vec8 o;
@@ -463,13 +554,15 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
       for (int t = 0; t < 9; ++t) xv[t] = xin[(2 * y + t / 3) * C12_IX + 2 * x + t % 3];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        float acc = wl[9 * 32 + c0 + e];
+        float acc = br[e];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc = __fmaf_rn(wl[t * 32 + c0 + e], xv[t], acc);
+        for (int t = 0; t < 9; ++t) acc = __fmaf_rn(wr[e][t], xv[t], acc);
         o.h[e] = f2bf(fmaxf(acc, 0.f));
       }
     }
-    *(uint4 *)&a1[pos * 32 + c0] = o.u;
+    uint2 *dst = (uint2 *)&a1[pos * C12_PS + c0];
+    dst[0] = make_uint2(o.u.x, o.u.y);
+    dst[1] = make_uint2(o.u.z, o.u.w);
   }
   __syncthreads();
   // second layer: MFMA row tiles i = pixels [16 i, 16 i + 16) of the 8 x 16
@@ -483,7 +576,12 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int y = 2 * i + ky, x = 2 * (lane & 15) + kx;
-      const bf16x8 af = *(const bf16x8 *)&a1[(y * C12_PX + x) * 32 + cq];
+      const uint2 *src = (const uint2 *)&a1[(y * C12_PX + x) * C12_PS + cq];
+      Vec8 a;
+      const uint2 lo = src[0], hi = src[1];
+      a.u = make_uint4(lo.x, lo.y, hi.x, hi.y);
+      bf16x8 af;
+      __builtin_memcpy(&af, &a, 16);
       acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bw[tap], acc[i], 0, 0, 0);
     }
   }
@@ -672,7 +770,7 @@ static hipError_t launch_gemm(const Op &op, int M, int N, int K, int splits, hip
   int kchunk = K;
   if (splits > 1) {
     kchunk = (int)(((int64_t)K + splits - 1) / splits);
-    kchunk = (kchunk + BK - 1) / BK * BK;
+    kchunk = (kchunk + MK - 1) / MK * MK;
     splits = (K + kchunk - 1) / kchunk;
   }
   // larger tiles where there are enough of them to fill the chip
@@ -692,7 +790,7 @@ static hipError_t launch_gemm(const Op &op, int M, int N, int K, int splits, hip
 int wgrad_splits(int M, int N, int K) {
   const int tiles = (int)(cdiv_(M, 64) * cdiv_(N, 64));
   int s = (512 + tiles - 1) / tiles;
-  s = std::max(1, std::min(s, K / BK));
+  s = std::max(1, std::min(s, K / MK));
   return s;
 }
 
@@ -706,6 +804,7 @@ hipError_t conv_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int
   }
   ConvFwdOp op;
   op.g = {B, Hi, Wi, Cin, Hi / 2, Wi / 2, Cout};
+  op.tap_uniform = Cin % BK == 0;
   op.in = in; op.w = w; op.bias = bias; op.out = out; op.out32 = out32; op.relu = relu;
   return launch_gemm(op, B * (Hi / 2) * (Wi / 2), Cout, 9 * Cin, 1, st);
 }
@@ -723,6 +822,7 @@ hipError_t conv_dgrad(const bf16 *dout, const bf16 *wt, const bf16 *act_in, int 
                       int Cin, int Cout, bf16 *din, float *din32, hipStream_t st) {
   ConvDgradOp op;
   op.g = {B, Hi, Wi, Cin, Hi / 2, Wi / 2, Cout};
+  op.tap_uniform = Cout % BK == 0;
   op.dout = dout; op.wt = wt; op.act_in = act_in; op.din = din; op.din32 = din32;
   return launch_gemm(op, B * Hi * Wi, Cin, 9 * Cout, 1, st);
 }
@@ -748,7 +848,7 @@ hipError_t conv_wgrad(const bf16 *dout, const bf16 *in, int B, int Hi, int Wi, i
   while ((size_t)s * M * N > part_cap && s > 1) --s;
   if ((size_t)s * M * N > part_cap) return hipErrorInvalidValue;
   int kchunk = (K + s - 1) / s;
-  kchunk = (kchunk + BK - 1) / BK * BK;
+  kchunk = (kchunk + MK - 1) / MK * MK;
   s = (K + kchunk - 1) / kchunk;
   hipError_t e = launch_gemm(op, M, N, K, s, st);
   if (e != hipSuccess) return e;
@@ -783,7 +883,7 @@ hipError_t lin_wgrad(const bf16 *dy, const bf16 *x, int B, int In, int Out, floa
   while ((size_t)s * M * N > part_cap && s > 1) --s;
   if ((size_t)s * M * N > part_cap) return hipErrorInvalidValue;
   int kchunk = (K + s - 1) / s;
-  kchunk = (kchunk + BK - 1) / BK * BK;
+  kchunk = (kchunk + MK - 1) / MK * MK;
   s = (K + kchunk - 1) / kchunk;
   hipError_t e = launch_gemm(op, M, N, K, s, st);
   if (e != hipSuccess) return e;

@@ -12,7 +12,7 @@
 // G_Q = F^-1(H^ . F(G_X)) reuses the three passes; the row pass between the
 // two applications fuses the inverse rows of X, the residual X - Y, the
 // squared-error partial sums and the forward rows of G_X.
-#include "cs_internal.hpp"
+#include "cs_ctf_dev.hpp"
 
 namespace cs {
 
@@ -122,52 +122,6 @@ k_fft_rows_fwd(const float *src, FftPlan P, const float2 *tw, int B, float2 *spe
   const float2 *res = fft_team(x, y, P, twl, t, 64, false);
   float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
   split_store(res, L, t, sa, sa + Dh, valid);
-}
-
-// ---------------------------------------------------------------------------
-// CTF on the DFT grid.  Index k has frequency f(k)/(D p) with f(k) = k for
-// k < D/2 (k = D/2 maps to -D/2) and k - D above; the row frequency is
-// negated (y-flip of Eq. 13).  The Nyquist row/column value is the mean
-// over the two mirror frequencies, which keeps H^ exactly even.
-// ---------------------------------------------------------------------------
-__device__ double ctf_at(double sx, double sy, const CtfDev &c, double du, double dv,
-                         double c2a, double s2a, double ph) {
-  const double s2 = sx * sx + sy * sy;
-  double df = 0.5 * (du + dv);
-  if (s2 > 0.0 && du != dv) {
-    const double cos2 = (sx * sx - sy * sy) / s2, sin2 = 2.0 * sx * sy / s2;
-    df += 0.5 * (du - dv) * (cos2 * c2a + sin2 * s2a);
-  }
-  const double chi = M_PI * c.lam * df * s2 - 0.5 * M_PI * c.cs * c.lam * c.lam * c.lam * s2 * s2 - ph;
-  // phase in FP64, reduced to [-pi, pi] in FP64, then one FP32 sincos (about
-  // 1e-7 absolute in the CTF)
-  const double turns = chi * (0.5 / M_PI);
-  const float red = (float)((turns - rint(turns)) * (2.0 * M_PI));
-  float sn, cs;
-  sincosf(red, &sn, &cs);
-  double h = -(sqrt(1.0 - c.w * c.w) * (double)sn + c.w * (double)cs);
-  if (c.bfactor != 0.0) h *= exp(-0.25 * c.bfactor * s2);
-  return h;
-}
-
-__device__ float ctf_grid_value(int ky, int kx, int L, float pixel, const CtfDev &c, int b) {
-  const double du = c.defocus_u[b], dv = c.defocus_v[b];
-  const double a = c.astig ? (double)c.astig[b] : 0.0;
-  const double ph = c.phase ? (double)c.phase[b] : 0.0;
-  float s2f, c2f;
-  sincosf((float)(2.0 * a), &s2f, &c2f);
-  const double c2a = c2f, s2a = s2f;
-  const int half = L / 2;
-  const double inv = 1.0 / ((double)L * (double)pixel);
-  const int fkx = (kx < (L + 1) / 2) ? kx : kx - L;
-  const int fky = (ky < (L + 1) / 2) ? ky : ky - L;
-  const double sx = fkx * inv, sy = -fky * inv;
-  double h = ctf_at(sx, sy, c, du, dv, c2a, s2a, ph);
-  if ((L % 2 == 0) && (kx == half || ky == half)) {
-    const double mx = (kx == half) ? -sx : sx, my = (ky == half) ? -sy : sy;
-    h = 0.5 * (h + ctf_at(mx, my, c, du, dv, c2a, s2a, ph));
-  }
-  return (float)h;
 }
 
 // H^ / D^2 on the half-spectrum grid [B][D][D/2+1], once per call.

@@ -306,9 +306,11 @@ int cs_pose_batch_create(cs_ctx *ctx, int32_t D, float pixel, int32_t capacity,
   q->pixel = pixel;
   const size_t C = capacity, Dh = D / 2 + 1;
   size_t o = 0;
-  const size_t o_table = o; o += al256(C * q->F * 4);
-  const size_t o_spec = o;  o += al256(C * D * Dh * 8);
-  const size_t o_Z = o;     o += al256(C * q->npx * 4);
+  // the one-pass preparation at D = 128 needs no spectrum, table or Z buffers
+  const size_t CF = (D == kPrepD) ? 0 : C;
+  const size_t o_table = o; o += al256(CF * q->F * 4);
+  const size_t o_spec = o;  o += al256(CF * D * Dh * 8);
+  const size_t o_Z = o;     o += al256(CF * q->npx * 4);
   const size_t o_zs = o;    o += al256(C * q->S * q->npx * 2);
   const size_t o_zb = o;    o += al256(C * D * (D + 16) * 2);
   const size_t o_w = o;     o += al256(C * q->F8 * 2);
@@ -350,12 +352,20 @@ int cs_pose_batch_load(cs_pose_batch *q, const float *images, const cs_ctf *ctf,
   if (ctf && (!ctf->defocus_u || !ctf->defocus_v)) return fail(ctx, CS_ERR_INVALID_ARG, "null defocus");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  int rc = ctf_filter_into(ctx, q->D, q->pixel, images, ctf, P, q->table, q->spec, q->Z, st);
-  if (rc) return rc;
-  HIPCHK(pose_prep(images, q->Z, q->table, P, q->D, q->F8, q->zb, q->w, q->yy, st));
+  if (q->D == kPrepD) {
+    const float2 *tw = nullptr;
+    int rc = get_twiddles(ctx, q->D, &tw);
+    if (rc) return rc;
+    HIPCHK(pose_prep128(images, tw, q->pixel, make_ctf(ctf), P, q->F8, filtered, q->zb, q->w, q->yy,
+                        st));
+  } else {
+    int rc = ctf_filter_into(ctx, q->D, q->pixel, images, ctf, P, q->table, q->spec, q->Z, st);
+    if (rc) return rc;
+    HIPCHK(pose_prep(images, q->Z, q->table, P, q->D, q->F8, q->zb, q->w, q->yy, st));
+    if (filtered)
+      HIPCHK(hipMemcpyAsync(filtered, q->Z, (size_t)P * q->npx * 4, hipMemcpyDeviceToDevice, st));
+  }
   q->zs_valid = false;
-  if (filtered)
-    HIPCHK(hipMemcpyAsync(filtered, q->Z, (size_t)P * q->npx * 4, hipMemcpyDeviceToDevice, st));
   q->P = P;
   return CS_OK;
 }

@@ -200,3 +200,47 @@ def test_batch_api_matches_convenience_calls_and_filter(gpu_lib):
     assert max(normwise(host(F)[b], HY[b]) for b in range(5)) <= 1e-5
     bank.close()
     batch.close()
+
+
+@pytest.mark.parametrize("use_ctf", [True, False])
+def test_one_pass_preparation_d128_matches_oracle(gpu_lib, use_ctf):
+    """At D = 128 a batch is prepared in one pass per particle (2-D FFT, CTF
+    and inverse in LDS): the filtered images, and through the scores the
+    energy weights, ||Y||^2 and the padded -2 Z rows, against the oracle."""
+    announce(f"one-pass particle preparation at D=128 (ctf={use_ctf})")
+    rng = np.random.default_rng(905 + int(use_ctf))
+    g = inputs.mixture_anisotropic(rng, 60, 10.0)
+    D, pixel = 128, 1.5
+    G = o_pose.grid(1, 4).astype(np.float32)
+    P = 3
+    v, Y = _particles(g, P, D, pixel, rng, shift_px=[[0, 0], [1, -1], [-1, 0]],
+                      q_cut=model.Q_FAITHFUL)
+    ctf = ctf_arg(v) if use_ctf else None
+    bank = gpu_lib.pose_bank(**mixture_args(g), rot=dev(G), n_psi=4, D=D, pixel=pixel)
+    batch = gpu_lib.pose_batch(D, pixel, P, shift_radius=1)
+    Z = torch.empty(P, D, D, device="cuda")
+    batch.load(dev(Y), ctf, filtered=Z)
+    out = batch.search(bank, want_scores=True)
+    torch.cuda.synchronize()
+    from oracle import ctf as o_ctf
+    HY = (o_ctf.apply_ctf(Y.astype(np.float64), o_ctf.ctf_grid_for(v)) if use_ctf
+          else Y.astype(np.float64))
+    zerr = max(normwise(host(Z)[b], HY[b]) for b in range(P))
+    announce(f"  filtered images: normwise {zerr:.2e}")
+    assert zerr <= 1e-5
+    scores = host(out["scores"])
+    for p in range(P):
+        ref = o_pose.scores(g, Y[p], v.subset([p]), _f64(G), 1, q_cut=model.Q_FAITHFUL,
+                            use_ctf=use_ctf)
+        bound = (_bf16_bound(g, Y[p], v.subset([p]), _f64(G), 1) if use_ctf else
+                 None)
+        err = np.abs(scores[p] - ref)
+        if bound is not None:
+            announce(f"  particle {p}: max |err| / bound = {np.max(err / bound):.3f}")
+            assert np.all(err <= bound), p
+        else:
+            announce(f"  particle {p}: normwise {normwise(scores[p], ref):.2e}")
+            assert normwise(scores[p], ref) <= TOL, p
+        assert float(out["score"][p]) == scores[p].min()
+    bank.close()
+    batch.close()
