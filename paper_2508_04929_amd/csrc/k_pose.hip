@@ -51,13 +51,14 @@ __device__ __forceinline__ float ord_float(unsigned o) {
 // where Z = H Y and table = H^ / D^2 (the CTF table of the FFT kernels).
 // ---------------------------------------------------------------------------
 // 8 consecutive bfloat16 starting at element c of a dword-aligned row.
+// Branch-free: five dword reads and a funnel shift by 0 or 16 bits (the row
+// holds at least c / 2 + 5 dwords).
 __device__ __forceinline__ uint4 load8_at(const unsigned *row, int c) {
   const int d = c >> 1;
+  const unsigned sh = (unsigned)(c & 1) << 4;
   const unsigned w0 = row[d], w1 = row[d + 1], w2 = row[d + 2], w3 = row[d + 3], w4 = row[d + 4];
-  if (c & 1)
-    return make_uint4(__builtin_amdgcn_alignbit(w1, w0, 16), __builtin_amdgcn_alignbit(w2, w1, 16),
-                      __builtin_amdgcn_alignbit(w3, w2, 16), __builtin_amdgcn_alignbit(w4, w3, 16));
-  return make_uint4(w0, w1, w2, w3);
+  return make_uint4(__builtin_amdgcn_alignbit(w1, w0, sh), __builtin_amdgcn_alignbit(w2, w1, sh),
+                    __builtin_amdgcn_alignbit(w3, w2, sh), __builtin_amdgcn_alignbit(w4, w3, sh));
 }
 
 // zb[p][i][t] = bfloat16(-2 Z[p][i][(t - 8) mod D]), rows of D + 16 (8 columns
@@ -367,11 +368,14 @@ __global__ void __launch_bounds__(256) k_pose_gemm(PoseGemmArgs a) {
 // synchronise after the LDS fill.  Value = acc + ||Y||^2; 64-bit atomicMin of
 // (score, bank row x S + s) per particle.
 // ---------------------------------------------------------------------------
-template <int PF, int KSPLIT>
+template <int PF, int KSPLIT, bool A32>
 __global__ void __launch_bounds__(256) k_pose_refine_z(PoseRefineArgs a) {
   extern __shared__ unsigned lz[];
   constexpr int NG = 4 / KSPLIT;  // candidate groups of 16 per block
-  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // the wave index is uniform across the wave: in a scalar register, so that
+  // the K-range bounds below and the branches on them are scalar
+  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int cg = wv / KSPLIT, kp = wv % KSPLIT;
   const int D = a.D, RS = D + 16;
   const int zdw = D * RS / 2, wdw = a.F8 / 2;
@@ -388,16 +392,18 @@ __global__ void __launch_bounds__(256) k_pose_refine_z(PoseRefineArgs a) {
     if (brow < 0 || brow >= a.nrows) brow = -1;
   }
   const int kq = (lane >> 4) * 8;
+  // a skipped candidate reads bank row 0 (its sums are never used), which
+  // keeps the loads free of divergent branches
   const unsigned short *bp = a.bank + (brow < 0 ? 0 : brow * a.ldb) + kq;
   const int side = 2 * a.r + 1;
+  // lanes of shift rows s >= S read the unshifted particle; their sums are
+  // never used
   int dx[2], dy[2];
-  bool rv[2];
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
     const int s = f * 16 + (lane & 15);
-    rv[f] = s < a.S;
-    dy[f] = rv[f] ? s / side - a.r : 0;
-    dx[f] = rv[f] ? s % side - a.r : 0;
+    dy[f] = s < a.S ? s / side - a.r : 0;
+    dx[f] = s < a.S ? s % side - a.r : 0;
   }
   const int nsl_all = (a.npx + a.F8) / 32, npsl = a.npx / 32;
   // this wave's part of the K slices
@@ -406,47 +412,86 @@ __global__ void __launch_bounds__(256) k_pose_refine_z(PoseRefineArgs a) {
   uint4 q[PF];
 #pragma unroll
   for (int u = 0; u < PF; ++u)
-    q[u] = (brow >= 0 && ks0 + u < ks1) ? *(const uint4 *)(bp + (size_t)(ks0 + u) * 32) : zero;
+    q[u] = (ks0 + u < ks1) ? *(const uint4 *)(bp + (size_t)(ks0 + u) * 32) : zero;
   f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
-  const int e0 = ks0 * 32 + kq;
-  int i = e0 / D, j = e0 - (e0 / D) * D;  // image row / column of this lane's 8 pixels
-  for (int k0 = ks0; k0 < ks1; k0 += PF) {
+  // A operand of a pixel slice: 8 pixels of image row i, columns j .. j + 7,
+  // shifted by (dy, dx) = dword address ad[f] into the padded rows and a
+  // funnel shift sh[f] (the column parity never changes: j moves by 32 or by
+  // -D, both even); the addresses move along with j instead of being
+  // recomputed.  With D a multiple of 32 every lane changes row at the same
+  // slice (a scalar countdown); otherwise each lane checks its own column.
+  const int e0 = min(ks0, npsl) * 32 + kq;
+  int j = e0 % D;
+  int cs = (D - (e0 - kq) % D) / 32;  // slices left in the current row (A32)
+  int ad[2], si[2];
+  unsigned sh[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    si[f] = (e0 / D - dy[f] + D) % D;
+    const int c = j + dx[f] + 8;
+    sh[f] = (unsigned)(c & 1) << 4;
+    ad[f] = si[f] * (RS / 2) + (c >> 1);
+  }
+  const unsigned *lw = lz + zdw;
+  auto next_row = [&](int f) {
+    ad[f] += RS / 2 - D / 2;
+    if (++si[f] == D) {
+      si[f] = 0;
+      ad[f] -= D * (RS / 2);
+    }
+  };
+  auto step = [&](int ks, const uint4 &b) {
+    uint4 av[2];
+    if (ks < npsl) {
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const unsigned *r = lz + ad[f];
+        const unsigned w0 = r[0], w1 = r[1], w2 = r[2], w3 = r[3], w4 = r[4];
+        av[f] = make_uint4(__builtin_amdgcn_alignbit(w1, w0, sh[f]), __builtin_amdgcn_alignbit(w2, w1, sh[f]),
+                           __builtin_amdgcn_alignbit(w3, w2, sh[f]), __builtin_amdgcn_alignbit(w4, w3, sh[f]));
+        ad[f] += 16;
+      }
+      if (A32) {
+        if (--cs == 0) {
+          cs = D / 32;
+#pragma unroll
+          for (int f = 0; f < 2; ++f) next_row(f);
+        }
+      } else {
+        // D >= 16: at most two row changes per slice
+        j += 32;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          if (j >= D) {
+            j -= D;
+#pragma unroll
+            for (int f = 0; f < 2; ++f) next_row(f);
+          }
+      }
+    } else {
+      av[0] = av[1] = ((const uint4 *)lw)[((ks - npsl) * 32 + kq) >> 3];
+    }
+    bf16x8_t bb, a0, a1;
+    __builtin_memcpy(&bb, &b, 16);
+    __builtin_memcpy(&a0, &av[0], 16);
+    __builtin_memcpy(&a1, &av[1], 16);
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb, acc[1], 0, 0, 0);
+  };
+  // full groups of PF slices: no bounds checks; then the tail
+  int k0 = ks0;
+  for (; k0 + PF <= ks1; k0 += PF) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int ks = k0 + u;
-      if (ks < ks1) {
-        const uint4 b = q[u];
-        if (ks + PF < ks1) q[u] = (brow >= 0) ? *(const uint4 *)(bp + (size_t)(ks + PF) * 32) : zero;
-        uint4 av[2];
-        if (ks < npsl) {
-#pragma unroll
-          for (int f = 0; f < 2; ++f) {
-            av[f] = zero;
-            if (rv[f]) {
-              int si = i - dy[f];
-              si += (si < 0) ? D : 0;
-              si -= (si >= D) ? D : 0;
-              av[f] = load8_at(lz + (size_t)si * (RS / 2), j + dx[f] + 8);
-            }
-          }
-          j += 32;
-          while (j >= D) {
-            j -= D;
-            ++i;
-          }
-        } else {
-          const int e2 = (ks - npsl) * 32 + kq;
-          av[0] = av[1] = ((const uint4 *)(lz + zdw))[e2 >> 3];
-        }
-        bf16x8_t bb, a0, a1;
-        __builtin_memcpy(&bb, &b, 16);
-        __builtin_memcpy(&a0, &av[0], 16);
-        __builtin_memcpy(&a1, &av[1], 16);
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bb, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bb, acc[1], 0, 0, 0);
-      }
+      const uint4 b = q[u];
+      if (ks + PF < ks1) q[u] = *(const uint4 *)(bp + (size_t)(ks + PF) * 32);
+      step(ks, b);
     }
   }
+#pragma unroll
+  for (int u = 0; u < PF; ++u)
+    if (k0 + u < ks1) step(k0 + u, q[u]);
   if (KSPLIT > 1) {
     // partial sums of the K parts, added in part order (deterministic); the
     // particle's LDS rows are no longer read after this barrier
@@ -578,7 +623,10 @@ hipError_t pose_refine_z(const PoseRefineArgs &a, int P, hipStream_t st) {
   // range: the gathered rows are the traffic, and four independent streams
   // per block keep more of them in flight
   const size_t lds = pose_refine_z_lds(a.D, a.F8);
-  hipLaunchKernelGGL((k_pose_refine_z<16, 4>), dim3(P, pcdiv(a.L, 16)), dim3(256), lds, st, a);
+  if (a.D % 32 == 0)
+    hipLaunchKernelGGL((k_pose_refine_z<16, 4, true>), dim3(P, pcdiv(a.L, 16)), dim3(256), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_pose_refine_z<16, 4, false>), dim3(P, pcdiv(a.L, 16)), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 

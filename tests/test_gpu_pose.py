@@ -90,11 +90,14 @@ def test_grid_search_scores_match_oracle(gpu_lib):
     bank.close()
 
 
-def test_refine_explicit_candidates_match_grid_scores(gpu_lib):
-    announce("refine with explicit candidate lists")
+@pytest.mark.parametrize("D", [48, 64])
+def test_refine_explicit_candidates_match_grid_scores(gpu_lib, D):
+    """D = 48: each lane tracks its own image row; D = 64 (a multiple of 32):
+    all lanes change row together."""
+    announce(f"refine with explicit candidate lists, D={D}")
     rng = np.random.default_rng(901)
     g = inputs.mixture_anisotropic(rng, 400, 12.0)
-    D, pixel = 48, 1.5
+    pixel = 1.5
     G = o_pose.grid(1, 8).astype(np.float32)
     P, L = 4, 40
     v, Y = _particles(g, P, D, pixel, rng)
