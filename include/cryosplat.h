@@ -264,6 +264,13 @@ int cs_cnn_set_params(cs_cnn *net, const float *src, void *stream);
 int cs_cnn_forward(cs_cnn *net, const float *images, int32_t B, float *rot, float *shift,
                    float *raw, void *stream);
 
+/* Inference from an input already standardised per image, bfloat16 [B][D][D]
+ * (as cs_pose_batch_load writes it): cs_cnn_forward without its
+ * standardisation step; the input stays the caller's (cs_cnn_tensor index 0
+ * is not stored). */
+int cs_cnn_forward_std(cs_cnn *net, const uint16_t *x, int32_t B, float *rot, float *shift,
+                       float *raw, void *stream);
+
 /* One training step: forward, loss (written to loss[0], device), backward
  * through every layer, then (apply_update != 0) one Adam step with
  * (beta1, beta2, eps) = (0.9, 0.999, 1e-8) and learning rate lr on all
@@ -396,14 +403,18 @@ int cs_pose_refine(cs_pose_bank *bank, const float *images, const cs_ctf *ctf, i
  * and 3, <= 512), shift radius 0 <= r <= 4; device memory about
  * capacity * D^2 * (2 (2r+1)^2 + 18) bytes.  load: P <= capacity images
  * [P][D][D] with per-particle CTF parameters (ctf NULL = no CTF); filtered
- * (may be NULL) receives Z [P][D][D] FP32.  A batch is reused by later
+ * (may be NULL) receives Z [P][D][D] FP32; standardized (may be NULL)
+ * receives Z standardised per image, (Z - mean) / std as bfloat16 [P][D][D],
+ * the input of cs_cnn_forward_std (at D = 128 the mean and variance come
+ * from the spectrum by Parseval's identity, so they can differ from a
+ * two-pass computation in the last bits).  A batch is reused by later
  * loads; searches use the last load. */
 typedef struct cs_pose_batch cs_pose_batch;
 int cs_pose_batch_create(cs_ctx *ctx, int32_t D, float pixel, int32_t capacity,
                          int32_t shift_radius, cs_pose_batch **out);
 void cs_pose_batch_destroy(cs_pose_batch *batch);
 int cs_pose_batch_load(cs_pose_batch *batch, const float *images, const cs_ctf *ctf, int32_t P,
-                       float *filtered, void *stream);
+                       float *filtered, uint16_t *standardized, void *stream);
 /* cs_pose_grid_search / cs_pose_refine on a loaded batch (same outputs;
  * the batch's shift radius applies). */
 int cs_pose_batch_search(cs_pose_bank *bank, cs_pose_batch *batch, int32_t *best_rot,

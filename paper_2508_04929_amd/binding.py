@@ -63,7 +63,7 @@ EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_b
            "cs_loss_and_grad", "cs_loss_and_grad_multi", "cs_autotune", "cs_adam_step",
            "cs_pair_count", "cs_set_timing", "cs_stage_time",
            "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_param_count", "cs_cnn_get_params",
-           "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_train_step",
+           "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_forward_std", "cs_cnn_train_step",
            "cs_bf16_conv3x3s2_forward", "cs_bf16_conv3x3s2_dgrad", "cs_bf16_conv3x3s2_wgrad",
            "cs_bf16_linear_forward", "cs_bf16_linear_dgrad", "cs_bf16_linear_wgrad",
            "cs_pose_head", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_destroy",
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_cnn_get_params.argtypes = [vp, vp, vp]
     lib.cs_cnn_set_params.argtypes = [vp, vp, vp]
     lib.cs_cnn_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.cs_cnn_forward_std.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.cs_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, f32, f32, vp, vp, i32, vp]
     lib.cs_bf16_conv3x3s2_forward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, vp,
                                               vp]
@@ -144,7 +145,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_pose_batch_create.argtypes = [vp, i32, f32, i32, i32, P(vp)]
     lib.cs_pose_batch_destroy.argtypes = [vp]
     lib.cs_pose_batch_destroy.restype = None
-    lib.cs_pose_batch_load.argtypes = [vp, vp, P(CsCtf), i32, vp, vp]
+    lib.cs_pose_batch_load.argtypes = [vp, vp, P(CsCtf), i32, vp, vp, vp]
     lib.cs_pose_batch_search.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.cs_pose_batch_refine.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
@@ -754,15 +755,20 @@ class PoseBatch:
     def _s(self):
         return torch.cuda.current_stream(self.device).cuda_stream
 
-    def load(self, images, ctf=None, filtered=None):
-        """Prepare P images; filtered [P][D][D] (optional) receives Z = H Y."""
+    def load(self, images, ctf=None, filtered=None, standardized=None):
+        """Prepare P images; filtered [P][D][D] FP32 (optional) receives Z = H Y,
+        standardized [P][D][D] bfloat16 (optional) the network input (Z
+        standardised per image)."""
         P = images.shape[0]
         _ptr(images, "images", self.device, (P, self.D, self.D))
         _ptr(filtered, "filtered", self.device, (P, self.D, self.D))
+        _ptr(standardized, "standardized", self.device, (P, self.D, self.D), torch.bfloat16)
         c = _ctf_struct(ctf, P, self.device)
         self.owner._check(self.ctx, self.lib.cs_pose_batch_load(
             self.h, images.data_ptr(), None if c is None else ctypes.byref(c), P,
-            None if filtered is None else filtered.data_ptr(), self._s()), "cs_pose_batch_load")
+            None if filtered is None else filtered.data_ptr(),
+            None if standardized is None else standardized.data_ptr(), self._s()),
+            "cs_pose_batch_load")
         self.P = P
         return filtered
 
@@ -851,6 +857,19 @@ class Network:
                                                             rot.data_ptr(), shift.data_ptr(),
                                                             raw.data_ptr(), self._s()),
                           "cs_cnn_forward")
+        return rot, shift, raw
+
+    def forward_standardized(self, x):
+        """Inference from a standardised bfloat16 input [B][D][D] (PoseBatch.load)."""
+        B = x.shape[0]
+        _ptr(x, "x", self.device, (B, self.D, self.D), torch.bfloat16)
+        rot = torch.empty(B, 3, 3, device=self.device)
+        shift = torch.empty(B, 2, device=self.device)
+        raw = torch.empty(B, 8, device=self.device)
+        self.owner._check(self.ctx, self.lib.cs_cnn_forward_std(self.h, x.data_ptr(), B,
+                                                                rot.data_ptr(), shift.data_ptr(),
+                                                                raw.data_ptr(), self._s()),
+                          "cs_cnn_forward_std")
         return rot, shift, raw
 
     def tensor(self, index: int, grad: bool, shape):

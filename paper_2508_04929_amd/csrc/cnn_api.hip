@@ -47,6 +47,7 @@ struct cs_cnn {
   int64_t step = 0;
   int last_B = 0;
   bool act1_valid = false;  // the first layer's activation is stored by training steps only
+  bool act0_valid = false;  // the standardised input is stored unless it came from the caller
   std::vector<size_t> elems;  // per-image elements of act[i] / dact[i]
   std::vector<void *> allocs;
 };
@@ -90,13 +91,17 @@ int refresh_bf16(cs_cnn *net, hipStream_t st) {
 
 // fused: inference, the first two convolutions in one kernel (the first
 // layer's activation is not stored; training steps need it and run unfused)
-int forward_layers(cs_cnn *net, const float *images, int B, hipStream_t st, bool fused = false) {
+// x0: an already standardised bfloat16 input (fused inference only), used in
+// place of the standardisation step.
+int forward_layers(cs_cnn *net, const float *images, int B, hipStream_t st, bool fused = false,
+                   const bf16 *x0 = nullptr) {
   cs_ctx *ctx = net->ctx;
-  HIPCHK(standardize(images, B, net->D * net->D, net->act[0], st));
+  if (!x0) HIPCHK(standardize(images, B, net->D * net->D, net->act[0], st));
+  net->act0_valid = x0 == nullptr;
   size_t l0 = 0;
   if (fused) {
     const Layer &L1 = net->layers[0], &L2 = net->layers[1];
-    HIPCHK(conv12_fwd(net->act[0], net->wbuf + L1.wb_off, net->param + L1.b_off,
+    HIPCHK(conv12_fwd(x0 ? x0 : net->act[0], net->wbuf + L1.wb_off, net->param + L1.b_off,
                       net->wbuf + L2.wb_off, net->param + L2.b_off, B, net->D, net->act[2], st));
     l0 = 2;
   }
@@ -265,6 +270,23 @@ int cs_cnn_forward(cs_cnn *net, const float *images, int32_t B, float *rot, floa
   return CS_OK;
 }
 
+int cs_cnn_forward_std(cs_cnn *net, const uint16_t *x, int32_t B, float *rot, float *shift,
+                       float *raw, void *stream) {
+  if (!net) return CS_ERR_INVALID_ARG;
+  cs_ctx *ctx = net->ctx;
+  if (!x || !rot) return fail(ctx, CS_ERR_INVALID_ARG, "null input or rot");
+  if (B < 1 || B > net->max_batch) return fail(ctx, CS_ERR_INVALID_ARG, "batch must be in [1, max_batch]");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  int rc = forward_layers(net, nullptr, B, st, true, x);
+  if (rc) return rc;
+  net->last_B = B;
+  net->act1_valid = false;
+  HIPCHK(head(net->out8, B, rot, shift, st));
+  if (raw) HIPCHK(hipMemcpyAsync(raw, net->out8, (size_t)B * 8 * 4, hipMemcpyDeviceToDevice, st));
+  return CS_OK;
+}
+
 int cs_cnn_train_step(cs_cnn *net, const float *images, const float *rot_target,
                       const float *shift_target, int32_t B, float lambda, float lr, float *loss,
                       float *grads_out, int32_t apply_update, void *stream) {
@@ -325,6 +347,8 @@ int cs_cnn_tensor(cs_cnn *net, int32_t index, int32_t grad, uint16_t *dst, int64
   if (n == 0) return fail(ctx, CS_ERR_INVALID_ARG, "no forward pass yet");
   if (index == 1 && !grad && !net->act1_valid)
     return fail(ctx, CS_ERR_INVALID_ARG, "inference does not store the first layer's activation");
+  if (index == 0 && !grad && !net->act0_valid)
+    return fail(ctx, CS_ERR_INVALID_ARG, "the last forward took its standardised input from the caller");
   if (capacity < n) return fail(ctx, CS_ERR_INVALID_ARG, "capacity %lld < %lld", (long long)capacity, (long long)n);
   HIPCHK(hipMemcpyAsync(dst, grad ? net->dact[index] : net->act[index], n * 2, hipMemcpyDeviceToDevice,
                         (hipStream_t)stream));

@@ -49,11 +49,12 @@ struct PoseRefineArgs {
 };
 
 // One-pass preparation at D = kPrepD (k_pose_prep.hip): Z = H Y (written
-// when Z is not null), the padded -2 Z rows, the energy weights and ||Y||^2.
+// when Z is not null), Z standardised per image as bfloat16 (when zs is not
+// null), the padded -2 Z rows, the energy weights and ||Y||^2.
 constexpr int kPrepD = 128;
 hipError_t pose_prep128(const float *Y, const float2 *tw, float pixel, const CtfDev &ctf, int P,
-                        int F8, float *Z, unsigned short *zb, unsigned short *w, float *yy,
-                        hipStream_t st);
+                        int F8, float *Z, unsigned short *zs, unsigned short *zb,
+                        unsigned short *w, float *yy, hipStream_t st);
 hipError_t pose_prep(const float *Y, const float *Z, const float *table, int P, int D, int F8,
                      unsigned short *zb, unsigned short *w, float *yy, hipStream_t st);
 hipError_t pose_shifts(const unsigned short *zb, int P, int D, int r, unsigned short *zs,

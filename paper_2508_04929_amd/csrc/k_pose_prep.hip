@@ -3,7 +3,8 @@
 // (App. A.2, Eq. 14), -2 Z as bfloat16 rows with 8 wrapped columns on each
 // side, the energy weights w_f H^2 / D^2 of the Parseval sum (bfloat16) and
 // ||Y||^2 (the terms of the squared error of Sec. 3.3.5 that do not depend
-// on the pose).
+// on the pose), and optionally the pose network's input: Z standardised per
+// image, its mean and variance taken from the spectrum (Parseval).
 //
 // The half spectrum (128 rows x 64 complex, row stride 65 so that column
 // accesses spread over the LDS banks) stays in LDS for the whole 2-D
@@ -233,10 +234,10 @@ __device__ __forceinline__ unsigned short energy_weight(float h, int kx) {
 
 __global__ void __launch_bounds__(256)
 k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8, float *Z,
-               unsigned short *zb, unsigned short *w, float *yy) {
+               unsigned short *zs, unsigned short *zb, unsigned short *w, float *yy) {
   __shared__ float2 sp[kN * kRS];
   __shared__ float2 twl[kN];
-  __shared__ double red[4];
+  __shared__ double red[4], pred[4], dcs;
   const int p = blockIdx.x, tid = threadIdx.x;
   const int wv = tid >> 6, g = (tid >> 3) & 7, q = tid & 7;
   if (tid < kN) twl[tid] = tw[tid];
@@ -294,6 +295,9 @@ k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8
   __syncthreads();
 
   // columns: forward, CTF multiply (energy weights on the way), inverse
+  // sum over the full spectrum of |Z^|^2 (half spectrum, kx = 1..63 twice)
+  // and the DC value: the mean and variance of Z by Parseval
+  double pw = 0.0;
   PrepCtf H;
   H.init(ctf, p, pixel);
   unsigned short *wp = w + (size_t)p * F8;
@@ -317,7 +321,9 @@ k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8
         const int ky = q + 8 * i;
         const float h = H.h(ky, kx);
         const float2 X = sl[ky];
-        sl[ky] = make_float2(X.x * h, X.y * h);
+        const float2 Xh = make_float2(X.x * h, X.y * h);
+        sl[ky] = Xh;
+        pw += 2.0 * ((double)Xh.x * Xh.x + (double)Xh.y * Xh.y);
         wp[ky * (kN / 2 + 1) + kx] = energy_weight(h, kx);
       }
     } else {
@@ -336,6 +342,9 @@ k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8
         const float2 Bv = make_float2(0.5f * (X.y + Xm.y) * h64, -0.5f * (X.x - Xm.x) * h64);
         sl[ky] = make_float2(A.x - Bv.y, A.y + Bv.x);
         sl[km] = make_float2(A.x + Bv.y, -A.y + Bv.x);
+        pw += (km != ky ? 2.0 : 1.0) *
+              ((double)A.x * A.x + (double)A.y * A.y + (double)Bv.x * Bv.x + (double)Bv.y * Bv.y);
+        if (ky == 0) dcs = A.x;
         wp[ky * (kN / 2 + 1)] = energy_weight(h0, 0);
         wp[ky * (kN / 2 + 1) + kN / 2] = energy_weight(h64, kN / 2);
         if (km != ky) {
@@ -355,7 +364,15 @@ k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8
     for (int n1 = 0; n1 < 16; ++n1) sl.nat(8 * n1 + q) = v[n1];
   }
   for (int f = kN * (kN / 2 + 1) + tid; f < F8; f += 256) wp[f] = 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pw += __shfl_xor(pw, o, 64);
+  if ((tid & 63) == 0) pred[wv] = pw;
   __syncthreads();
+  // standardisation of Z (as the network's input step): mean = Z^(0, 0),
+  // variance = sum |Z^|^2 - mean^2
+  const double zm = dcs, zv = (pred[0] + pred[1] + pred[2] + pred[3]) - zm * zm;
+  const float zmf = (float)zm, zinv = zv > 0.0 ? (float)(1.0 / sqrt(zv)) : 1.f;
+  unsigned short *sp0 = zs ? zs + (size_t)p * kN * kN : nullptr;
 
   // inverse rows: C[k] = A[k] + i B[k] from the spectrum rows (2j, 2j+1)
   float *zp = Z ? Z + (size_t)p * kN * kN : nullptr;
@@ -399,6 +416,10 @@ k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8
         zp[(2 * j) * kN + n] = z.x;
         zp[(2 * j + 1) * kN + n] = z.y;
       }
+      if (sp0) {
+        sp0[(2 * j) * kN + n] = bf16_rne((z.x - zmf) * zinv);
+        sp0[(2 * j + 1) * kN + n] = bf16_rne((z.y - zmf) * zinv);
+      }
       const unsigned short b0 = bf16_rne(-2.f * z.x), b1 = bf16_rne(-2.f * z.y);
       o0[n + 8] = b0;
       o1[n + 8] = b1;
@@ -417,10 +438,10 @@ k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8
 }  // namespace
 
 hipError_t pose_prep128(const float *Y, const float2 *tw, float pixel, const CtfDev &ctf, int P,
-                        int F8, float *Z, unsigned short *zb, unsigned short *w, float *yy,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_pose_prep128, dim3(P), dim3(256), 0, st, Y, tw, pixel, ctf, F8, Z, zb, w,
-                     yy);
+                        int F8, float *Z, unsigned short *zs, unsigned short *zb, unsigned short *w,
+                        float *yy, hipStream_t st) {
+  hipLaunchKernelGGL(k_pose_prep128, dim3(P), dim3(256), 0, st, Y, tw, pixel, ctf, F8, Z, zs, zb,
+                     w, yy);
   return hipGetLastError();
 }
 

@@ -344,7 +344,7 @@ void cs_pose_batch_destroy(cs_pose_batch *q) {
 }
 
 int cs_pose_batch_load(cs_pose_batch *q, const float *images, const cs_ctf *ctf, int32_t P,
-                       float *filtered, void *stream) {
+                       float *filtered, uint16_t *standardized, void *stream) {
   if (!q) return CS_ERR_INVALID_ARG;
   cs_ctx *ctx = q->ctx;
   if (!images) return fail(ctx, CS_ERR_INVALID_ARG, "null images");
@@ -356,14 +356,15 @@ int cs_pose_batch_load(cs_pose_batch *q, const float *images, const cs_ctf *ctf,
     const float2 *tw = nullptr;
     int rc = get_twiddles(ctx, q->D, &tw);
     if (rc) return rc;
-    HIPCHK(pose_prep128(images, tw, q->pixel, make_ctf(ctf), P, q->F8, filtered, q->zb, q->w, q->yy,
-                        st));
+    HIPCHK(pose_prep128(images, tw, q->pixel, make_ctf(ctf), P, q->F8, filtered, standardized,
+                        q->zb, q->w, q->yy, st));
   } else {
     int rc = ctf_filter_into(ctx, q->D, q->pixel, images, ctf, P, q->table, q->spec, q->Z, st);
     if (rc) return rc;
     HIPCHK(pose_prep(images, q->Z, q->table, P, q->D, q->F8, q->zb, q->w, q->yy, st));
     if (filtered)
       HIPCHK(hipMemcpyAsync(filtered, q->Z, (size_t)P * q->npx * 4, hipMemcpyDeviceToDevice, st));
+    if (standardized) HIPCHK(standardize(q->Z, P, q->npx, standardized, st));
   }
   q->zs_valid = false;
   q->P = P;
@@ -490,7 +491,8 @@ int cs_pose_grid_search(cs_pose_bank *b, const float *images, const cs_ctf *ctf,
     const int Pc = std::min(kParticleChunk, P - p0);
     cs_ctf c{};
     if (ctf) c = ctf_offset(ctf, p0);
-    rc = cs_pose_batch_load(q, images + (size_t)p0 * b->npx, ctf ? &c : nullptr, Pc, nullptr, stream);
+    rc = cs_pose_batch_load(q, images + (size_t)p0 * b->npx, ctf ? &c : nullptr, Pc, nullptr, nullptr,
+                            stream);
     if (rc) return rc;
     rc = cs_pose_batch_search(b, q, best_rot + p0, best_shift ? best_shift + p0 : nullptr,
                               best_score ? best_score + p0 : nullptr,
@@ -515,7 +517,8 @@ int cs_pose_refine(cs_pose_bank *b, const float *images, const cs_ctf *ctf, int3
     const int Pc = std::min(kParticleChunk, P - p0);
     cs_ctf c{};
     if (ctf) c = ctf_offset(ctf, p0);
-    rc = cs_pose_batch_load(q, images + (size_t)p0 * b->npx, ctf ? &c : nullptr, Pc, nullptr, stream);
+    rc = cs_pose_batch_load(q, images + (size_t)p0 * b->npx, ctf ? &c : nullptr, Pc, nullptr, nullptr,
+                            stream);
     if (rc) return rc;
     rc = cs_pose_batch_refine(b, q, proposal ? proposal + 9 * (size_t)p0 : nullptr, n_dir, n_psi_c,
                               cand ? cand + (size_t)p0 * L : nullptr, best_rot + p0,

@@ -108,13 +108,19 @@ class Stage:
 
 
 def learned_poses(lib, net: binding.Network, batch: binding.PoseBatch, images, ctf: binding.Ctf,
-                  stages: Sequence[Stage], rots: Sequence[torch.Tensor], zbuf: torch.Tensor,
+                  stages: Sequence[Stage], rots: Sequence[torch.Tensor], xbuf: torch.Tensor,
                   matched_filter: bool = True):
     """Prepare the particles once, network proposal (on Z = H Y with
-    matched_filter), then the refinement stages on the prepared batch.
+    matched_filter: the batch writes the standardised bfloat16 network input
+    into xbuf [P][D][D] as it prepares the particles), then the refinement
+    stages on the prepared batch.
     Returns (rot [P][3][3], shift index [P], proposal [P][3][3])."""
-    batch.load(images, ctf, filtered=zbuf if matched_filter else None)
-    W0, _, _ = net.forward(zbuf if matched_filter else images)
+    if matched_filter:
+        batch.load(images, ctf, standardized=xbuf)
+        W0, _, _ = net.forward_standardized(xbuf)
+    else:
+        batch.load(images, ctf)
+        W0, _, _ = net.forward(images)
     W, out = W0, None
     for i, st in enumerate(stages):
         out = batch.refine(st.bank, proposal=W, n_dir=st.n_dir, n_psi_c=st.n_psi_c)
@@ -199,7 +205,7 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
     imgs = render_particles(lib, gd, ps_te, 0, n_test, snr_db, seed + 1000)
     chunk = min(chunk, n_test)
     pb = lib.pose_batch(D, pixel, chunk, shift_radius)
-    zbuf = torch.empty(chunk, D, D, device=dev)
+    xbuf = torch.empty(chunk, D, D, device=dev, dtype=torch.bfloat16)
 
     def grid_all():
         return torch.cat([grid_poses(pb, banks[0], imgs[a:min(n_test, a + chunk)],
@@ -220,7 +226,7 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
         for a in range(0, n_test, chunk):
             b = min(n_test, a + chunk)
             W, _, W0 = learned_poses(lib, net, pb, imgs[a:b], ps_te.ctf(a, b), st, st_rots,
-                                     zbuf[:b - a], matched_filter)
+                                     xbuf[:b - a], matched_filter)
             Ws.append(W)
             W0s.append(W0)
         return torch.cat(Ws), torch.cat(W0s)

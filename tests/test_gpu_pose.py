@@ -247,3 +247,45 @@ def test_one_pass_preparation_d128_matches_oracle(gpu_lib, use_ctf):
         assert float(out["score"][p]) == scores[p].min()
     bank.close()
     batch.close()
+
+
+@pytest.mark.parametrize("D", [64, 128])
+def test_standardized_network_input(gpu_lib, D):
+    """The batch's standardised bfloat16 network input (D = 128: mean and
+    variance from the spectrum in the one-pass kernel; other D: the
+    network's own standardisation of Z) against the network's
+    standardisation of the filtered images and the oracle, and inference
+    from it against inference from the FP32 filtered images."""
+    announce(f"standardised network input from the pose batch, D={D}")
+    rng = np.random.default_rng(906 + D)
+    g = inputs.mixture_anisotropic(rng, 200, 10.0)
+    pixel, P = 1.5, 6
+    v, Y = _particles(g, P, D, pixel, rng)
+    batch = gpu_lib.pose_batch(D, pixel, P, shift_radius=2)
+    Z = torch.empty(P, D, D, device="cuda")
+    S = torch.empty(P, D, D, device="cuda", dtype=torch.bfloat16)
+    batch.load(dev(Y), ctf_arg(v), filtered=Z, standardized=S)
+    net = gpu_lib.network(D, P, 11)
+    _, _, raw_z = net.forward(Z)
+    X0 = net.tensor(0, False, (P, D, D))
+    _, _, raw_s = net.forward_standardized(X0)
+    with pytest.raises(binding.CryoSplatError):
+        net.tensor(0, False, (P, D, D))
+    torch.cuda.synchronize()
+    assert torch.equal(raw_s, raw_z)
+    s, x0 = S.float().cpu().numpy(), X0.float().cpu().numpy()
+    differ = s != x0
+    announce(f"  bfloat16 values that differ from the two-pass standardisation: {differ.mean():.2e}")
+    if D == 128:
+        assert differ.mean() <= 1e-3
+        assert np.all(np.abs(s - x0)[differ] <= 2.0 ** -7 * np.abs(x0)[differ] + 1e-6)
+    else:
+        assert not differ.any()
+    from oracle import cnn as o_cnn
+    from oracle import ctf as o_ctf
+    HY = o_ctf.apply_ctf(Y.astype(np.float64), o_ctf.ctf_grid_for(v))
+    ref = o_cnn.round_bf16(o_cnn.standardize(HY)[..., 0])
+    bad = s != ref
+    assert bad.mean() <= 1e-3
+    assert np.all(np.abs(s - ref)[bad] <= 2.0 ** -7 * np.abs(ref)[bad] + 1e-5)
+    batch.close()

@@ -43,6 +43,7 @@ def test_null_context_arguments_are_rejected(lib):
     assert L.cs_render(None, None, None, None, None, None, None) == -1
     assert L.cs_adam_step(None, None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
     assert L.cs_cnn_forward(None, None, 1, None, None, None, None) == -1
-    assert L.cs_pose_batch_load(None, None, None, 1, None, None) == -1
+    assert L.cs_pose_batch_load(None, None, None, 1, None, None, None) == -1
+    assert L.cs_cnn_forward_std(None, None, 1, None, None, None, None) == -1
     assert L.cs_pose_grid_search(None, None, None, 1, 2, None, None, None, None, None) == -1
     assert L.cs_cnn_param_count(None) == -1 and L.cs_pose_bank_size(None) == -1
