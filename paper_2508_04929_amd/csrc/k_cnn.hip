@@ -111,8 +111,12 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
   constexpr int TI = TBM / 32, TJ = TBN / 32;
   constexpr int NA = TBM * BK / 8 / 256, NB = TBN * BK / 8 / 256;
   static_assert(NA >= 1 && NB >= 1, "tile");
-  __shared__ bf16 sA[2][TBM][LDK];
-  __shared__ bf16 sB[2][TBN][LDK];
+  // operand tiles; after the K loop the same memory stages the output tile
+  constexpr int LDC = TBN + 8;
+  static_assert(TBM * LDC <= 2 * (TBM + TBN) * LDK, "output tile");
+  __shared__ __attribute__((aligned(16))) bf16 smem[2 * (TBM + TBN) * LDK];
+  bf16 (*sA)[TBM][LDK] = (bf16 (*)[TBM][LDK])smem;
+  bf16 (*sB)[TBN][LDK] = (bf16 (*)[TBN][LDK])(smem + 2 * TBM * LDK);
   const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -126,61 +130,108 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
   Side<Op, TBN, NB, false> sb;
   sa.init(op, tid, m0, M);
   sb.init(op, tid, n0, N);
-  uint4 ra[NA], rb[NB];
+  // operand registers of S consecutive K steps: a step's global loads are
+  // issued S - 1 steps before it is staged into LDS, so their latency hides
+  // behind that many steps of MFMA work
+  constexpr int S = 3;
+  uint4 ra[S][NA], rb[S][NB];
+  const int nsteps = (ke - kb + BK - 1) / BK;
 #pragma unroll
-  for (int q = 0; q < NA; ++q) ra[q] = sa.fetch(op, q, tid, m0, kb, M, ke);
+  for (int u = 0; u < S; ++u) {
 #pragma unroll
-  for (int q = 0; q < NB; ++q) rb[q] = sb.fetch(op, q, tid, n0, kb, N, ke);
+    for (int q = 0; q < NA; ++q) ra[u][q] = sa.fetch(op, q, tid, m0, kb + u * BK, M, ke);
 #pragma unroll
-  for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[0], tid + 256 * q, ra[q]);
-#pragma unroll
-  for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[0], tid + 256 * q, rb[q]);
-  __syncthreads();
-  int cur = 0;
-  for (int k0 = kb; k0 < ke; k0 += BK) {
-    const bool more = k0 + BK < ke;
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < NA; ++q) ra[q] = sa.fetch(op, q, tid, m0, k0 + BK, M, ke);
-#pragma unroll
-      for (int q = 0; q < NB; ++q) rb[q] = sb.fetch(op, q, tid, n0, k0 + BK, N, ke);
-    }
-#pragma unroll
-    for (int ks = 0; ks < BK / MK; ++ks) {
-      if (k0 + ks * MK >= ke) break;  // past the end of this K range: nothing to add
-      bf16x8 af[TI], bv[TJ];
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-        af[i] = *(const bf16x8 *)&sA[cur][wm + i * 16 + (lane & 15)][ks * MK + (lane >> 4) * 8];
-#pragma unroll
-      for (int j = 0; j < TJ; ++j)
-        bv[j] = *(const bf16x8 *)&sB[cur][wn + j * 16 + (lane & 15)][ks * MK + (lane >> 4) * 8];
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[cur ^ 1], tid + 256 * q, ra[q]);
-#pragma unroll
-      for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[cur ^ 1], tid + 256 * q, rb[q]);
-    }
-    __syncthreads();
-    cur ^= 1;
+    for (int q = 0; q < NB; ++q) rb[u][q] = sb.fetch(op, q, tid, n0, kb + u * BK, N, ke);
   }
 #pragma unroll
-  for (int i = 0; i < TI; ++i)
+  for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[0], tid + 256 * q, ra[0][q]);
 #pragma unroll
-    for (int j = 0; j < TJ; ++j)
+  for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[0], tid + 256 * q, rb[0][q]);
+  __syncthreads();
+  for (int t0 = 0; t0 < nsteps; t0 += S) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-        const int n = n0 + wn + j * 16 + (lane & 15);
-        if (m < M && n < N) op.store(m, n, acc[i][j][r], blockIdx.z);
+    for (int u = 0; u < S; ++u) {
+      const int t = t0 + u;
+      if (t < nsteps) {
+        const int cur = t & 1, k0 = kb + t * BK;
+        // register slot u held step t (already in LDS): refill it with t + S
+        if (t + S < nsteps) {
+#pragma unroll
+          for (int q = 0; q < NA; ++q) ra[u][q] = sa.fetch(op, q, tid, m0, k0 + S * BK, M, ke);
+#pragma unroll
+          for (int q = 0; q < NB; ++q) rb[u][q] = sb.fetch(op, q, tid, n0, k0 + S * BK, N, ke);
+        }
+#pragma unroll
+        for (int ks = 0; ks < BK / MK; ++ks) {
+          if (k0 + ks * MK >= ke) break;  // past the end of this K range: nothing to add
+          bf16x8 af[TI], bv[TJ];
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+            af[i] = *(const bf16x8 *)&sA[cur][wm + i * 16 + (lane & 15)][ks * MK + (lane >> 4) * 8];
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            bv[j] = *(const bf16x8 *)&sB[cur][wn + j * 16 + (lane & 15)][ks * MK + (lane >> 4) * 8];
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        if (t + 1 < nsteps) {
+          const int un = (u + 1) % S;  // a constant once the loop is unrolled
+#pragma unroll
+          for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[cur ^ 1], tid + 256 * q, ra[un][q]);
+#pragma unroll
+          for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[cur ^ 1], tid + 256 * q, rb[un][q]);
+        }
+        __syncthreads();
       }
+    }
+  }
+  if constexpr (Op::kStaged) {
+    // epilogue through LDS: values (bias / ReLU / mask applied per element)
+    // rounded to bfloat16 into an output tile, then written as 16-byte rows
+    // (N is a multiple of 8); the optional FP32 copy is stored per element
+    bf16 (*sC)[LDC] = (bf16 (*)[LDC])smem;
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int nl = wn + j * 16 + (lane & 15), n = n0 + nl;
+      const float cv = n < N ? op.col(n) : 0.f;
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = wm + i * 16 + (lane >> 4) * 4 + r, m = m0 + ml;
+          float v = 0.f;
+          if (m < M && n < N) {
+            v = op.epi(m, n, acc[i][j][r], cv);
+            if (op.f32_out()) op.f32_out()[(size_t)m * op.ldo() + n] = v;
+          }
+          sC[ml][nl] = f2bf(v);
+        }
+    }
+    __syncthreads();
+    bf16 *out = op.bf16_out();
+    const int64_t ldo = op.ldo();
+    for (int e = tid; e < TBM * TBN / 8; e += 256) {
+      const int ml = e / (TBN / 8), nl = (e % (TBN / 8)) * 8;
+      const int m = m0 + ml, n = n0 + nl;
+      if (m < M && n < N) *(uint4 *)&out[(size_t)m * ldo + n] = *(const uint4 *)&sC[ml][nl];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int j = 0; j < TJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+          const int n = n0 + wn + j * 16 + (lane & 15);
+          if (m < M && n < N) op.store(m, n, acc[i][j][r], blockIdx.z);
+        }
+  }
 }
+
 
 // ---------------------------------------------------------------------------
 // 3x3 stride-2 pad-1 convolution as GEMMs (NHWC, Cin and Cout multiples of 8)
@@ -231,13 +282,15 @@ struct ConvFwdOp {
   __device__ uint4 vec_b(const Row &r, int k0, int koff) const {
     return *(const uint4 *)&w[r.off + k0 + koff];
   }
-  __device__ void store(int m, int n, float v, int) const {
-    v += bias ? bias[n] : 0.f;
-    if (relu) v = fmaxf(v, 0.f);
-    const size_t o = (size_t)m * g.Cout + n;
-    if (out32) out32[o] = v;
-    out[o] = f2bf(v);
+  static constexpr bool kStaged = true;
+  __device__ float col(int n) const { return bias ? bias[n] : 0.f; }
+  __device__ float epi(int, int, float v, float cv) const {
+    v += cv;
+    return relu ? fmaxf(v, 0.f) : v;
   }
+  __device__ bf16 *bf16_out() const { return out; }
+  __device__ float *f32_out() const { return out32; }
+  __device__ int64_t ldo() const { return g.Cout; }
 };
 
 // data gradient: M = B Hi Wi, N = Cin, K = 9 Cout (k = tap * Cout + co);
@@ -280,12 +333,14 @@ struct ConvDgradOp {
   __device__ uint4 vec_b(const Row &r, int k0, int koff) const {
     return *(const uint4 *)&wt[r.off + k0 + koff];
   }
-  __device__ void store(int m, int n, float v, int) const {
-    const size_t o = (size_t)m * g.Cin + n;
-    if (act_in && !(bf2f(act_in[o]) > 0.f)) v = 0.f;
-    if (din32) din32[o] = v;
-    din[o] = f2bf(v);
+  static constexpr bool kStaged = true;
+  __device__ float col(int) const { return 0.f; }
+  __device__ float epi(int m, int n, float v, float) const {
+    return (act_in && !(bf2f(act_in[(size_t)m * g.Cin + n]) > 0.f)) ? 0.f : v;
   }
+  __device__ bf16 *bf16_out() const { return din; }
+  __device__ float *f32_out() const { return din32; }
+  __device__ int64_t ldo() const { return g.Cin; }
 };
 
 // weight gradient: M = Cout, N = 9 Cin (n = tap * Cin + ci), K = B Ho Wo
@@ -306,6 +361,7 @@ struct ConvWgradOp {
     if (iy < 0 || iy >= g.Hi || ix < 0 || ix >= g.Wi) return make_uint4(0, 0, 0, 0);
     return *(const uint4 *)&in[(((size_t)b * g.Hi + iy) * g.Wi + ix) * g.Cin + ci];
   }
+  static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int z) const {
     part[((size_t)z * g.Cout + m) * 9 * g.Cin + n] = v;
   }
@@ -335,6 +391,7 @@ struct LinFwdOp {  // M = B, N = Out, K = In
   __device__ Row row_b(int n) const { return Row{(int64_t)n * g.In}; }
   __device__ uint4 vec_a(const Row &r, int k0, int koff) const { return *(const uint4 *)&x[r.off + k0 + koff]; }
   __device__ uint4 vec_b(const Row &r, int k0, int koff) const { return *(const uint4 *)&w[r.off + k0 + koff]; }
+  static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int) const {
     v += bias ? bias[n] : 0.f;
     if (relu) v = fmaxf(v, 0.f);
@@ -355,6 +412,7 @@ struct LinDgradOp {  // M = B, N = In, K = Out; wt = W^T [In][Out]
   __device__ Row row_b(int n) const { return Row{(int64_t)n * g.Out}; }
   __device__ uint4 vec_a(const Row &r, int k0, int koff) const { return *(const uint4 *)&dy[r.off + k0 + koff]; }
   __device__ uint4 vec_b(const Row &r, int k0, int koff) const { return *(const uint4 *)&wt[r.off + k0 + koff]; }
+  static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int) const {
     const size_t o = (size_t)m * g.In + n;
     if (x_act && !(bf2f(x_act[o]) > 0.f)) v = 0.f;
@@ -371,6 +429,7 @@ struct LinWgradOp {  // M = Out, N = In, K = B; split-K partials
   struct Row {};
   __device__ uint4 a_vecT(int m, int b) const { return *(const uint4 *)&dy[(size_t)b * g.Out + m]; }
   __device__ uint4 b_vecT(int n, int b) const { return *(const uint4 *)&x[(size_t)b * g.In + n]; }
+  static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int z) const {
     part[((size_t)z * g.Out + m) * g.In + n] = v;
   }
@@ -534,11 +593,20 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
 #pragma unroll
     for (int t = 0; t < 9; ++t) wr[e][t] = bf2f(w1[(c0 + e) * 9 + t]);  // w1 [c][tap]
   }
-  // input patch rows 4 oy0 - 3 .., columns 4 ox0 - 3 ..
-  const int iy0 = 4 * oy0 - 3, ix0 = 4 * ox0 - 3;
-  for (int q = tid; q < C12_IY * C12_IX; q += 256) {
-    const int yy = iy0 + q / C12_IX, xx = ix0 + q % C12_IX;
-    xin[q] = (yy >= 0 && yy < H0 && xx >= 0 && xx < H0) ? bf2f(in0[((size_t)b * H0 + yy) * H0 + xx]) : 0.f;
+  // input patch rows 4 oy0 - 3 .., columns 4 ox0 - 3 .. 4 ox0 + 63: 16-byte
+  // loads of the aligned columns 4 ox0 - 8 .. 4 ox0 + 63 (9 per row)
+  const int iy0 = 4 * oy0 - 3, cx0 = 4 * ox0 - 8;
+  for (int q = tid; q < C12_IY * 9; q += 256) {
+    const int ry = q / 9, t = q - ry * 9;
+    const int yy = iy0 + ry, xx = cx0 + 8 * t;
+    Vec8 v;
+    v.u = make_uint4(0, 0, 0, 0);
+    if (yy >= 0 && yy < H0 && xx >= 0 && xx < H0) v.u = *(const uint4 *)&in0[((size_t)b * H0 + yy) * H0 + xx];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = 8 * t + e - 5;  // patch column of input column xx + e
+      if (c >= 0 && c < C12_IX) xin[ry * C12_IX + c] = bf2f(v.h[e]);
+    }
   }
   __syncthreads();
   // first layer at patch positions (y, x) = first-layer rows 2 oy0 - 1 + y, columns 2 ox0 - 1 + x
@@ -585,16 +653,23 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
       acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bw[tap], acc[i], 0, 0, 0);
     }
   }
+  // output tile [128 pixels][64 channels] staged in the first-layer buffer,
+  // then written as 16-byte chunks (each output row of 16 pixels is 2 KiB
+  // of contiguous NHWC memory)
   const int n = wv * 16 + (lane & 15);
   const float bn = b2 ? b2[n] : 0.f;
+  __syncthreads();
+  bf16 *sc = a1;  // [128][72]
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = i * 16 + (lane >> 4) * 4 + r;
-      const int oy = oy0 + (m >> 4), ox = ox0 + (m & 15);
-      out[(((size_t)b * H2 + oy) * H2 + ox) * 64 + n] = f2bf(fmaxf(acc[i][r] + bn, 0.f));
-    }
+    for (int r = 0; r < 4; ++r) sc[(i * 16 + (lane >> 4) * 4 + r) * 72 + n] = f2bf(fmaxf(acc[i][r] + bn, 0.f));
+  __syncthreads();
+  for (int e = tid; e < 128 * 8; e += 256) {
+    const int m = e >> 3, c8 = (e & 7) * 8;
+    const int oy = oy0 + (m >> 4), ox = ox0 + (m & 15);
+    *(uint4 *)&out[(((size_t)b * H2 + oy) * H2 + ox) * 64 + c8] = *(const uint4 *)&sc[m * 72 + c8];
+  }
 }
 
 // ---------------------------------------------------------------------------
