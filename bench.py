@@ -327,8 +327,11 @@ def main():
     if args.pose:
         from paper_2508_04929_amd import binding, pose
         log = lambda m: print(f"[pose] {m}", file=sys.stderr, flush=True)
+        # the default refinement (coarse 6 directions x 2 angles, fine 4 x 2) and,
+        # with the same network, two configurations with more candidates
         r = pose.run_c5(binding.library(), n_train=args.pose_train, epochs=args.pose_epochs,
-                        n_test=args.pose_test, log=log)
+                        n_test=args.pose_test, log=log,
+                        stage_sweep=(((0, 5, 3), (1, 5, 3)), ((0, 5, 2), (1, 5, 3))))
         res["pose"] = {
             "workload": ("learned pose proposal: N=20,000 mixture, D=128, p=1.5 A, SNR -20 dB, "
                          "CTF; network trained on %d renders x %d epochs; %d held-out particles; "
@@ -341,6 +344,7 @@ def main():
             "untrained": r["untrained"], "training": r["training"],
             "literal_grid_search_images_per_s": r.get("literal_grid_search_images_per_s"),
             "speedup_vs_literal_grid_search": r.get("speedup_vs_literal_grid_search"),
+            "stage_sweep": r.get("stage_sweep"),
             "bank_build_s": r["bank_build_s"], "bank_sizes": r["bank_sizes"]}
     print(json.dumps(res))
 

@@ -416,12 +416,16 @@ void cs_pose_batch_destroy(cs_pose_batch *batch);
 int cs_pose_batch_load(cs_pose_batch *batch, const float *images, const cs_ctf *ctf, int32_t P,
                        float *filtered, uint16_t *standardized, void *stream);
 /* cs_pose_grid_search / cs_pose_refine on a loaded batch (same outputs;
- * the batch's shift radius applies). */
+ * the batch's shift radius applies).  best_rotation (may be NULL) receives
+ * the winning rotation matrices [P][3][3] from the bank's table (NaN where
+ * no candidate was scored), ready to serve as the next stage's proposal. */
 int cs_pose_batch_search(cs_pose_bank *bank, cs_pose_batch *batch, int32_t *best_rot,
-                         int32_t *best_shift, float *best_score, float *scores, void *stream);
+                         int32_t *best_shift, float *best_score, float *scores,
+                         float *best_rotation, void *stream);
 int cs_pose_batch_refine(cs_pose_bank *bank, cs_pose_batch *batch, const float *proposal,
                          int32_t n_dir, int32_t n_psi_c, int32_t *cand, int32_t *best_rot,
-                         int32_t *best_shift, float *best_score, float *scores, void *stream);
+                         int32_t *best_shift, float *best_score, float *scores,
+                         float *best_rotation, void *stream);
 
 /* ApplyCTF of Alg. 1 for arbitrary images (App. A.2, Eq. 14):
  * out = F^-1(H^ . F images) [B][D][D], per-image CTF (NULL = identity);

@@ -146,8 +146,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_pose_batch_destroy.argtypes = [vp]
     lib.cs_pose_batch_destroy.restype = None
     lib.cs_pose_batch_load.argtypes = [vp, vp, P(CsCtf), i32, vp, vp, vp]
-    lib.cs_pose_batch_search.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-    lib.cs_pose_batch_refine.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.cs_pose_batch_search.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.cs_pose_batch_refine.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
     for name in ("cs_pose_batch_create", "cs_pose_batch_load", "cs_pose_batch_search",
                  "cs_pose_batch_refine", "cs_ctf_filter", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
@@ -777,13 +777,14 @@ class PoseBatch:
         return {"rot_idx": torch.empty(P, device=d, dtype=torch.int32),
                 "shift_idx": torch.empty(P, device=d, dtype=torch.int32),
                 "score": torch.empty(P, device=d),
+                "rot": torch.empty(P, 3, 3, device=d),
                 "scores": torch.empty(P, ncols, self.S, device=d) if want_scores else None}
 
     def search(self, bank: "PoseBank", want_scores=False):
         out = self._outs(bank.K, want_scores)
         self.owner._check(self.ctx, self.lib.cs_pose_batch_search(
             bank.h, self.h, out["rot_idx"].data_ptr(), out["shift_idx"].data_ptr(),
-            out["score"].data_ptr(), PoseBank._p(out["scores"]), self._s()),
+            out["score"].data_ptr(), PoseBank._p(out["scores"]), out["rot"].data_ptr(), self._s()),
             "cs_pose_batch_search")
         return out
 
@@ -805,7 +806,7 @@ class PoseBatch:
         self.owner._check(self.ctx, self.lib.cs_pose_batch_refine(
             bank.h, self.h, PoseBank._p(proposal), int(n_dir), int(n_psi_c), PoseBank._p(cand),
             out["rot_idx"].data_ptr(), out["shift_idx"].data_ptr(), out["score"].data_ptr(),
-            PoseBank._p(out["scores"]), self._s()), "cs_pose_batch_refine")
+            PoseBank._p(out["scores"]), out["rot"].data_ptr(), self._s()), "cs_pose_batch_refine")
         return out
 
 

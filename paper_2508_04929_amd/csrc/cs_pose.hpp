@@ -66,7 +66,7 @@ hipError_t rows_to_bf16(const float *src, int64_t rows, int len, unsigned short 
 hipError_t fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
 hipError_t fill_u16(unsigned short *p, int64_t n, hipStream_t st);
 hipError_t pose_decode(const unsigned long long *best, int P, int S, int *rot_idx, int *shift_idx,
-                       float *score, hipStream_t st);
+                       float *score, const float *bank_rot, float *rot_out, hipStream_t st);
 hipError_t pose_gemm_store(const PoseGemmArgs &a, hipStream_t st);
 hipError_t pose_gemm_score(const PoseGemmArgs &a, hipStream_t st);
 hipError_t pose_gemm_refine(const PoseGemmArgs &a, int P, hipStream_t st);

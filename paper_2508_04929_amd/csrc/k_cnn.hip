@@ -113,8 +113,8 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
   static_assert(NA >= 1 && NB >= 1, "tile");
   // operand tiles; after the K loop the same memory stages the output tile
   constexpr int LDC = TBN + 8;
-  static_assert(TBM * LDC <= 2 * (TBM + TBN) * LDK, "output tile");
-  __shared__ __attribute__((aligned(16))) bf16 smem[2 * (TBM + TBN) * LDK];
+  constexpr int kOps = 2 * (TBM + TBN) * LDK, kOut = TBM * LDC;
+  __shared__ __attribute__((aligned(16))) bf16 smem[kOps > kOut ? kOps : kOut];
   bf16 (*sA)[TBM][LDK] = (bf16 (*)[TBM][LDK])smem;
   bf16 (*sB)[TBN][LDK] = (bf16 (*)[TBN][LDK])(smem + 2 * TBM * LDK);
   const int m0 = blockIdx.x * TBM, n0 = blockIdx.y * TBN;

@@ -145,10 +145,11 @@ __global__ void __launch_bounds__(256) k_fill_u16(unsigned short *p, int64_t n) 
   if (i < n) p[i] = 0;
 }
 
-// best key -> (rotation index, shift index, score)
+// best key -> (rotation index, shift index, score) and optionally the
+// rotation matrix itself, bank_rot[rotation index] (NaN when nothing won)
 __global__ void __launch_bounds__(256)
 k_pose_decode(const unsigned long long *best, int P, int S, int *rot_idx, int *shift_idx,
-              float *score) {
+              float *score, const float *bank_rot, float *rot_out) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= P) return;
   const unsigned long long k = best[p];
@@ -157,6 +158,11 @@ k_pose_decode(const unsigned long long *best, int P, int S, int *rot_idx, int *s
   if (rot_idx) rot_idx[p] = none ? -1 : (int)(idx / S);
   if (shift_idx) shift_idx[p] = none ? -1 : (int)(idx % S);
   if (score) score[p] = none ? __int_as_float(0x7fc00000) : ord_float((unsigned)(k >> 32));
+  if (rot_out) {
+    const float *A = bank_rot + 9 * (size_t)(idx / S);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) rot_out[9 * (size_t)p + e] = none ? __int_as_float(0x7fc00000) : A[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -556,6 +562,16 @@ size_t pose_refine_z_lds(int D, int F8) {
 __global__ void __launch_bounds__(256)
 k_pose_candidates(const float *prop, int P, const float *bank_rot, int ndir, int n_psi, int n_dir,
                   int n_psi_c, int *cand) {
+  // viewing directions (third rows at psi = 0) of the bank, staged once per
+  // block of four particles
+  extern __shared__ float vd[];
+  for (int d = threadIdx.x; d < ndir; d += 256) {
+    const float *A = bank_rot + 9 * ((size_t)d * n_psi);
+    vd[3 * d] = A[6];
+    vd[3 * d + 1] = A[7];
+    vd[3 * d + 2] = A[8];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (p >= P) return;  // whole wave exits together
@@ -566,8 +582,7 @@ k_pose_candidates(const float *prop, int P, const float *bank_rot, int ndir, int
   for (int q = 0; q < n_dir; ++q) {
     unsigned long long best = 0ull;
     for (int d = lane; d < ndir; d += 64) {
-      const float *A = bank_rot + 9 * ((size_t)d * n_psi);
-      const float dot = A[6] * v0 + A[7] * v1 + A[8] * v2;
+      const float dot = vd[3 * d] * v0 + vd[3 * d + 1] * v1 + vd[3 * d + 2] * v2;
       const unsigned long long k = ((unsigned long long)ord_bits(dot) << 32) | (0xffffffffu - (unsigned)d);
       if (k < prev && k > best) best = k;
     }
@@ -648,9 +663,9 @@ hipError_t fill_u16(unsigned short *p, int64_t n, hipStream_t st) {
 }
 
 hipError_t pose_decode(const unsigned long long *best, int P, int S, int *rot_idx, int *shift_idx,
-                       float *score, hipStream_t st) {
+                       float *score, const float *bank_rot, float *rot_out, hipStream_t st) {
   hipLaunchKernelGGL(k_pose_decode, dim3(pcdiv(P, 256)), dim3(256), 0, st, best, P, S, rot_idx,
-                     shift_idx, score);
+                     shift_idx, score, bank_rot, rot_out);
   return hipGetLastError();
 }
 
@@ -674,8 +689,8 @@ hipError_t pose_gemm_refine(const PoseGemmArgs &a, int P, hipStream_t st) {
 
 hipError_t pose_candidates(const float *prop, int P, const float *bank_rot, int ndir, int n_psi,
                            int n_dir, int n_psi_c, int *cand, hipStream_t st) {
-  hipLaunchKernelGGL(k_pose_candidates, dim3(pcdiv(P, 4)), dim3(256), 0, st, prop, P, bank_rot,
-                     ndir, n_psi, n_dir, n_psi_c, cand);
+  hipLaunchKernelGGL(k_pose_candidates, dim3(pcdiv(P, 4)), dim3(256), (size_t)ndir * 12, st, prop,
+                     P, bank_rot, ndir, n_psi, n_dir, n_psi_c, cand);
   return hipGetLastError();
 }
 

@@ -372,7 +372,7 @@ int cs_pose_batch_load(cs_pose_batch *q, const float *images, const cs_ctf *ctf,
 }
 
 int cs_pose_batch_search(cs_pose_bank *b, cs_pose_batch *q, int32_t *best_rot, int32_t *best_shift,
-                         float *best_score, float *scores, void *stream) {
+                         float *best_score, float *scores, float *best_rotation, void *stream) {
   if (!q) return CS_ERR_INVALID_ARG;
   cs_ctx *ctx = q->ctx;
   int rc = check_batch(ctx, b, q);
@@ -403,13 +403,13 @@ int cs_pose_batch_search(cs_pose_bank *b, cs_pose_batch *q, int32_t *best_rot, i
   a.E = E; a.lde = b->K; a.yy = q->yy; a.best = q->best;
   a.scores = scores;
   HIPCHK(pose_gemm_score(a, st));
-  HIPCHK(pose_decode(q->best, q->P, q->S, best_rot, best_shift, best_score, st));
+  HIPCHK(pose_decode(q->best, q->P, q->S, best_rot, best_shift, best_score, b->rot, best_rotation, st));
   return CS_OK;
 }
 
 int cs_pose_batch_refine(cs_pose_bank *b, cs_pose_batch *q, const float *proposal, int32_t n_dir,
                          int32_t n_psi_c, int32_t *cand, int32_t *best_rot, int32_t *best_shift,
-                         float *best_score, float *scores, void *stream) {
+                         float *best_score, float *scores, float *best_rotation, void *stream) {
   if (!q) return CS_ERR_INVALID_ARG;
   cs_ctx *ctx = q->ctx;
   int rc = check_batch(ctx, b, q);
@@ -443,7 +443,7 @@ int cs_pose_batch_refine(cs_pose_bank *b, cs_pose_batch *q, const float *proposa
     z.D = q->D; z.r = q->r; z.S = q->S; z.F8 = q->F8; z.npx = q->npx;
     z.yy = q->yy; z.best = q->best; z.scores = scores;
     HIPCHK(pose_refine_z(z, q->P, st));
-    HIPCHK(pose_decode(q->best, q->P, q->S, best_rot, best_shift, best_score, st));
+    HIPCHK(pose_decode(q->best, q->P, q->S, best_rot, best_shift, best_score, b->rot, best_rotation, st));
     return CS_OK;
   }
   if (!q->zs_valid) {  // particles too large for LDS: gathered GEMM over the shifted copies
@@ -459,7 +459,7 @@ int cs_pose_batch_refine(cs_pose_bank *b, cs_pose_batch *q, const float *proposa
   a.yy = q->yy; a.best = q->best;
   a.scores = scores;
   HIPCHK(pose_gemm_refine(a, q->P, st));
-  HIPCHK(pose_decode(q->best, q->P, q->S, best_rot, best_shift, best_score, st));
+  HIPCHK(pose_decode(q->best, q->P, q->S, best_rot, best_shift, best_score, b->rot, best_rotation, st));
   return CS_OK;
 }
 
@@ -496,7 +496,8 @@ int cs_pose_grid_search(cs_pose_bank *b, const float *images, const cs_ctf *ctf,
     if (rc) return rc;
     rc = cs_pose_batch_search(b, q, best_rot + p0, best_shift ? best_shift + p0 : nullptr,
                               best_score ? best_score + p0 : nullptr,
-                              scores ? scores + (size_t)p0 * b->K * q->S : nullptr, stream);
+                              scores ? scores + (size_t)p0 * b->K * q->S : nullptr, nullptr,
+                              stream);
     if (rc) return rc;
   }
   return CS_OK;
@@ -524,7 +525,8 @@ int cs_pose_refine(cs_pose_bank *b, const float *images, const cs_ctf *ctf, int3
                               cand ? cand + (size_t)p0 * L : nullptr, best_rot + p0,
                               best_shift ? best_shift + p0 : nullptr,
                               best_score ? best_score + p0 : nullptr,
-                              scores ? scores + (size_t)p0 * L * q->S : nullptr, stream);
+                              scores ? scores + (size_t)p0 * L * q->S : nullptr, nullptr,
+                              stream);
     if (rc) return rc;
   }
   return CS_OK;

@@ -108,7 +108,7 @@ class Stage:
 
 
 def learned_poses(lib, net: binding.Network, batch: binding.PoseBatch, images, ctf: binding.Ctf,
-                  stages: Sequence[Stage], rots: Sequence[torch.Tensor], xbuf: torch.Tensor,
+                  stages: Sequence[Stage], xbuf: torch.Tensor,
                   matched_filter: bool = True):
     """Prepare the particles once, network proposal (on Z = H Y with
     matched_filter: the batch writes the standardised bfloat16 network input
@@ -122,18 +122,17 @@ def learned_poses(lib, net: binding.Network, batch: binding.PoseBatch, images, c
         batch.load(images, ctf)
         W0, _, _ = net.forward(images)
     W, out = W0, None
-    for i, st in enumerate(stages):
+    for st in stages:
         out = batch.refine(st.bank, proposal=W, n_dir=st.n_dir, n_psi_c=st.n_psi_c)
-        W = rots[i][out["rot_idx"].long()].contiguous()
+        W = out["rot"]
     return W, (out["shift_idx"] if out is not None else None), W0
 
 
-def grid_poses(batch: binding.PoseBatch, bank: binding.PoseBank, images, ctf: binding.Ctf,
-               rot: torch.Tensor):
+def grid_poses(batch: binding.PoseBatch, bank: binding.PoseBank, images, ctf: binding.Ctf):
     """Exhaustive search of one bank: (rot [P][3][3], shift index [P])."""
     batch.load(images, ctf)
     out = batch.search(bank)
-    return rot[out["rot_idx"].long()].contiguous(), out["shift_idx"]
+    return out["rot"], out["shift_idx"]
 
 
 def timed(fn, reps: int = 3):
@@ -180,11 +179,13 @@ def literal_grid_search(lib, gd, image, ctf_one: binding.Ctf, grid_rot: torch.Te
 
 def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, gamma=0.85,
            lam=0.1, snr_db=-20.0, seed=5, coarse=(4, 24), fine=(8, 48), shift_radius=2,
-           stages=((0, 5, 3), (1, 5, 3)), matched_filter=True, chunk=2048,
-           literal_particles=2, log=print):
+           stages=((0, 6, 2), (1, 4, 2)), matched_filter=True, chunk=2048,
+           literal_particles=2, stage_sweep=(), log=print):
     """The learned-pose experiment: returns angular errors and throughputs.
 
-    stages: (bank 0 = coarse / 1 = fine, n_dir, n_psi_c) per refinement stage.
+    stages: (bank 0 = coarse / 1 = fine, n_dir, n_psi_c) per refinement stage;
+    stage_sweep: other stage lists evaluated with the same trained network
+    (error and throughput of each, under "stage_sweep").
     Both paths are timed from particle images in device memory to poses,
     particle preparation (CTF filtering, shifted copies) included."""
     dev = torch.device("cuda")
@@ -209,7 +210,7 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
 
     def grid_all():
         return torch.cat([grid_poses(pb, banks[0], imgs[a:min(n_test, a + chunk)],
-                                     ps_te.ctf(a, min(n_test, a + chunk)), rots[0])[0]
+                                     ps_te.ctf(a, min(n_test, a + chunk)))[0]
                           for a in range(0, n_test, chunk)])
 
     W_gs, t_gs = timed(grid_all)
@@ -218,15 +219,14 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
                           "images_per_s": n_test / t_gs, "seconds": t_gs}
     log(f"grid search: median {np.median(err_gs):.2f} deg, {n_test / t_gs:.0f} img/s")
     st = [Stage(banks[b], nd, npc) for b, nd, npc in stages]
-    st_rots = [rots[b] for b, _, _ in stages]
     net = lib.network(D, max_batch=max(batch, chunk), seed=seed)
 
-    def learned():
+    def learned(st=st):
         Ws, W0s = [], []
         for a in range(0, n_test, chunk):
             b = min(n_test, a + chunk)
-            W, _, W0 = learned_poses(lib, net, pb, imgs[a:b], ps_te.ctf(a, b), st, st_rots,
-                                     xbuf[:b - a], matched_filter)
+            W, _, W0 = learned_poses(lib, net, pb, imgs[a:b], ps_te.ctf(a, b), st, xbuf[:b - a],
+                                     matched_filter)
             Ws.append(W)
             W0s.append(W0)
         return torch.cat(Ws), torch.cat(W0s)
@@ -258,6 +258,17 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
         f"{n_test / t_l:.0f} img/s")
     res["speedup_vs_grid_search"] = t_gs / t_l
     res["reaches_grid_search_error"] = bool(np.median(err_t) <= np.median(err_gs))
+    sweep = []
+    for stv in stage_sweep:
+        sv = [Stage(banks[b], nd, npc) for b, nd, npc in stv]
+        (W_v, _), t_v = timed(lambda: learned(sv))
+        e_v = angular_error_deg(W_v, ps_te.rot)
+        sweep.append({"stages": [list(x) for x in stv], "median_deg": float(np.median(e_v)),
+                      "images_per_s": n_test / t_v, "speedup_vs_grid_search": t_gs / t_v})
+        log(f"stages {stv}: refined {np.median(e_v):.2f} deg, {n_test / t_v:.0f} img/s, "
+            f"{t_gs / t_v:.1f}x grid search")
+    if sweep:
+        res["stage_sweep"] = sweep
     if literal_particles > 0:
         t0 = time.perf_counter()
         for p in range(literal_particles):

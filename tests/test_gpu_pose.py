@@ -194,6 +194,10 @@ def test_batch_api_matches_convenience_calls_and_filter(gpu_lib):
     torch.cuda.synchronize()
     assert torch.equal(out["scores"], ref["scores"])
     assert torch.equal(out["rot_idx"], ref["rot_idx"])
+    # the winning rotation matrices come from the bank's table
+    Gd = dev(G)
+    assert torch.equal(out["rot"], Gd[out["rot_idx"].long()])
+    assert torch.equal(r2["rot"], Gd[r2["rot_idx"].long()])
     assert torch.equal(r1["scores"], r2["scores"]) and torch.equal(r1["rot_idx"], r2["rot_idx"])
     # the batch's filtered images and cs_ctf_filter are H Y (Eq. 14) vs the oracle
     from oracle import ctf as o_ctf
