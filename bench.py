@@ -304,6 +304,8 @@ def main():
                          "then learned proposal + refinement vs grid search; about a minute)")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
                     help="skip the uneven-batching measurement (8 mixtures in one launch)")
+    ap.add_argument("--no-pose-sweep", dest="pose_sweep", action="store_false",
+                    help="skip the extra refinement configurations of the pose leg")
     ap.add_argument("--pose-train", type=int, default=200000)
     ap.add_argument("--pose-epochs", type=int, default=12)
     ap.add_argument("--pose-test", type=int, default=2048)
@@ -331,7 +333,8 @@ def main():
         # with the same network, two configurations with more candidates
         r = pose.run_c5(binding.library(), n_train=args.pose_train, epochs=args.pose_epochs,
                         n_test=args.pose_test, log=log,
-                        stage_sweep=(((0, 5, 3), (1, 5, 3)), ((0, 5, 2), (1, 5, 3))))
+                        stage_sweep=(((0, 5, 3), (1, 5, 3)), ((0, 5, 2), (1, 5, 3)))
+                        if args.pose_sweep else ())
         res["pose"] = {
             "workload": ("learned pose proposal: N=20,000 mixture, D=128, p=1.5 A, SNR -20 dB, "
                          "CTF; network trained on %d renders x %d epochs; %d held-out particles; "

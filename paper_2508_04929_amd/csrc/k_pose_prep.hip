@@ -232,6 +232,8 @@ __device__ __forceinline__ unsigned short energy_weight(float h, int kx) {
   return bf16_rne(wf * h * h * ((float)kN * (float)kN));
 }
 
+}  // namespace
+
 __global__ void __launch_bounds__(256)
 k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8, float *Z,
                unsigned short *zs, unsigned short *zb, unsigned short *w, float *yy) {
@@ -434,8 +436,6 @@ k_pose_prep128(const float *Y, const float2 *tw, float pixel, CtfDev ctf, int F8
   __syncthreads();
   if (tid == 0) yy[p] = (float)(red[0] + red[1] + red[2] + red[3]);
 }
-
-}  // namespace
 
 hipError_t pose_prep128(const float *Y, const float2 *tw, float pixel, const CtfDev &ctf, int P,
                         int F8, float *Z, unsigned short *zs, unsigned short *zb, unsigned short *w,

@@ -135,6 +135,26 @@ def grid_poses(batch: binding.PoseBatch, bank: binding.PoseBank, images, ctf: bi
     return out["rot"], out["shift_idx"]
 
 
+class Graphed:
+    """A fixed sequence of library calls captured once as a HIP graph and
+    replayed: one launch instead of one per kernel.  The sequence runs once
+    eagerly first, so every library buffer it needs already exists (the
+    library must not allocate during capture); its outputs are the tensors
+    returned by the captured call, rewritten by every replay."""
+
+    def __init__(self, fn):
+        fn()
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.out = fn()
+        torch.cuda.synchronize()
+
+    def __call__(self):
+        self.graph.replay()
+        return self.out
+
+
 def timed(fn, reps: int = 3):
     """(result, median seconds) of a GPU call sequence."""
     res, ts = None, []
@@ -180,12 +200,14 @@ def literal_grid_search(lib, gd, image, ctf_one: binding.Ctf, grid_rot: torch.Te
 def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, gamma=0.85,
            lam=0.1, snr_db=-20.0, seed=5, coarse=(4, 24), fine=(8, 48), shift_radius=2,
            stages=((0, 6, 2), (1, 4, 2)), matched_filter=True, chunk=2048,
-           literal_particles=2, stage_sweep=(), log=print):
+           literal_particles=2, stage_sweep=(), use_graphs=True, log=print):
     """The learned-pose experiment: returns angular errors and throughputs.
 
     stages: (bank 0 = coarse / 1 = fine, n_dir, n_psi_c) per refinement stage;
     stage_sweep: other stage lists evaluated with the same trained network
-    (error and throughput of each, under "stage_sweep").
+    (error and throughput of each, under "stage_sweep").  With use_graphs
+    both timed paths are replayed HIP graphs (the eager times are reported
+    too).
     Both paths are timed from particle images in device memory to poses,
     particle preparation (CTF filtering, shifted copies) included."""
     dev = torch.device("cuda")
@@ -213,10 +235,17 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
                                      ps_te.ctf(a, min(n_test, a + chunk)))[0]
                           for a in range(0, n_test, chunk)])
 
-    W_gs, t_gs = timed(grid_all)
+    W_gs, t_gs_eager = timed(grid_all)
+    t_gs = t_gs_eager
+    if use_graphs:
+        g_grid = Graphed(grid_all)
+        W_gs2, t_gs = timed(g_grid)
+        if not torch.equal(W_gs2, W_gs):
+            raise RuntimeError("graph replay of the grid search differs from the eager run")
     err_gs = angular_error_deg(W_gs, ps_te.rot)
     res["grid_search"] = {"median_deg": float(np.median(err_gs)), "mean_deg": float(err_gs.mean()),
-                          "images_per_s": n_test / t_gs, "seconds": t_gs}
+                          "images_per_s": n_test / t_gs, "seconds": t_gs,
+                          "images_per_s_eager": n_test / t_gs_eager}
     log(f"grid search: median {np.median(err_gs):.2f} deg, {n_test / t_gs:.0f} img/s")
     st = [Stage(banks[b], nd, npc) for b, nd, npc in stages]
     net = lib.network(D, max_batch=max(batch, chunk), seed=seed)
@@ -247,12 +276,19 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
                        "seconds": t_train, "images_per_s": epochs * n_train / t_train,
                        "loss_first": hist[0][1] if hist else None,
                        "loss_last": hist[-1][1] if hist else None}
-    (W_t, W0_t), t_l = timed(learned)
+    (W_t, W0_t), t_l_eager = timed(learned)
+    t_l = t_l_eager
+    if use_graphs:
+        g_learned = Graphed(learned)
+        (W_t2, W0_t2), t_l = timed(g_learned)
+        if not (torch.equal(W_t2, W_t) and torch.equal(W0_t2, W0_t)):
+            raise RuntimeError("graph replay of the learned path differs from the eager run")
     err_t = angular_error_deg(W_t, ps_te.rot)
     err_pt = angular_error_deg(W0_t, ps_te.rot)
     res["learned"] = {"median_deg": float(np.median(err_t)), "mean_deg": float(err_t.mean()),
                       "proposal_median_deg": float(np.median(err_pt)),
                       "images_per_s": n_test / t_l, "seconds": t_l,
+                      "images_per_s_eager": n_test / t_l_eager,
                       "stages": [list(s) for s in stages]}
     log(f"learned: proposal {np.median(err_pt):.1f} deg, refined {np.median(err_t):.2f} deg, "
         f"{n_test / t_l:.0f} img/s")
@@ -261,7 +297,8 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
     sweep = []
     for stv in stage_sweep:
         sv = [Stage(banks[b], nd, npc) for b, nd, npc in stv]
-        (W_v, _), t_v = timed(lambda: learned(sv))
+        fn_v = (lambda: learned(sv))
+        (W_v, _), t_v = timed(Graphed(fn_v) if use_graphs else fn_v)
         e_v = angular_error_deg(W_v, ps_te.rot)
         sweep.append({"stages": [list(x) for x in stv], "median_deg": float(np.median(e_v)),
                       "images_per_s": n_test / t_v, "speedup_vs_grid_search": t_gs / t_v})

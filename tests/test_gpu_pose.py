@@ -293,3 +293,41 @@ def test_standardized_network_input(gpu_lib, D):
     assert bad.mean() <= 1e-3
     assert np.all(np.abs(s - ref)[bad] <= 2.0 ** -7 * np.abs(ref)[bad] + 1e-5)
     batch.close()
+
+
+@pytest.mark.parametrize("D", [64, 128])
+def test_graphed_pose_paths_match_eager(gpu_lib, D):
+    """Learned path (batch preparation, network, two refinement stages) and
+    grid search captured as HIP graphs: every replay, with eager library
+    work and synchronisations in between, equals the eager result."""
+    from paper_2508_04929_amd import pose
+    announce(f"graph-captured pose paths, D={D}")
+    rng = np.random.default_rng(907 + D)
+    g = inputs.mixture_anisotropic(rng, 150, 10.0)
+    pixel, P = 1.5, 40
+    v, Y = _particles(g, P, D, pixel, rng)
+    G1, G2 = o_pose.grid(1, 8).astype(np.float32), o_pose.grid(2, 8).astype(np.float32)
+    b1 = gpu_lib.pose_bank(**mixture_args(g), rot=dev(G1), n_psi=8, D=D, pixel=pixel)
+    b2 = gpu_lib.pose_bank(**mixture_args(g), rot=dev(G2), n_psi=8, D=D, pixel=pixel)
+    batch = gpu_lib.pose_batch(D, pixel, P, shift_radius=2)
+    net = gpu_lib.network(D, P, 3)
+    xbuf = torch.empty(P, D, D, device="cuda", dtype=torch.bfloat16)
+    imgs, ctf = dev(Y), ctf_arg(v)
+    stages = [pose.Stage(b1, 3, 2), pose.Stage(b2, 3, 2)]
+    learned = lambda: pose.learned_poses(gpu_lib, net, batch, imgs, ctf, stages, xbuf)
+    grid = lambda: pose.grid_poses(batch, b1, imgs, ctf)
+    W_e, s_e, W0_e = [t.clone() for t in learned()]
+    Wg_e, sg_e = [t.clone() for t in grid()]
+    gl, gg = pose.Graphed(learned), pose.Graphed(grid)
+    for rep in range(3):
+        W, s, W0 = gl()
+        Wg, sg = gg()
+        torch.cuda.synchronize()
+        assert torch.equal(W, W_e) and torch.equal(s, s_e) and torch.equal(W0, W0_e), rep
+        assert torch.equal(Wg, Wg_e) and torch.equal(sg, sg_e), rep
+        # eager work between replays: a search with another bank, then a sync
+        batch.load(imgs, ctf)
+        batch.search(b2)
+        torch.cuda.synchronize()
+    for h in (b1, b2, batch, net):
+        h.close()
