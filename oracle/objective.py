@@ -18,7 +18,16 @@ r in the image with G_Q = dL/dQ:
                                         back through Sigma' = W Sigma W^T)
 
 then through Sigma = R diag(s)^2 R^T to s and the quaternion and through the
-activations to the stored parameters.  Eq. 18 prints W where the adjoint of
+activations to the stored parameters.
+
+The same per-image terms give the gradient w.r.t. the views themselves
+(the joint pose optimisation the paper leaves to future work, Sec. 6):
+with P the first two rows of the view rotation W, mu~ = P mu + t and
+S~ = P Sigma P^T,
+
+    dL/dt = sum_n dL/dmu~_n,    dL/dP = sum_n dL/dmu~_n mu_n^T + 2 dL/dS~_n P Sigma_n,
+
+and the third row of W does not enter the image.  Eq. 18 prints W where the adjoint of
 the viewing transform is W^T; the transpose is used (checked against finite
 differences).
 """
@@ -93,6 +102,10 @@ def backward_from_image_grad(g, v, GQ, *, q_cut=None, scale_act="exp",
     d_mu = np.zeros((N, 3))
     d_sigma = np.zeros((N, 3, 3))
     d_A = np.zeros(N)
+    B = W.shape[0]
+    d_rot = np.zeros((B, 3, 3))
+    d_shift = np.zeros((B, 2))
+    means = np.asarray(g.means, dtype=np.float64)
     for b in range(W.shape[0]):
         P = W[b, :2, :]
         S2 = cov2[b]
@@ -126,6 +139,9 @@ def backward_from_image_grad(g, v, GQ, *, q_cut=None, scale_act="exp",
         d_S2 = -inv @ d_inv @ inv                                   # dL/dS~
         d_mu += d_mu2 @ P                                           # P^T dmu~
         d_sigma += np.einsum("ai,nab,bj->nij", P, d_S2, P)         # P^T dS~ P
+        d_shift[b] = d_mu2.sum(axis=0)                              # pose: t
+        d_rot[b, :2] = (np.einsum("na,nj->aj", d_mu2, means)        # pose: P
+                        + 2.0 * np.einsum("nab,bk,nkj->aj", d_S2, P, cov))
 
     # Sigma = R diag(s^2) R^T  ->  s and R (Eq. 5), then q and activations.
     s = model.scales_from(g.log_scales, scale_act)
@@ -144,7 +160,7 @@ def backward_from_image_grad(g, v, GQ, *, q_cut=None, scale_act="exp",
     a = np.asarray(g.amps, dtype=np.float64)
     d_a = d_A * (1.0 if amp_act == "identity" else model.sigmoid(a))
     return {"means": d_mu, "log_scales": d_l, "quats": d_q, "amps": d_a,
-            "d_sigma": d_sigma, "d_A": d_A}
+            "rot": d_rot, "shift": d_shift, "d_sigma": d_sigma, "d_A": d_A}
 
 
 def loss_and_grad(g, v, Y, *, q_cut=None, reduction="sum", scale_act="exp",
@@ -159,6 +175,22 @@ def loss_and_grad(g, v, Y, *, q_cut=None, reduction="sum", scale_act="exp",
                                      amp_act=amp_act)
     f.update(GX=GX, GQ=GQ, grads=grads)
     return f
+
+
+def finite_difference_view(g, v, Y, field, entries, *, h=1e-6, **kw):
+    """Central differences of the loss for entries of the views' "rot"
+    [B][3][3] (taken entry-wise, not kept orthonormal) or "shift" [B][2]."""
+    import dataclasses
+    base = np.asarray(getattr(v, field), dtype=np.float64).copy()
+    out = []
+    for e in entries:
+        vals = []
+        for sgn in (+1.0, -1.0):
+            a = base.copy()
+            a[e] += sgn * h
+            vals.append(forward(g, dataclasses.replace(v, **{field: a}), Y, **kw)["loss"])
+        out.append((vals[0] - vals[1]) / (2.0 * h))
+    return np.array(out)
 
 
 def finite_difference(g, v, Y, field, entries, *, h_rel=1e-6, **kw):

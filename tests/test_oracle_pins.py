@@ -448,6 +448,51 @@ def test_pin9_gradient_vs_finite_differences(acts, reduction):
     assert np.abs((gq * qhat).sum(1)).max() < 1e-12 * np.abs(gq).max()
 
 
+@pytest.mark.parametrize("reduction", ["sum", "mean"])
+def test_pin9_pose_gradient_vs_finite_differences(reduction):
+    """Gradients w.r.t. the views' rotation entries and shifts (the third
+    row of the rotation does not enter the image: zero) against central
+    differences of the loss."""
+    rng = np.random.default_rng(27)
+    D, p = 24, 1.0
+    g = _mixture(rng, 4, 4.0, 0.8, 2.0)
+    v = _views(rng, 3, D, p, shift_px=1.0, astig=True)
+    Y = rng.standard_normal((3, D, D)) * 0.01
+    out = objective.loss_and_grad(g, v, Y, reduction=reduction)
+    for field in ("rot", "shift"):
+        arr = out["grads"][field]
+        ent = list(np.ndindex(arr.shape))
+        fd = objective.finite_difference_view(g, v, Y, field, ent, reduction=reduction)
+        an = np.array([arr[e] for e in ent])
+        assert np.abs(fd - an).max() <= 1e-7 * np.abs(an).max(), field
+    assert np.all(out["grads"]["rot"][:, 2, :] == 0.0)
+
+
+def test_pin9_pose_gradient_identities():
+    """One view: shifting the image is moving every Gaussian in the image
+    plane, dL/dt = P sum_n dL/dmu_n; the view W exp([a]x) sees the
+    mixture turned by exp([a]x) through W, which ties the rotation gradient
+    to the mean and covariance gradients."""
+    rng = np.random.default_rng(28)
+    D, p = 24, 1.0
+    g = _mixture(rng, 5, 4.0, 0.8, 2.0)
+    v = _views(rng, 1, D, p, shift_px=1.0, astig=True)
+    Y = rng.standard_normal((1, D, D)) * 0.01
+    gr = objective.loss_and_grad(g, v, Y)["grads"]
+    W = v.rot[0].astype(np.float64)
+    P = W[:2]
+    np.testing.assert_allclose(gr["shift"][0], P @ gr["means"].sum(0), rtol=1e-10,
+                               atol=1e-12 * np.abs(gr["shift"]).max())
+    mu = g.means.astype(np.float64)
+    for a in np.eye(3):
+        K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+        lhs = np.sum(gr["rot"][0] * (W @ K))
+        cov = __import__("oracle.model", fromlist=["covariance"]).covariance(g.log_scales, g.quats)
+        rhs = (np.sum(gr["means"] * (mu @ K.T)) +
+               np.sum(gr["d_sigma"] * (K @ cov - cov @ K)))
+        assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), np.abs(gr["rot"]).max()), (a, lhs, rhs)
+
+
 def test_pin9_global_translation():
     rng = np.random.default_rng(18)
     D, p = 24, 1.0
