@@ -193,6 +193,48 @@ def run(args):
     lib.set_timing(dev, False)
     final_loss = float(loss[-1].item())
 
+    # the same step with the gradients w.r.t. the 64 views' rotations and
+    # shifts as well (joint pose refinement): step time, and the pose-gradient
+    # kernels' HIP-event times against the bytes they must read
+    grads_pose = dict(grads, rot=torch.empty(B, 3, 3, device=dev), shift=torch.empty(B, 2, device=dev))
+
+    def step_pose():
+        lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
+                          grads=grads_pose, loss=loss)
+        step_no[0] += 1
+        lib.adam_step(flat, gflat, m, vv, step_no[0], lr=1e-3)
+
+    for _ in range(2):
+        step_pose()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step_pose()
+    torch.cuda.synchronize()
+    ms_pose = 1e3 * (time.perf_counter() - t1) / args.steps
+    lib.set_timing(dev, True)
+    for _ in range(timing_steps):
+        step_pose()
+    torch.cuda.synchronize()
+    pg = {}
+    for name in ("k_pose_grad_part", "k_pose_grad_sum"):
+        ms, n = lib.stage_time(dev, name)
+        if n:
+            pg[name] = ms / n
+    lib.set_timing(dev, False)
+    # per launch: six pixel moments and the visibility key per (image, Gaussian),
+    # the Gaussian records, 8 partial sums per (image, block of 256)
+    pg_bytes = B * N * (24 + 4) + N * 48 + B * ((N + 255) // 256) * 32
+    pose_grad = {
+        "ms_per_step": ms_pose, "ms_per_step_without": None,
+        "ms_per_launch": pg,
+        "roofline": ({"bound": "hbm", "kernel": "k_pose_grad_part",
+                      "achieved": pg_bytes / (pg["k_pose_grad_part"] * 1e-3) / 1e9,
+                      "peak": 8000.0, "unit": "GB/s",
+                      "frac": pg_bytes / (pg["k_pose_grad_part"] * 1e-3) / 8e12,
+                      "bytes_per_launch": pg_bytes}
+                     if "k_pose_grad_part" in pg else None)}
+
     ms_step = 1e3 * elapsed / args.steps
     value = B * args.steps / elapsed
     dom = max(("k_splat_fwd", "k_splat_bwd"), key=lambda k: stages.get(k, {}).get("ms_total", 0))
@@ -225,7 +267,9 @@ def run(args):
         "step_fraction_of_splat_roofline": step_roof_s / (ms_step * 1e-3),
         "stages_ms_per_step": {k: s["ms_total"] / timing_steps for k, s in stages.items()},
         "graph_replay": bool(args.graph),
+        "pose_gradients": pose_grad,
     }
+    pose_grad["ms_per_step_without"] = ms_step
     return result
 
 

@@ -106,12 +106,21 @@ typedef struct {
 } cs_ctf;
 
 /* Gradient outputs, same shapes as the cs_gaussians arrays (overwritten).
- * Any member may be NULL to skip that output. */
+ * Any member may be NULL to skip that output.  rot [B][3][3] and shift
+ * [B][2] are the gradients w.r.t. the views' rotation matrices (entry-wise,
+ * the matrices taken as given, not constrained to SO(3); the third row does
+ * not enter the image and gets 0) and shifts: the pose gradients that a
+ * joint optimisation of poses and Gaussians needs (Sec. 6, future work),
+ * from the same adjoint (App. A.2, Eq. 18 and 21):
+ *   dL/dt = sum_n dL/dmu~_n,  dL/dP = sum_n (dL/dmu~_n mu_n^T + 2 dL/dSigma~_n P Sigma_n)
+ * with P the first two rows of the rotation. */
 typedef struct {
   float *means;
   float *log_scales;
   float *quats;
   float *amps;
+  float *rot;
+  float *shift;
 } cs_grads;
 
 /* Launch options; pass NULL for defaults.  Results do not depend on tile,

@@ -44,7 +44,19 @@ class CsCtf(ctypes.Structure):
 
 class CsGrads(ctypes.Structure):
     _fields_ = [("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p),
-                ("quats", ctypes.c_void_p), ("amps", ctypes.c_void_p)]
+                ("quats", ctypes.c_void_p), ("amps", ctypes.c_void_p),
+                ("rot", ctypes.c_void_p), ("shift", ctypes.c_void_p)]
+
+
+_GRAD_SHAPES = {"means": lambda n, b: (n, 3), "log_scales": lambda n, b: (n, 3),
+                "quats": lambda n, b: (n, 4), "amps": lambda n, b: (n,),
+                "rot": lambda n, b: (b, 3, 3), "shift": lambda n, b: (b, 2)}
+
+
+def _grads_struct(grads, dev, n, b):
+    """CsGrads of a dict of output tensors (missing or None keys are skipped)."""
+    return CsGrads(*(_ptr(grads.get(k), k, dev, _GRAD_SHAPES[k](n, b)) for k in
+                     ("means", "log_scales", "quats", "amps", "rot", "shift")))
 
 
 class CsOptions(ctypes.Structure):
@@ -292,19 +304,22 @@ class Library:
         self._check(ctx, rc, "cs_render")
         return out
 
-    def _grads(self, dev, n, want=True):
+    def _grads(self, dev, n, b, pose=False):
+        """Fresh gradient outputs: the Gaussian parameters, and with pose the
+        views' rotations [B][3][3] and shifts [B][2]."""
         z = lambda *s: torch.empty(s, device=dev, dtype=torch.float32)
         gr = {"means": z(n, 3), "log_scales": z(n, 3), "quats": z(n, 4), "amps": z(n)}
-        cg = CsGrads(gr["means"].data_ptr(), gr["log_scales"].data_ptr(), gr["quats"].data_ptr(),
-                     gr["amps"].data_ptr())
-        return gr, cg
+        if pose:
+            gr.update(rot=z(b, 3, 3), shift=z(b, 2))
+        return gr, _grads_struct(gr, dev, n, b)
 
     def render_backward(self, means, log_scales, quats, amps, rot, shift, D, pixel, d_images,
-                        ctf=None, options=None, scale_act="exp", amp_act="identity"):
+                        ctf=None, options=None, scale_act="exp", amp_act="identity",
+                        want_pose_grads=False):
         dev, n, b, g, v, c, o = self._pack(means, log_scales, quats, amps, rot, shift, D, pixel,
                                            ctf, options, scale_act, amp_act)
         _ptr(d_images, "d_images", dev, (b, D, D))
-        gr, cg = self._grads(dev, n)
+        gr, cg = self._grads(dev, n, b, want_pose_grads)
         ctx = self.ctx(dev)
         rc = self.lib.cs_render_backward(ctx, ctypes.byref(g), ctypes.byref(v), self._ref(c),
                                          self._ref(o), d_images.data_ptr(), ctypes.byref(cg),
@@ -315,7 +330,10 @@ class Library:
     def loss_and_grad(self, means, log_scales, quats, amps, rot, shift, D, pixel, observed,
                       ctf=None, options=None, reduction="sum", want_grads=True,
                       want_images=False, scale_act="exp", amp_act="identity", grads=None,
-                      loss=None):
+                      loss=None, want_pose_grads=False):
+        """Loss per image (+ total) and gradients; with want_pose_grads the
+        gradients also hold "rot" [B][3][3] and "shift" [B][2]; a caller's
+        grads dict may hold any subset of the six outputs."""
         dev, n, b, g, v, c, o = self._pack(means, log_scales, quats, amps, rot, shift, D, pixel,
                                            ctf, options, scale_act, amp_act)
         _ptr(observed, "observed", dev, (b, D, D))
@@ -325,9 +343,9 @@ class Library:
         cg = None
         if want_grads:
             if grads is None:
-                grads, cg = self._grads(dev, n)
+                grads, cg = self._grads(dev, n, b, want_pose_grads)
             else:
-                cg = CsGrads(*(_ptr(grads[k], k, dev) for k in ("means", "log_scales", "quats", "amps")))
+                cg = _grads_struct(grads, dev, n, b)
         images = torch.empty((b, D, D), device=dev, dtype=torch.float32) if want_images else None
         ctx = self.ctx(dev)
         rc = self.lib.cs_loss_and_grad(
@@ -341,12 +359,14 @@ class Library:
     # -- batched problems -------------------------------------------------
     def make_problem(self, means, log_scales, quats, amps, rot, shift, D, pixel, observed,
                      ctf=None, options=None, reduction="sum", want_grads=True, want_images=False,
-                     scale_act="exp", amp_act="identity") -> Problem:
+                     scale_act="exp", amp_act="identity", want_pose_grads=False) -> Problem:
         dev = rot.device
         n, b = means.shape[0], rot.shape[0]
         z = lambda *s: torch.zeros(s, device=dev, dtype=torch.float32)
         grads = ({"means": z(n, 3), "log_scales": z(n, 3), "quats": z(n, 4), "amps": z(n)}
                  if want_grads else None)
+        if grads is not None and want_pose_grads:
+            grads.update(rot=z(b, 3, 3), shift=z(b, 2))
         return Problem(means, log_scales, quats, amps, rot, shift, D, pixel, observed, ctf,
                        options or Options(), reduction, z(b + 1), grads,
                        z(b, D, D) if want_images else None, scale_act, amp_act)
@@ -359,7 +379,7 @@ class Library:
         _ptr(pr.loss, "loss", dev, (b + 1,))
         cg = CsGrads()
         if pr.grads is not None:
-            cg = CsGrads(*(_ptr(pr.grads[k], k, dev) for k in ("means", "log_scales", "quats", "amps")))
+            cg = _grads_struct(pr.grads, dev, n, b)
         io = _ptr(pr.images_out, "images_out", dev, (b, pr.D, pr.D)) if pr.images_out is not None else None
         s = CsProblem(g, v, ctypes.pointer(c) if c is not None else None, o, pr.observed.data_ptr(),
                       CS_MEAN if pr.reduction == "mean" else CS_SUM, pr.loss.data_ptr(), cg, io)
@@ -901,7 +921,7 @@ class Network:
 STAGES = ("k_build", "k_bin_count", "k_bin_blockscan", "k_scan", "k_bin_scatter", "k_ctf_table", "k_splat_fwd", "k_canvas_reduce",
           "k_big_fwd", "k_fft_rows_fwd", "k_fft_cols_ctf", "k_fft_rows_inv_loss", "k_fft_rows_inv",
           "k_residual", "k_loss_reduce", "k_loss_total", "k_splat_bwd", "k_big_bwd", "k_chain", "k_adam",
-          "k_fill", "k_pair_count")
+          "k_fill", "k_pair_count", "k_pose_grad_part", "k_pose_grad_sum")
 
 _LIB: Optional[Library] = None
 

@@ -69,7 +69,8 @@ enum Mode { RENDER, BACKWARD, LOSS };
 
 struct Layout {
   size_t gc = 0, key = 0, count = 0, off = 0, blk = 0, item_off = 0, n_items = 0, queues = 0,
-         items = 0, list = 0, partials = 0, Q = 0, spec = 0, ctf = 0, mom = 0, loss_part = 0;
+         items = 0, list = 0, partials = 0, Q = 0, spec = 0, ctf = 0, mom = 0, loss_part = 0,
+         pose_part = 0;
   size_t total = 0;
   int max_items = 0;
   int nbx = 0;  // Gaussian blocks of the binning kernels
@@ -126,7 +127,10 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
     L.spec = take((size_t)G.B * G.D * (G.D / 2 + 1) * 8);
     L.ctf = take((size_t)G.B * G.D * (G.D / 2 + 1) * 4);
   }
-  if (need_mom) L.mom = take(BN * 24 + 32);
+  if (need_mom) {
+    L.mom = take(BN * 24 + 32);
+    L.pose_part = take((size_t)G.B * std::max(L.nbx, 1) * 32);
+  }
   L.loss_part = take((size_t)G.B * G.D * 4);
   L.total = o;
   return L;
@@ -265,7 +269,9 @@ CtfDev make_ctf(const cs_ctf *ctf) {
 
 namespace {
 
-bool has_grads(const cs_grads &g) { return g.means || g.log_scales || g.quats || g.amps; }
+bool has_grads(const cs_grads &g) {
+  return g.means || g.log_scales || g.quats || g.amps || g.rot || g.shift;
+}
 
 // ---------------------------------------------------------------------------
 // Enqueue helpers
@@ -379,6 +385,15 @@ int launch_backward_finish(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   TLAUNCH(k_chain, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.gc),
           P.g.log_scales, P.g.quats, P.g.amps, P.v.rot, P.v.shift, G, (const int *)(ws + P.L.key),
           mom, P.grads.means, P.grads.log_scales, P.grads.quats, P.grads.amps);
+  if (P.grads.rot || P.grads.shift) {
+    const int nblk = cdiv(G.N, kBlock);
+    float *part = (float *)(ws + P.L.pose_part);
+    TLAUNCH(k_pose_grad_part, dim3(nblk, cdiv(G.B, kPoseImg)), dim3(kBlock), 0, st,
+            (const float4 *)(ws + P.L.gc), P.v.rot, P.v.shift, G, (const int *)(ws + P.L.key), mom,
+            part);
+    TLAUNCH(k_pose_grad_sum, dim3(G.B), dim3(kBlock), 0, st, (const float *)part, G.B, nblk,
+            P.grads.rot, P.grads.shift);
+  }
   return CS_OK;
 }
 

@@ -290,6 +290,39 @@ k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, co
 // sum_r dM_rk R_rk, dR = dM diag(s), then the unit-quaternion and
 // activation derivatives (the 3DGS chain the paper defers to, App. A.2).
 // ---------------------------------------------------------------------------
+// Screen-frame gradients of one (image, Gaussian) pair from its six pixel
+// moments m: dL/dmu~ (Angstrom, x right / y up) and the symmetric dL/dSigma~
+// (Eq. 18, 20, with the |C|^1/2 of the weight folded in).
+struct ScreenGrad {
+  float dmx, dmy, Sxx, Sxy, Syy;
+};
+
+__device__ __forceinline__ ScreenGrad screen_grad(const Proj &P, const float *m, float pixel) {
+  const float p2 = pixel * pixel, ip = 1.f / pixel;
+  const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4], m5 = m[5];
+  const float inv_det = 1.f / P.det;
+  const float Cxx = P.syy * inv_det, Cxy = -P.sxy * inv_det, Cyy = P.sxx * inv_det;
+  const float a = p2 * Cxx, bb = -p2 * Cxy, c = p2 * Cyy;
+  const float w = P.w;
+  const float dLdu = w * (a * m1 + bb * m2);
+  const float dLdv = w * (bb * m1 + c * m2);
+  ScreenGrad r;
+  r.dmx = dLdu * ip;
+  r.dmy = -dLdv * ip;
+  // symmetric gradient w.r.t. C (entries), from d/da, d/db, d/dc
+  const float Gxx = -0.5f * w * m3 * p2;
+  const float Gxy = 0.5f * w * m4 * p2;
+  const float Gyy = -0.5f * w * m5 * p2;
+  // -C G C - (w m0 / 2) C
+  const float t_xx = Cxx * Gxx + Cxy * Gxy, t_xy = Cxx * Gxy + Cxy * Gyy;
+  const float t_yx = Cxy * Gxx + Cyy * Gxy, t_yy = Cxy * Gxy + Cyy * Gyy;
+  const float hw = 0.5f * w * m0;
+  r.Sxx = -(t_xx * Cxx + t_xy * Cxy) - hw * Cxx;
+  r.Sxy = -(t_xx * Cxy + t_xy * Cyy) - hw * Cxy;
+  r.Syy = -(t_yx * Cxy + t_yy * Cyy) - hw * Cyy;
+  return r;
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_chain(const float4 *gc, const float *log_scales, const float *quats, const float *amps,
         const float *rot, const float *shift, Geom G, const int *key, const float *mom,
@@ -297,7 +330,6 @@ k_chain(const float4 *gc, const float *log_scales, const float *quats, const flo
   const int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= G.N) return;
   const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
-  const float p = G.pixel, p2 = p * p, ip = 1.f / p;
   float dmu[3] = {0, 0, 0};
   float dS[6] = {0, 0, 0, 0, 0, 0};  // xx xy xz yy yz zz
   float dw_sum = 0.f;                // sum_b dL/dw * w / A  (= dL/dA)
@@ -308,25 +340,9 @@ k_chain(const float4 *gc, const float *log_scales, const float *quats, const flo
     Proj P;
     project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
     const float *m = mom + ((size_t)b * G.N + n) * 6;
-    const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4], m5 = m[5];
-    const float inv_det = 1.f / P.det;
-    const float Cxx = P.syy * inv_det, Cxy = -P.sxy * inv_det, Cyy = P.sxx * inv_det;
-    const float a = p2 * Cxx, bb = -p2 * Cxy, c = p2 * Cyy;
-    const float w = P.w;
-    const float dLdu = w * (a * m1 + bb * m2);
-    const float dLdv = w * (bb * m1 + c * m2);
-    const float dmx = dLdu * ip, dmy = -dLdv * ip;
-    // symmetric gradient w.r.t. C (entries), from d/da, d/db, d/dc
-    const float Gxx = -0.5f * w * m3 * p2;
-    const float Gxy = 0.5f * w * m4 * p2;
-    const float Gyy = -0.5f * w * m5 * p2;
-    // -C G C - (w m0 / 2) C
-    const float t_xx = Cxx * Gxx + Cxy * Gxy, t_xy = Cxx * Gxy + Cxy * Gyy;
-    const float t_yx = Cxy * Gxx + Cyy * Gxy, t_yy = Cxy * Gxy + Cyy * Gyy;
-    const float hw = 0.5f * w * m0;
-    const float Sxx = -(t_xx * Cxx + t_xy * Cxy) - hw * Cxx;
-    const float Sxy = -(t_xx * Cxy + t_xy * Cyy) - hw * Cxy;
-    const float Syy = -(t_yx * Cxy + t_yy * Cyy) - hw * Cyy;
+    const ScreenGrad sg = screen_grad(P, m, G.pixel);
+    const float dmx = sg.dmx, dmy = sg.dmy, Sxx = sg.Sxx, Sxy = sg.Sxy, Syy = sg.Syy;
+    const float m0 = m[0];
 #pragma unroll
     for (int k = 0; k < 3; ++k) dmu[k] += p0[k] * dmx + p1[k] * dmy;
     const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
@@ -401,6 +417,103 @@ k_chain(const float4 *gc, const float *log_scales, const float *quats, const flo
   if (g_amps) {
     const float a = amps[n];
     g_amps[n] = dw_sum * (G.amp_act ? sigmoidf_(a) : 1.f);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pose gradients (the joint pose optimisation the paper names as future work,
+// Sec. 6, from the same adjoint, App. A.2 Eq. 18 and 21).  With the
+// projection P = the first two rows of the view rotation W, mu~ = P mu + t
+// and Sigma~ = P Sigma P^T:
+//   dL/dt = sum_n dL/dmu~_n,
+//   dL/dP = sum_n ( dL/dmu~_n mu_n^T + 2 dL/dSigma~_n P Sigma_n ),
+// the third row of W does not enter the image (its gradient is zero).
+// Partials per (image, block of Gaussians) in a fixed order, then a
+// fixed-order sum over blocks: deterministic.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_pose_grad_part(const float4 *gc, const float *rot, const float *shift, Geom G, const int *key,
+                 const float *mom, float *part) {
+  __shared__ float red[kBlock / 64][8];
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float4 g0 = make_float4(0, 0, 0, 0), g1 = g0, g2 = g0;
+  if (n < G.N) {
+    g0 = gc[3 * n];
+    g1 = gc[3 * n + 1];
+    g2 = gc[3 * n + 2];
+  }
+  // kPoseImg images per block: the Gaussian's record is read once
+  const int b1 = min(G.B, (int)(blockIdx.y + 1) * kPoseImg);
+  for (int b = blockIdx.y * kPoseImg; b < b1; ++b) {
+    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // t_x, t_y, P_0 (3), P_1 (3)
+    if (n < G.N && key[(size_t)b * G.N + n] >= 0) {
+      float p0[3], p1[3], tx, ty;
+      load_pose(rot, shift, b, p0, p1, tx, ty);
+      Proj P;
+      project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
+      const ScreenGrad sg = screen_grad(P, mom + ((size_t)b * G.N + n) * 6, G.pixel);
+      // Sigma p0, Sigma p1 (Sigma symmetric: the rows of P Sigma)
+      const float sp0[3] = {g1.x * p0[0] + g1.y * p0[1] + g1.z * p0[2],
+                            g1.y * p0[0] + g1.w * p0[1] + g2.x * p0[2],
+                            g1.z * p0[0] + g2.x * p0[1] + g2.y * p0[2]};
+      const float sp1[3] = {g1.x * p1[0] + g1.y * p1[1] + g1.z * p1[2],
+                            g1.y * p1[0] + g1.w * p1[1] + g2.x * p1[2],
+                            g1.z * p1[0] + g2.x * p1[1] + g2.y * p1[2]};
+      const float mu[3] = {g0.x, g0.y, g0.z};
+      v[0] = sg.dmx;
+      v[1] = sg.dmy;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        v[2 + k] = sg.dmx * mu[k] + 2.f * (sg.Sxx * sp0[k] + sg.Sxy * sp1[k]);
+        v[5 + k] = sg.dmy * mu[k] + 2.f * (sg.Sxy * sp0[k] + sg.Syy * sp1[k]);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float x = v[e];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) red[wv][e] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      float x = 0.f;
+      for (int w = 0; w < kBlock / 64; ++w) x += red[w][threadIdx.x];
+      part[((size_t)b * gridDim.x + blockIdx.x) * 8 + threadIdx.x] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// g_rot [B][3][3] (third row zero), g_shift [B][2]; either may be null.  One
+// block per image: each thread sums a strided subset of the block partials,
+// then a fixed tree over the threads.
+__global__ void __launch_bounds__(kBlock)
+k_pose_grad_sum(const float *part, int B, int nblk, float *g_rot, float *g_shift) {
+  __shared__ float red[kBlock][8];
+  const int b = blockIdx.x, t = threadIdx.x;
+  float x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = t; k < nblk; k += kBlock)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] += part[((size_t)b * nblk + k) * 8 + e];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) red[t][e] = x[e];
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) red[t][e] += red[t + h][e];
+    __syncthreads();
+  }
+  if (t < 8) {
+    const float v = red[0][t];
+    if (t < 2) {
+      if (g_shift) g_shift[2 * b + t] = v;
+    } else if (g_rot) {
+      g_rot[9 * b + (t - 2)] = v;  // rows 0 and 1: entries 0..5
+      if (t < 5) g_rot[9 * b + 6 + (t - 2)] = 0.f;
+    }
   }
 }
 
