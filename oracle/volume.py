@@ -35,17 +35,15 @@ def voxel_axis(D, pixel):
     return (np.arange(D) - D // 2) * float(pixel)
 
 
-def voxelize(g, D, pixel, q_cut=None, scale_act="exp", amp_act="identity", chunk=64):
-    """Mixture density on the D^3 grid [iz][iy][ix] (FP64)."""
+def density_at(g, pts, q_cut=None, scale_act="exp", amp_act="identity", chunk=64):
+    """Mixture density at points [P][3] (x, y, z), Angstrom (FP64)."""
     cov = model.covariance(g.log_scales, g.quats, scale_act)
     A = model.amps_from(g.amps, amp_act)
     mu = np.asarray(g.means, dtype=np.float64)
     inv = np.linalg.inv(cov)
     w = A * (2.0 * np.pi) ** -1.5 / np.sqrt(np.linalg.det(cov))
-    ax = voxel_axis(D, pixel)
-    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
-    pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
-    out = np.zeros(D ** 3)
+    pts = np.asarray(pts, dtype=np.float64)
+    out = np.zeros(len(pts))
     for n0 in range(0, len(mu), chunk):
         d = pts[None, :, :] - mu[n0:n0 + chunk, None, :]
         q = np.einsum("npi,nij,npj->np", d, inv[n0:n0 + chunk], d)
@@ -53,7 +51,24 @@ def voxelize(g, D, pixel, q_cut=None, scale_act="exp", amp_act="identity", chunk
         if q_cut is not None:
             e = np.where(q <= q_cut, e, 0.0)
         out += (w[n0:n0 + chunk, None] * e).sum(axis=0)
-    return out.reshape(D, D, D)
+    return out
+
+
+def voxel_points(D, pixel, idx=None):
+    """Positions (x, y, z) of voxels [iz][iy][ix] (all, or the listed
+    (iz, iy, ix) index triples)."""
+    ax = voxel_axis(D, pixel)
+    if idx is None:
+        Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+        return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    idx = np.asarray(idx)
+    return np.stack([ax[idx[:, 2]], ax[idx[:, 1]], ax[idx[:, 0]]], axis=1)
+
+
+def voxelize(g, D, pixel, q_cut=None, scale_act="exp", amp_act="identity", chunk=64):
+    """Mixture density on the D^3 grid [iz][iy][ix] (FP64)."""
+    return density_at(g, voxel_points(D, pixel), q_cut, scale_act, amp_act,
+                      chunk).reshape(D, D, D)
 
 
 def shell_index(D):
