@@ -273,6 +273,48 @@ def run(args):
     return result
 
 
+def run_volume(reps: int = 5):
+    """The reconstruction read out as a volume and compared (Sec. 3 overview,
+    Sec. 4 Eq. 10): voxelise the N = 200,000 training mixture and its ground
+    truth at D = 256 (1.1 A voxels), FSC between them."""
+    import numpy as np
+    import torch
+
+    from paper_2508_04929_amd import binding, inputs
+
+    lib = binding.library()
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    g, v, gt, rn = inputs.c4(b=1)
+    D, p = 256, 1.1
+    ma = [t(g.means), t(g.log_scales), t(g.quats), t(g.amps)]
+    mb = [t(gt.means), t(gt.log_scales), t(gt.quats), t(gt.amps)]
+    Va, Vb = lib.voxelize(*ma, D, p), lib.voxelize(*mb, D, p)
+    curve = lib.fsc(Va, Vb)
+    torch.cuda.synchronize()
+
+    def timed_ms(fn):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    ms_vox = timed_ms(lambda: lib.voxelize(*mb, D, p, out=Vb))
+    ms_fsc = timed_ms(lambda: lib.fsc(Va, Vb, out=curve))
+    return {"workload": ("voxelise the N=200,000 ground-truth mixture at D=256, 1.1 A "
+                         "(q <= 2 ln 1e6); FSC of the training start vs the ground truth"),
+            "voxelize_ms": ms_vox, "voxels_per_s": D ** 3 / (ms_vox * 1e-3),
+            "gaussians_per_s": gt.n / (ms_vox * 1e-3),
+            "fsc_ms": ms_fsc,
+            "fsc_bytes_min": 2 * D ** 3 * 4,
+            "resolution_A": binding.Library.resolution(curve.cpu().numpy(), D, p)}
+
+
 def run_batched(reps: int = 10, autotune: bool = True):
     """Uneven batching: 8 mixtures (N = 5k ... 150k) x 128 images, D in
     {128, 192, 256}, fwd + adjoint of all problems in one persistent launch
@@ -346,6 +388,8 @@ def main():
     ap.add_argument("--no-pose", dest="pose", action="store_false",
                     help="skip the learned-pose experiment (network trained on 200k renders, "
                          "then learned proposal + refinement vs grid search; about a minute)")
+    ap.add_argument("--no-volume", dest="volume", action="store_false",
+                    help="skip the voxelisation / FSC measurement")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
                     help="skip the uneven-batching measurement (8 mixtures in one launch)")
     ap.add_argument("--no-pose-sweep", dest="pose_sweep", action="store_false",
@@ -365,6 +409,10 @@ def main():
               file=sys.stderr, flush=True)
     res = run(args)
     res["cpu_baseline"] = cpu
+    if args.volume:
+        res["volume"] = run_volume()
+        print(f"[bench] volume: voxelise {res['volume']['voxelize_ms']:.2f} ms, "
+              f"FSC {res['volume']['fsc_ms']:.2f} ms", file=sys.stderr, flush=True)
     if args.batched:
         res["batched"] = run_batched()
         print(f"[bench] batched: {res['batched']['batched']['images_per_s']:.0f} images/s "

@@ -436,6 +436,29 @@ int cs_pose_batch_refine(cs_pose_bank *bank, cs_pose_batch *batch, const float *
                          int32_t *best_shift, float *best_score, float *scores,
                          float *best_rotation, void *stream);
 
+/* The mixture read out as a volume (the voxelisation of the reconstruction
+ * in the overview of Sec. 3): vol [D][D][D] (index [iz][iy][ix]) receives
+ * sum_n A_n (2 pi)^-3/2 det(Sigma_n)^-1/2 exp(-q_n / 2) at (x, y, z) =
+ * ((ix - D/2) p, (iy - D/2) p, (iz - D/2) p), over the Gaussians with
+ * q_n = (x - mu_n)^T Sigma_n^-1 (x - mu_n) <= q_cut (q_cut <= 0: the
+ * renderer's default 2 ln 1e6); the integral along z is the identity-pose
+ * image (Eq. 8) up to the raster's row flip.  D a multiple of 8, at most
+ * 512.  Exact fixed-point sums: the result is reproducible bit for bit.
+ * Reads the (brick, Gaussian) pair count back from the device, so the call
+ * waits for the stream and cannot be captured in a graph. */
+int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, float q_cut,
+                float *vol, void *stream);
+
+/* Fourier shell correlation of two volumes (Sec. 4, Eq. 10): fsc
+ * [D/2 + 1] receives, for shells k = round(|(kx, ky, kz)|) = 0 .. D/2 of the
+ * integer frequency grid, sum Re(Va^ conj Vb^) / sqrt(sum |Va^|^2 sum
+ * |Vb^|^2) over the full spectrum (0 for a shell without energy); the
+ * resolution is the first shell where it drops below 0.143.  D even with
+ * prime factors 2 and 3, at most 512.  Shell sums are exact fixed-point sums
+ * (reproducible). */
+int cs_fsc(cs_ctx *ctx, const float *vol_a, const float *vol_b, int32_t D, float *fsc,
+           void *stream);
+
 /* ApplyCTF of Alg. 1 for arbitrary images (App. A.2, Eq. 14):
  * out = F^-1(H^ . F images) [B][D][D], per-image CTF (NULL = identity);
  * D even with prime factors 2 and 3, at most 512; out may alias images. */

@@ -81,7 +81,8 @@ EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_b
            "cs_pose_head", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_destroy",
            "cs_pose_bank_size", "cs_pose_bank_rotations", "cs_pose_grid_search", "cs_pose_refine", "cs_add_noise", "cs_cnn_tensor",
            "cs_pose_batch_create", "cs_pose_batch_destroy", "cs_pose_batch_load",
-           "cs_pose_batch_search", "cs_pose_batch_refine", "cs_ctf_filter")
+           "cs_pose_batch_search", "cs_pose_batch_refine", "cs_ctf_filter",
+           "cs_voxelize", "cs_fsc")
 
 
 class CryoSplatError(RuntimeError):
@@ -159,10 +160,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_pose_batch_destroy.restype = None
     lib.cs_pose_batch_load.argtypes = [vp, vp, P(CsCtf), i32, vp, vp, vp]
     lib.cs_pose_batch_search.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.cs_voxelize.argtypes = [vp, P(CsGaussians), i32, f32, f32, vp, vp]
+    lib.cs_fsc.argtypes = [vp, vp, vp, i32, vp, vp]
     lib.cs_pose_batch_refine.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
     for name in ("cs_pose_batch_create", "cs_pose_batch_load", "cs_pose_batch_search",
-                 "cs_pose_batch_refine", "cs_ctf_filter", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
+                 "cs_pose_batch_refine", "cs_ctf_filter", "cs_voxelize", "cs_fsc", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
                  "cs_pose_grid_search", "cs_pose_refine"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("cs_cnn_create", "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward",
@@ -303,6 +306,49 @@ class Library:
                                 out.data_ptr(), torch.cuda.current_stream(dev).cuda_stream)
         self._check(ctx, rc, "cs_render")
         return out
+
+    def voxelize(self, means, log_scales, quats, amps, D, pixel, q_cut=0.0, scale_act="exp",
+                 amp_act="identity", out=None):
+        """The mixture's density on a D^3 grid [iz][iy][ix] (cs_voxelize)."""
+        dev = means.device
+        n = means.shape[0]
+        g = CsGaussians(_ptr(means, "means", dev, (n, 3)), _ptr(log_scales, "log_scales", dev, (n, 3)),
+                        _ptr(quats, "quats", dev, (n, 4)), _ptr(amps, "amps", dev, (n,)), n,
+                        _SCALE_ACT[scale_act], _AMP_ACT[amp_act])
+        if out is None:
+            out = torch.empty((D, D, D), device=dev, dtype=torch.float32)
+        _ptr(out, "vol", dev, (D, D, D))
+        ctx = self.ctx(dev)
+        self._check(ctx, self.lib.cs_voxelize(ctx, ctypes.byref(g), int(D), float(pixel),
+                                              float(q_cut), out.data_ptr(),
+                                              torch.cuda.current_stream(dev).cuda_stream),
+                    "cs_voxelize")
+        return out
+
+    def fsc(self, vol_a, vol_b, out=None):
+        """Fourier shell correlation per shell 0 .. D/2 (cs_fsc)."""
+        dev = vol_a.device
+        D = vol_a.shape[0]
+        _ptr(vol_a, "vol_a", dev, (D, D, D))
+        _ptr(vol_b, "vol_b", dev, (D, D, D))
+        if out is None:
+            out = torch.empty(D // 2 + 1, device=dev, dtype=torch.float32)
+        _ptr(out, "fsc", dev, (D // 2 + 1,))
+        ctx = self.ctx(dev)
+        self._check(ctx, self.lib.cs_fsc(ctx, vol_a.data_ptr(), vol_b.data_ptr(), int(D),
+                                         out.data_ptr(), torch.cuda.current_stream(dev).cuda_stream),
+                    "cs_fsc")
+        return out
+
+    @staticmethod
+    def resolution(fsc, D, pixel, threshold=0.143):
+        """Resolution in Angstrom: D p / k at the first shell k >= 1 where the
+        curve drops below the threshold (the last shell if it never does)."""
+        c = [float(x) for x in fsc]
+        for k in range(1, len(c)):
+            if c[k] < threshold:
+                return D * float(pixel) / k
+        return D * float(pixel) / (len(c) - 1)
 
     def _grads(self, dev, n, b, pose=False):
         """Fresh gradient outputs: the Gaussian parameters, and with pose the

@@ -733,6 +733,7 @@ void cs_destroy(cs_ctx *ctx) {
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->aux) (void)hipFree(ctx->aux);
+  if (ctx->vol) (void)hipFree(ctx->vol);
   for (auto &kv : ctx->twiddles) (void)hipFree(kv.second);
   delete ctx;
 }

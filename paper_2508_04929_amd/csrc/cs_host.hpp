@@ -35,6 +35,9 @@ struct cs_ctx {
   // scratch of the standalone network-layer entry points
   void *aux = nullptr;
   size_t aux_bytes = 0;
+  // scratch of the voxelisation and FSC entry points
+  void *vol = nullptr;
+  size_t vol_bytes = 0;
 };
 
 namespace cs {
@@ -86,3 +89,22 @@ CtfDev make_ctf(const cs_ctf *ctf);                        // disabled when ctf 
       ctx->pending.push_back({#kernel, ea_, eb_});                                   \
     }                                                                                \
   } while (0)
+
+namespace cs {
+
+// Grow-only device buffer (synchronises the device before a reallocation).
+inline int grow(cs_ctx *ctx, void **p, size_t *cap, size_t bytes) {
+  if (bytes <= *cap) return CS_OK;
+  HIPCHK(hipDeviceSynchronize());
+  if (*p) HIPCHK(hipFree(*p));
+  *p = nullptr;
+  *cap = 0;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, CS_ERR_OOM, "allocation of %zu bytes", bytes);
+  }
+  *cap = bytes;
+  return CS_OK;
+}
+
+}  // namespace cs

@@ -209,6 +209,8 @@ __global__ void k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, i
                                     const float *obs, float *images_out, float grad_scale,
                                     float *loss_part);
 
+__global__ void k_fft_axis(float2 *data, FftPlan P, const float2 *tw, int inner, int cpw);
+
 __global__ void k_fft_cols_power(const float2 *spec, FftPlan P, const float2 *tw, int B, int cpw,
                                  unsigned short *out, size_t ld);
 __global__ void k_loss_reduce(const float *loss_part, int B, int parts, float scale, float *loss);

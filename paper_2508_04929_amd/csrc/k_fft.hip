@@ -325,6 +325,38 @@ k_residual(float *Q, const float *obs, float *images_out, int B, int D, float gr
 
 
 // ---------------------------------------------------------------------------
+// Forward transform along the middle axis of data[outer][L][inner]
+// (complex, in place): cpw adjacent inner columns per block, outer index =
+// blockIdx.y.  The y and z passes of the 3-D transform of a volume.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_fft_axis(float2 *data, FftPlan P, const float2 *tw, int inner, int cpw) {
+  extern __shared__ float2 lds[];
+  const int L = P.L;
+  const int i0 = blockIdx.x * cpw;
+  const int ts = 256 / cpw;
+  const int team = threadIdx.x / ts, t = threadIdx.x % ts;
+  float2 *base = data + (size_t)blockIdx.y * L * inner;
+  float2 *twl = lds + (size_t)cpw * 2 * L;
+  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
+  for (int q = threadIdx.x; q < cpw * L; q += 256) {
+    const int c = q % cpw, r = q / cpw;
+    const int i = i0 + c;
+    lds[c * 2 * L + r] = (i < inner) ? base[(size_t)r * inner + i] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2 *x = lds + team * 2 * L, *y = x + L;
+  float2 *res = fft_team(x, y, P, twl, t, ts, false);
+  const int oofs = (int)(res - (lds + team * 2 * L));
+  __syncthreads();
+  for (int q = threadIdx.x; q < cpw * L; q += 256) {
+    const int c = q % cpw, r = q / cpw;
+    const int i = i0 + c;
+    if (i < inner) base[(size_t)r * inner + i] = lds[c * 2 * L + oofs + r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Column pass for power spectra: for cpw adjacent half-spectrum columns per
 // block, forward FFT over rows and |.|^2 stored as bfloat16 (nearest even)
 // at out[b * ld + ky * (D/2+1) + kx].

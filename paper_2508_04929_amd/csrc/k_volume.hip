@@ -1,0 +1,263 @@
+// Voxelisation of the mixture and Fourier shell correlation.
+//
+// The reconstruction is a Gaussian mixture; the overview of Sec. 3 reads
+// the final volume out by voxelising it, and Sec. 4 compares volumes by the
+// Fourier shell correlation of Eq. 10 with the 0.143 threshold.
+//
+// Voxelisation: voxel (iz, iy, ix) sits at ((ix - c0) p, (iy - c0) p,
+// (iz - c0) p) and holds sum_n A_n (2 pi)^-3/2 det(Sigma_n)^-1/2
+// exp(-q_n / 2) over the Gaussians with q_n <= q_cut.  Bricks of 8^3 voxels:
+// every Gaussian is listed under the bricks its q <= q_cut box touches
+// (counting sort); a block evaluates one brick against its list, two voxels
+// per thread.  Each voxel's sum is kept as a 64-bit fixed-point integer
+// (scale 2^e with the bound sum_n w_n < 2^61 / scale), so the result does
+// not depend on the order of the list: it is reproducible bit for bit.
+//
+// FSC: the 3-D real DFT is the renderer's row pass (real rows along x, two
+// per complex transform) over the D slices, then the same Stockham
+// transform along y and along z (k_fft_axis); shell sums of
+// Re(Fa conj Fb), |Fa|^2, |Fb|^2 (weight 2 off the kx = 0 and Nyquist
+// planes) are again exact 64-bit fixed-point sums, scaled by Parseval's
+// bound D^3 max(sum Va^2, sum Vb^2) on every shell sum.
+#include "cs_volume.hpp"
+
+namespace cs {
+
+constexpr int kBrick = 8;
+
+__device__ __forceinline__ int clampi(float x, int lo, int hi) {
+  x = fminf(fmaxf(x, (float)lo), (float)hi);
+  return (int)x;
+}
+
+// Per Gaussian: mean and weight, inverse covariance (FP64 adjugate), the
+// brick range of its q <= q_cut box, and the brick counts.
+__global__ void __launch_bounds__(256)
+k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box, int *count) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= V.N) return;
+  const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
+  const double sxx = g1.x, sxy = g1.y, sxz = g1.z, syy = g1.w, syz = g2.x, szz = g2.y;
+  const double cxx = syy * szz - syz * syz, cxy = sxz * syz - sxy * szz, cxz = sxy * syz - sxz * syy;
+  const double cyy = sxx * szz - sxz * sxz, cyz = sxy * sxz - sxx * syz, czz = sxx * syy - sxy * sxy;
+  const double det = fmax(sxx * cxx + sxy * cxy + sxz * cxz, 1e-30);
+  const double id = 1.0 / det;
+  const float w = (float)((double)g0.w * 0.063493635934240969 / sqrt(det));  // (2 pi)^-3/2
+  rec[3 * n] = make_float4(g0.x, g0.y, g0.z, w);
+  rec[3 * n + 1] = make_float4((float)(cxx * id), (float)(cxy * id), (float)(cxz * id), (float)(cyy * id));
+  rec[3 * n + 2] = make_float4((float)(cyz * id), (float)(czz * id), 0.f, 0.f);
+  // axis-aligned box of the ellipsoid q <= q_cut: half extents sqrt(q_cut S_ii)
+  const float mu[3] = {g0.x, g0.y, g0.z};
+  const float hh[3] = {sqrtf(V.q_cut * g1.x), sqrtf(V.q_cut * g1.w), sqrtf(V.q_cut * g2.y)};
+  const float ip = 1.f / V.pixel;
+  int lo[3], hi[3];
+  bool empty = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float a = ceilf((mu[k] - hh[k]) * ip + (float)V.c0);
+    const float b = floorf((mu[k] + hh[k]) * ip + (float)V.c0);
+    empty |= !(a <= b) || b < 0.f || a > (float)(V.D - 1);
+    lo[k] = clampi(a, 0, V.D - 1) / kBrick;
+    hi[k] = clampi(b, 0, V.D - 1) / kBrick;
+  }
+  if (empty) {
+    box[n] = make_int4(0, 0, 0, 0);
+    return;
+  }
+  box[n] = make_int4(lo[0] | (hi[0] << 16), lo[1] | (hi[1] << 16), lo[2] | (hi[2] << 16), 1);
+  for (int bz = lo[2]; bz <= hi[2]; ++bz)
+    for (int by = lo[1]; by <= hi[1]; ++by)
+      for (int bx = lo[0]; bx <= hi[0]; ++bx) atomicAdd(&count[(bz * V.nb + by) * V.nb + bx], 1);
+}
+
+// Exclusive scan of the brick counts (one block) and the fixed-point scale
+// of the voxel sums from the bound sum_n w_n (fixed-order FP64 sum).
+__global__ void __launch_bounds__(1024)
+k_vox_scan(const int *count, int nbr, const float4 *rec, int N, int *off, double *scale) {
+  __shared__ int part[1024];
+  __shared__ double wsum[1024];
+  const int t = threadIdx.x;
+  const int per = (nbr + 1023) / 1024;
+  const int a = t * per, b = min(nbr, a + per);
+  int s = 0;
+  for (int i = a; i < b; ++i) s += count[i];
+  part[t] = s;
+  double ws = 0.0;
+  for (int n = t; n < N; n += 1024) ws += (double)rec[3 * n].w;
+  wsum[t] = ws;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan of the chunk sums
+    const int v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  for (int h = 512; h > 0; h >>= 1) {
+    if (t < h) wsum[t] += wsum[t + h];
+    __syncthreads();
+  }
+  int run = t ? part[t - 1] : 0;
+  for (int i = a; i < b; ++i) {
+    off[i] = run;
+    run += count[i];
+  }
+  if (t == 0) {
+    off[nbr] = part[1023];
+    const double total = wsum[0] > 0.0 ? wsum[0] : 1.0;
+    int e;
+    frexp(total, &e);  // total < 2^e
+    *scale = ldexp(1.0, 61 - e);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_vox_fill(const int4 *box, VoxGeom V, const int *off, int *cursor, int *list) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= V.N) return;
+  const int4 bx4 = box[n];
+  if (!bx4.w) return;
+  const int x0 = bx4.x & 0xffff, x1 = bx4.x >> 16, y0 = bx4.y & 0xffff, y1 = bx4.y >> 16;
+  const int z0 = bx4.z & 0xffff, z1 = bx4.z >> 16;
+  for (int bz = z0; bz <= z1; ++bz)
+    for (int by = y0; by <= y1; ++by)
+      for (int bx = x0; bx <= x1; ++bx) {
+        const int k = (bz * V.nb + by) * V.nb + bx;
+        list[off[k] + atomicAdd(&cursor[k], 1)] = n;
+      }
+}
+
+// One brick of 8^3 voxels per block, two voxels per thread; its Gaussians
+// staged through LDS 256 at a time.
+__global__ void __launch_bounds__(256)
+k_vox_eval(const float4 *rec, const int *list, const int *off, VoxGeom V, const double *scale,
+           float *vol) {
+  __shared__ float4 sr[3][256];
+  const int k = blockIdx.x;
+  const int bx = k % V.nb, by = (k / V.nb) % V.nb, bz = k / (V.nb * V.nb);
+  const int t = threadIdx.x;
+  float px[2], py[2], pz[2];
+  int vi[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int v = t + 256 * h;
+    const int ix = bx * kBrick + (v & 7), iy = by * kBrick + ((v >> 3) & 7), iz = bz * kBrick + (v >> 6);
+    px[h] = (float)(ix - V.c0) * V.pixel;
+    py[h] = (float)(iy - V.c0) * V.pixel;
+    pz[h] = (float)(iz - V.c0) * V.pixel;
+    vi[h] = (iz * V.D + iy) * V.D + ix;
+  }
+  const double S = *scale;
+  long long acc[2] = {0, 0};
+  const int b0 = off[k], cnt = off[k + 1] - b0;
+  for (int c = 0; c < cnt; c += 256) {
+    if (c + t < cnt) {
+      const int n = list[b0 + c + t];
+      sr[0][t] = rec[3 * n];
+      sr[1][t] = rec[3 * n + 1];
+      sr[2][t] = rec[3 * n + 2];
+    }
+    __syncthreads();
+    const int m = min(256, cnt - c);
+    for (int j = 0; j < m; ++j) {
+      const float4 a = sr[0][j], iv = sr[1][j], iw = sr[2][j];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float dx = px[h] - a.x, dy = py[h] - a.y, dz = pz[h] - a.z;
+        const float q = dx * (iv.x * dx + 2.f * (iv.y * dy + iv.z * dz)) +
+                        dy * (iv.w * dy + 2.f * iw.x * dz) + iw.y * dz * dz;
+        if (q <= V.q_cut) acc[h] += __double2ll_rn((double)(a.w * __expf(-0.5f * q)) * S);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) vol[vi[h]] = (float)((double)acc[h] / S);
+}
+
+// ---------------------------------------------------------------------------
+// FSC
+// ---------------------------------------------------------------------------
+
+// sum of squares of each volume (fixed-order FP64), and the shell scale
+__global__ void __launch_bounds__(1024)
+k_fsc_energy(const float *va, const float *vb, int64_t n, int D, double *scale) {
+  __shared__ double r[2][1024];
+  const int t = threadIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = t; i < n; i += 1024) {
+    a += (double)va[i] * va[i];
+    b += (double)vb[i] * vb[i];
+  }
+  r[0][t] = a;
+  r[1][t] = b;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (t < h) {
+      r[0][t] += r[0][t + h];
+      r[1][t] += r[1][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    // every shell sum is at most D^3 max(sum Va^2, sum Vb^2) (Parseval)
+    double bound = (double)D * D * D * fmax(r[0][0], r[1][0]);
+    if (!(bound > 0.0)) bound = 1.0;
+    int e;
+    frexp(bound, &e);
+    *scale = ldexp(1.0, 61 - e);
+  }
+}
+
+// Shell sums over the half spectrum [kz][ky][kx] (kx = 0 .. D/2).
+__global__ void __launch_bounds__(256)
+k_fsc_shells(const float2 *fa, const float2 *fb, int D, const double *scale,
+             unsigned long long *sums) {
+  extern __shared__ unsigned long long ls[];  // [3][ns]
+  const int ns = D / 2 + 1, Dh = D / 2 + 1;
+  for (int i = threadIdx.x; i < 3 * ns; i += 256) ls[i] = 0ull;
+  __syncthreads();
+  const double S = *scale;
+  const int64_t total = (int64_t)D * D * Dh;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int kx = (int)(i % Dh);
+    const int64_t r = i / Dh;
+    const int ky = (int)(r % D), kz = (int)(r / D);
+    const int fy = ky < (D + 1) / 2 ? ky : ky - D, fz = kz < (D + 1) / 2 ? kz : kz - D;
+    const int s = (int)rint(sqrt((double)(kx * kx + fy * fy + fz * fz)));
+    if (s > D / 2) continue;
+    const double w = (kx == 0 || kx == D / 2) ? 1.0 : 2.0;
+    const float2 a = fa[i], b = fb[i];
+    const double num = w * ((double)a.x * b.x + (double)a.y * b.y);
+    const double da = w * ((double)a.x * a.x + (double)a.y * a.y);
+    const double db = w * ((double)b.x * b.x + (double)b.y * b.y);
+    atomicAdd(&ls[s], (unsigned long long)__double2ll_rn(num * S));
+    atomicAdd(&ls[ns + s], (unsigned long long)__double2ll_rn(da * S));
+    atomicAdd(&ls[2 * ns + s], (unsigned long long)__double2ll_rn(db * S));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * ns; i += 256)
+    if (ls[i]) atomicAdd(&sums[i], ls[i]);
+}
+
+__global__ void __launch_bounds__(256)
+k_fsc_final(const unsigned long long *sums, int ns, const double *scale, float *fsc) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ns) return;
+  const double S = *scale;
+  const double num = (double)(long long)sums[s] / S;
+  const double da = (double)(long long)sums[ns + s] / S, db = (double)(long long)sums[2 * ns + s] / S;
+  const double den = sqrt(da * db);
+  fsc[s] = den > 0.0 ? (float)(num / den) : 0.f;
+}
+
+__global__ void __launch_bounds__(256) k_fill_u64z(unsigned long long *p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void __launch_bounds__(256) k_fill_i32z(int *p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace cs

@@ -152,20 +152,6 @@ cs_ctf ctf_offset(const cs_ctf *ctf, int p0) {
   return c;
 }
 
-int grow(cs_ctx *ctx, void **p, size_t *cap, size_t bytes) {
-  if (bytes <= *cap) return CS_OK;
-  HIPCHK(hipDeviceSynchronize());
-  if (*p) HIPCHK(hipFree(*p));
-  *p = nullptr;
-  *cap = 0;
-  if (hipMalloc(p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, CS_ERR_OOM, "allocation of %zu bytes", bytes);
-  }
-  *cap = bytes;
-  return CS_OK;
-}
-
 int check_batch(cs_ctx *ctx, const cs_pose_bank *b, const cs_pose_batch *q) {
   if (!b || !q) return fail(ctx, CS_ERR_INVALID_ARG, "null bank or batch");
   if (b->D != q->D) return fail(ctx, CS_ERR_INVALID_ARG, "bank side %d != batch side %d", b->D, q->D);

@@ -1,0 +1,134 @@
+"""Voxelisation of the mixture and FSC (Eq. 10) on the GPU against the FP64
+oracle: voxel values within 1e-4 normwise (the image bar), FSC curves
+within 1e-5, exact reproducibility (fixed-point sums: the same bits for a
+permuted mixture), the identity-pose projection against the renderer, and
+sampled checks at the training size (N = 200,000, D = 256)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import volume as o_vol
+from paper_2508_04929_amd import binding, inputs
+
+from gpu_util import announce, dev, host, mixture_args, normwise
+
+pytestmark = pytest.mark.gpu
+
+Q_MATCHED = 2.0 * np.log(1e6)
+
+
+def _vox(lib, g, D, p, **kw):
+    m = mixture_args(g)
+    return lib.voxelize(m["means"], m["log_scales"], m["quats"], m["amps"], D, p, **kw)
+
+
+@pytest.mark.parametrize("D", [32, 48])
+def test_voxelize_matches_oracle(gpu_lib, D):
+    rng = np.random.default_rng(50 + D)
+    g = inputs.mixture_anisotropic(rng, 300, 0.25 * D * 1.5)
+    announce(f"voxelise 300 Gaussians, D={D}")
+    V = host(_vox(gpu_lib, g, D, 1.5))
+    ref = o_vol.voxelize(g, D, 1.5, q_cut=Q_MATCHED)
+    ref_exact = o_vol.voxelize(g, D, 1.5)
+    assert normwise(V, ref) <= 1e-4
+    assert normwise(V, ref_exact) <= 1e-4
+
+
+def test_voxelize_activations_and_cut(gpu_lib):
+    rng = np.random.default_rng(53)
+    g = inputs.mixture_anisotropic(rng, 200, 10.0)
+    g.amps = rng.standard_normal(g.n).astype(np.float32)
+    m = mixture_args(g)
+    V = host(gpu_lib.voxelize(m["means"], m["log_scales"], m["quats"], m["amps"], 32, 1.2,
+                              q_cut=9.0, scale_act="softplus", amp_act="softplus"))
+    ref = o_vol.voxelize(g, 32, 1.2, q_cut=9.0, scale_act="softplus", amp_act="softplus")
+    assert normwise(V, ref) <= 1e-4
+
+
+def test_voxelize_is_exact_and_order_free(gpu_lib):
+    rng = np.random.default_rng(54)
+    g = inputs.mixture_anisotropic(rng, 3000, 20.0)
+    V1 = _vox(gpu_lib, g, 64, 1.0)
+    V2 = _vox(gpu_lib, g, 64, 1.0)
+    perm = rng.permutation(g.n)
+    gp = inputs.Mixture(g.means[perm], g.log_scales[perm], g.quats[perm], g.amps[perm])
+    V3 = _vox(gpu_lib, gp, 64, 1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(V1, V2) and torch.equal(V1, V3)
+
+
+def test_voxel_projection_equals_identity_pose_render(gpu_lib):
+    rng = np.random.default_rng(55)
+    g = inputs.mixture_anisotropic(rng, 2000, 18.0)
+    D, p = 64, 1.0
+    announce("voxel projection vs identity-pose render, D=64")
+    V = _vox(gpu_lib, g, D, p)
+    img = gpu_lib.render(**mixture_args(g), rot=torch.eye(3, device="cuda")[None].contiguous(),
+                         shift=torch.zeros(1, 2, device="cuda"), D=D, pixel=p)[0]
+    proj = host(V.sum(0) * p)
+    ref = np.roll(host(img)[::-1, :], 1, axis=0)
+    assert normwise(proj, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("D", [32, 48])
+def test_fsc_matches_oracle(gpu_lib, D):
+    rng = np.random.default_rng(56 + D)
+    a = rng.standard_normal((D, D, D))
+    b = 0.6 * a + 0.8 * rng.standard_normal((D, D, D))
+    announce(f"FSC of correlated volumes, D={D}")
+    got = host(gpu_lib.fsc(dev(a), dev(b)))
+    ref = o_vol.fsc(a.astype(np.float32), b.astype(np.float32))
+    assert np.abs(got - ref).max() <= 1e-5
+    same = host(gpu_lib.fsc(dev(a), dev(a)))
+    neg = host(gpu_lib.fsc(dev(a), dev(-a)))
+    assert np.all(same == 1.0) and np.all(neg == -1.0)
+
+
+def test_fsc_of_reconstruction_like_pair(gpu_lib):
+    """Two voxelised mixtures that share their means but not their widths:
+    the curve falls with frequency; the resolution shell matches the
+    oracle's."""
+    rng = np.random.default_rng(58)
+    g = inputs.mixture_anisotropic(rng, 1500, 20.0)
+    h = inputs.Mixture(g.means.copy(), (g.log_scales + 0.4).astype(np.float32), g.quats.copy(),
+                       g.amps.copy())
+    D, p = 64, 1.0
+    Va, Vb = _vox(gpu_lib, g, D, p), _vox(gpu_lib, h, D, p)
+    got = host(gpu_lib.fsc(Va, Vb))
+    ref = o_vol.fsc(host(Va).astype(np.float32), host(Vb).astype(np.float32))
+    assert np.abs(got - ref).max() <= 1e-5
+    assert binding.Library.resolution(got, D, p) == pytest.approx(o_vol.resolution(ref, D, p))
+
+
+def test_volume_full_size_sampled(gpu_lib):
+    """N = 200,000 (the training mixture and its ground truth), D = 256,
+    p = 1.1 A: 256 sampled voxels of each volume against the oracle's
+    density, and the FSC between them against the oracle's FSC of the
+    same two GPU volumes."""
+    g, v, gt, rn = inputs.c4(b=1)
+    D, p = 256, 1.1
+    announce("voxelise N=200000 at D=256 (sampled) and FSC")
+    Va, Vb = _vox(gpu_lib, g, D, p), _vox(gpu_lib, gt, D, p)
+    idx = np.random.default_rng(59).integers(D // 2 - 64, D // 2 + 64, size=(256, 3))
+    for V, mix in ((Va, g), (Vb, gt)):
+        got = host(V)[idx[:, 0], idx[:, 1], idx[:, 2]]
+        ref = o_vol.density_at(mix, o_vol.voxel_points(D, p, idx), q_cut=Q_MATCHED)
+        assert normwise(got, ref) <= 1e-4
+    got = host(gpu_lib.fsc(Va, Vb))
+    a, b = host(Va).astype(np.float32), host(Vb).astype(np.float32)
+    ref = o_vol.fsc(a, b)
+    # The FFT runs in FP32: its error energy, spread over the spectrum, is
+    # about (log2(D^3) u)^2 of the total (u = 2^-24); shells whose own energy
+    # approaches that (the smooth volumes' high shells) carry a correlation
+    # error of about 2 sqrt(error / energy).
+    _, da, db = o_vol.fsc_sums(a, b)
+    s, w = o_vol.shell_index(D)
+    n_s = np.bincount(s[s <= D // 2], w[s <= D // 2], minlength=D // 2 + 1)
+    total = D ** 3 * max(float((a.astype(np.float64) ** 2).sum()), float((b.astype(np.float64) ** 2).sum()))
+    err_e = (np.log2(D ** 3) * 2.0 ** -24) ** 2 * total * n_s / D ** 3
+    bound = 1e-5 + 4.0 * np.sqrt(err_e / np.maximum(np.minimum(da, db), 1e-300))
+    worst = np.max(np.abs(got - ref) / bound)
+    announce(f"  max |FSC - oracle| / bound = {worst:.3f}; resolution "
+             f"{binding.Library.resolution(got, D, p):.2f} A (oracle {o_vol.resolution(ref, D, p):.2f} A)")
+    assert worst <= 1.0
+    assert binding.Library.resolution(got, D, p) == pytest.approx(o_vol.resolution(ref, D, p))
