@@ -20,7 +20,9 @@ __global__ void k_vox_scan(const int *count, int nbr, const float4 *rec, int N, 
 __global__ void k_vox_fill(const int4 *box, VoxGeom V, const int *off, int *cursor, int *list);
 __global__ void k_vox_eval(const float4 *rec, const int *list, const int *off, VoxGeom V,
                            const double *scale, float *vol);
-__global__ void k_fsc_energy(const float *va, const float *vb, int64_t n, int D, double *scale);
+constexpr int kEnergyBlocks = 1024;  // fixed grid of the energy pass (order-stable sums)
+__global__ void k_fsc_energy_part(const float *va, const float *vb, int64_t n, double *part);
+__global__ void k_fsc_energy_scale(const double *part, int D, double *scale);
 __global__ void k_fsc_shells(const float2 *fa, const float2 *fb, int D, const double *scale,
                              unsigned long long *sums);
 __global__ void k_fsc_final(const unsigned long long *sums, int ns, const double *scale,

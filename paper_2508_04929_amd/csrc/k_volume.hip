@@ -10,7 +10,7 @@
 // every Gaussian is listed under the bricks its q <= q_cut box touches
 // (counting sort); a block evaluates one brick against its list, two voxels
 // per thread.  Each voxel's sum is kept as a 64-bit fixed-point integer
-// (scale 2^e with the bound sum_n w_n < 2^61 / scale), so the result does
+// (scale 2^e with the bound sum_n |w_n| < 2^61 / scale), so the result does
 // not depend on the order of the list: it is reproducible bit for bit.
 //
 // FSC: the 3-D real DFT is the renderer's row pass (real rows along x, two
@@ -41,11 +41,14 @@ k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box, int *count) {
   const double cxx = syy * szz - syz * syz, cxy = sxz * syz - sxy * szz, cxz = sxy * syz - sxz * syy;
   const double cyy = sxx * szz - sxz * sxz, cyz = sxy * sxz - sxx * syz, czz = sxx * syy - sxy * sxy;
   const double det = fmax(sxx * cxx + sxy * cxy + sxz * cxz, 1e-30);
-  const double id = 1.0 / det;
   const float w = (float)((double)g0.w * 0.063493635934240969 / sqrt(det));  // (2 pi)^-3/2
+  // quadratic form scaled by log2(e) / 2, cross terms doubled, so that
+  // exp(-q / 2) = 2^-(x^T B x) with B = (log2(e) / 2) Sigma^-1
+  const double f = 0.72134752044448170 / det;  // log2(e) / 2 / det
   rec[3 * n] = make_float4(g0.x, g0.y, g0.z, w);
-  rec[3 * n + 1] = make_float4((float)(cxx * id), (float)(cxy * id), (float)(cxz * id), (float)(cyy * id));
-  rec[3 * n + 2] = make_float4((float)(cyz * id), (float)(czz * id), 0.f, 0.f);
+  rec[3 * n + 1] = make_float4((float)(cxx * f), (float)(2.0 * cxy * f), (float)(2.0 * cxz * f),
+                               (float)(cyy * f));
+  rec[3 * n + 2] = make_float4((float)(2.0 * cyz * f), (float)(czz * f), 0.f, 0.f);
   // axis-aligned box of the ellipsoid q <= q_cut: half extents sqrt(q_cut S_ii)
   const float mu[3] = {g0.x, g0.y, g0.z};
   const float hh[3] = {sqrtf(V.q_cut * g1.x), sqrtf(V.q_cut * g1.w), sqrtf(V.q_cut * g2.y)};
@@ -71,7 +74,7 @@ k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box, int *count) {
 }
 
 // Exclusive scan of the brick counts (one block) and the fixed-point scale
-// of the voxel sums from the bound sum_n w_n (fixed-order FP64 sum).
+// of the voxel sums from the bound sum_n |w_n| (fixed-order FP64 sum).
 __global__ void __launch_bounds__(1024)
 k_vox_scan(const int *count, int nbr, const float4 *rec, int N, int *off, double *scale) {
   __shared__ int part[1024];
@@ -83,7 +86,7 @@ k_vox_scan(const int *count, int nbr, const float4 *rec, int N, int *off, double
   for (int i = a; i < b; ++i) s += count[i];
   part[t] = s;
   double ws = 0.0;
-  for (int n = t; n < N; n += 1024) ws += (double)rec[3 * n].w;
+  for (int n = t; n < N; n += 1024) ws += fabs((double)rec[3 * n].w);
   wsum[t] = ws;
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan of the chunk sums
@@ -126,8 +129,23 @@ k_vox_fill(const int4 *box, VoxGeom V, const int *off, int *cursor, int *list) {
       }
 }
 
-// One brick of 8^3 voxels per block, two voxels per thread; its Gaussians
-// staged through LDS 256 at a time.
+// w 2^k as a 64-bit integer, truncated toward zero, read off the float's
+// bits (kb = k - 150 folds in the exponent bias and the mantissa width);
+// zero and subnormal w give 0.  Exact up to the truncation, and a function
+// of w alone, so the voxel sums do not depend on the order of their terms.
+__device__ __forceinline__ long long fixed_point(float w, int kb) {
+  const unsigned u = __float_as_uint(w);
+  const int e = (int)((u >> 23) & 255u);
+  const unsigned m = (u & 0x7fffffu) | 0x800000u;
+  const int sh = e + kb;
+  unsigned long long mag = sh >= 0 ? (unsigned long long)m << sh : (sh > -24 ? (unsigned long long)(m >> -sh) : 0ull);
+  mag = e ? mag : 0ull;
+  return (u >> 31) ? -(long long)mag : (long long)mag;
+}
+
+// One brick of 8^3 voxels per block, two voxels per thread (same x and y,
+// z two voxels apart, so the x-y part of the quadratic form is shared); its
+// Gaussians staged through LDS 256 at a time.
 __global__ void __launch_bounds__(256)
 k_vox_eval(const float4 *rec, const int *list, const int *off, VoxGeom V, const double *scale,
            float *vol) {
@@ -135,19 +153,16 @@ k_vox_eval(const float4 *rec, const int *list, const int *off, VoxGeom V, const 
   const int k = blockIdx.x;
   const int bx = k % V.nb, by = (k / V.nb) % V.nb, bz = k / (V.nb * V.nb);
   const int t = threadIdx.x;
-  float px[2], py[2], pz[2];
-  int vi[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int v = t + 256 * h;
-    const int ix = bx * kBrick + (v & 7), iy = by * kBrick + ((v >> 3) & 7), iz = bz * kBrick + (v >> 6);
-    px[h] = (float)(ix - V.c0) * V.pixel;
-    py[h] = (float)(iy - V.c0) * V.pixel;
-    pz[h] = (float)(iz - V.c0) * V.pixel;
-    vi[h] = (iz * V.D + iy) * V.D + ix;
-  }
+  const int ix = bx * kBrick + (t & 7), iy = by * kBrick + ((t >> 3) & 7);
+  const int iz0 = bz * kBrick + (t >> 6), iz1 = iz0 + 4;
+  const float px = (float)(ix - V.c0) * V.pixel, py = (float)(iy - V.c0) * V.pixel;
+  const float pz0 = (float)(iz0 - V.c0) * V.pixel, pz1 = (float)(iz1 - V.c0) * V.pixel;
   const double S = *scale;
-  long long acc[2] = {0, 0};
+  int k2;
+  frexp(S, &k2);
+  const int kb = (k2 - 1) - 150;            // S = 2^(k2 - 1)
+  const float qc = V.q_cut * 0.72134752f;   // the cut in the scaled form
+  long long acc0 = 0, acc1 = 0;
   const int b0 = off[k], cnt = off[k + 1] - b0;
   for (int c = 0; c < cnt; c += 256) {
     if (c + t < cnt) {
@@ -159,39 +174,71 @@ k_vox_eval(const float4 *rec, const int *list, const int *off, VoxGeom V, const 
     __syncthreads();
     const int m = min(256, cnt - c);
     for (int j = 0; j < m; ++j) {
-      const float4 a = sr[0][j], iv = sr[1][j], iw = sr[2][j];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const float dx = px[h] - a.x, dy = py[h] - a.y, dz = pz[h] - a.z;
-        const float q = dx * (iv.x * dx + 2.f * (iv.y * dy + iv.z * dz)) +
-                        dy * (iv.w * dy + 2.f * iw.x * dz) + iw.y * dz * dz;
-        if (q <= V.q_cut) acc[h] += __double2ll_rn((double)(a.w * __expf(-0.5f * q)) * S);
-      }
+      const float4 a = sr[0][j], B = sr[1][j], C = sr[2][j];
+      const float dx = px - a.x, dy = py - a.y;
+      const float cxy = fmaf(fmaf(B.x, dx, B.y * dy), dx, B.w * dy * dy);
+      const float cz = fmaf(B.z, dx, C.x * dy);
+      const float dz0 = pz0 - a.z, dz1 = pz1 - a.z;
+      const float q0 = fmaf(dz0, fmaf(C.y, dz0, cz), cxy);
+      const float q1 = fmaf(dz1, fmaf(C.y, dz1, cz), cxy);
+      if (q0 <= qc) acc0 += fixed_point(a.w * __builtin_amdgcn_exp2f(-q0), kb);
+      if (q1 <= qc) acc1 += fixed_point(a.w * __builtin_amdgcn_exp2f(-q1), kb);
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int h = 0; h < 2; ++h) vol[vi[h]] = (float)((double)acc[h] / S);
+  vol[((int64_t)iz0 * V.D + iy) * V.D + ix] = (float)((double)acc0 / S);
+  vol[((int64_t)iz1 * V.D + iy) * V.D + ix] = (float)((double)acc1 / S);
 }
 
 // ---------------------------------------------------------------------------
 // FSC
 // ---------------------------------------------------------------------------
 
-// sum of squares of each volume (fixed-order FP64), and the shell scale
-__global__ void __launch_bounds__(1024)
-k_fsc_energy(const float *va, const float *vb, int64_t n, int D, double *scale) {
-  __shared__ double r[2][1024];
+// Sum of squares of each volume in FP64: a fixed grid of kEnergyBlocks
+// blocks, each over a fixed strided subset, so the summation order (and the
+// scale below) does not depend on the device or on timing.
+__global__ void __launch_bounds__(256)
+k_fsc_energy_part(const float *va, const float *vb, int64_t n, double *part) {
+  __shared__ double r[2][256];
   const int t = threadIdx.x;
   double a = 0.0, b = 0.0;
-  for (int64_t i = t; i < n; i += 1024) {
+  const int64_t stride = (int64_t)kEnergyBlocks * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + t;
+  for (; i + 3 * stride < n; i += 4 * stride) {  // four independent loads in flight
+    const float a0 = va[i], a1 = va[i + stride], a2 = va[i + 2 * stride], a3 = va[i + 3 * stride];
+    const float b0 = vb[i], b1 = vb[i + stride], b2 = vb[i + 2 * stride], b3 = vb[i + 3 * stride];
+    a += (double)a0 * a0 + (double)a1 * a1 + (double)a2 * a2 + (double)a3 * a3;
+    b += (double)b0 * b0 + (double)b1 * b1 + (double)b2 * b2 + (double)b3 * b3;
+  }
+  for (; i < n; i += stride) {
     a += (double)va[i] * va[i];
     b += (double)vb[i] * vb[i];
   }
   r[0][t] = a;
   r[1][t] = b;
   __syncthreads();
-  for (int h = 512; h > 0; h >>= 1) {
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      r[0][t] += r[0][t + h];
+      r[1][t] += r[1][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[blockIdx.x] = r[0][0];
+    part[kEnergyBlocks + blockIdx.x] = r[1][0];
+  }
+}
+
+// Total of the block sums (fixed tree) and the shell scale from it.
+__global__ void __launch_bounds__(kEnergyBlocks)
+k_fsc_energy_scale(const double *part, int D, double *scale) {
+  __shared__ double r[2][kEnergyBlocks];
+  const int t = threadIdx.x;
+  r[0][t] = part[t];
+  r[1][t] = part[kEnergyBlocks + t];
+  __syncthreads();
+  for (int h = kEnergyBlocks / 2; h > 0; h >>= 1) {
     if (t < h) {
       r[0][t] += r[0][t + h];
       r[1][t] += r[1][t + h];

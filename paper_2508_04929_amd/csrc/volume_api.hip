@@ -107,13 +107,17 @@ int cs_fsc(cs_ctx *ctx, const float *vol_a, const float *vol_b, int32_t D, float
   const int Dh = D / 2 + 1, ns = D / 2 + 1;
   const size_t spec = (size_t)D * D * Dh * 8;
   const size_t o_a = 0, o_b = al256v(spec), o_scale = o_b + al256v(spec), o_sums = o_scale + 256;
-  rc = grow(ctx, &ctx->vol, &ctx->vol_bytes, o_sums + al256v((size_t)3 * ns * 8));
+  const size_t o_part = o_sums + al256v((size_t)3 * ns * 8);
+  rc = grow(ctx, &ctx->vol, &ctx->vol_bytes, o_part + (size_t)2 * kEnergyBlocks * 8);
   if (rc) return rc;
   char *w = (char *)ctx->vol;
   float2 *fa = (float2 *)(w + o_a), *fb = (float2 *)(w + o_b);
   double *scale = (double *)(w + o_scale);
   unsigned long long *sums = (unsigned long long *)(w + o_sums);
-  TLAUNCH(k_fsc_energy, dim3(1), dim3(1024), 0, st, vol_a, vol_b, (int64_t)D * D * D, D, scale);
+  double *part = (double *)(w + o_part);
+  TLAUNCH(k_fsc_energy_part, dim3(kEnergyBlocks), dim3(256), 0, st, vol_a, vol_b,
+          (int64_t)D * D * D, part);
+  TLAUNCH(k_fsc_energy_scale, dim3(1), dim3(kEnergyBlocks), 0, st, (const double *)part, D, scale);
   const dim3 rgrid(cdivv(D / 2, kRowTeamsVol), D);
   const size_t rlds = (size_t)(kRowTeamsVol * 2 + 1) * D * 8;
   const int cpw = D > 256 ? 8 : 16;

@@ -45,6 +45,22 @@ def test_voxelize_activations_and_cut(gpu_lib):
     assert normwise(V, ref) <= 1e-4
 
 
+def test_voxelize_signed_amplitudes(gpu_lib):
+    """Amplitudes of both signs whose weights cancel exactly (each Gaussian
+    paired with a shifted copy of opposite amplitude): the fixed-point
+    scale must come from sum |w|, not from the (zero) sum w."""
+    rng = np.random.default_rng(57)
+    g = inputs.mixture_anisotropic(rng, 150, 8.0)
+    two = inputs.Mixture(np.concatenate([g.means, g.means + np.float32(3.0)]),
+                         np.concatenate([g.log_scales, g.log_scales]),
+                         np.concatenate([g.quats, g.quats]),
+                         np.concatenate([g.amps, -g.amps]))
+    announce("voxelise 300 Gaussians with cancelling amplitudes, D=32")
+    V = host(_vox(gpu_lib, two, 32, 1.2))
+    ref = o_vol.voxelize(two, 32, 1.2, q_cut=Q_MATCHED)
+    assert normwise(V, ref) <= 1e-4
+
+
 def test_voxelize_is_exact_and_order_free(gpu_lib):
     rng = np.random.default_rng(54)
     g = inputs.mixture_anisotropic(rng, 3000, 20.0)
