@@ -83,8 +83,10 @@ def ctf_grid(D, pixel, defocus_u, defocus_v, astig, phase, voltage_kv,
 
 
 def ctf_grid_for(views):
-    """ctf_grid from a ``Views`` record of the input generator."""
-    return ctf_grid(views.D, views.pixel, views.defocus_u, views.defocus_v,
+    """ctf_grid from a ``Views`` record of the input generator (on the Angstrom
+    pixel ``pixel_a`` when the geometry is in other units)."""
+    pixel = views.pixel_a if getattr(views, "pixel_a", 0.0) > 0 else views.pixel
+    return ctf_grid(views.D, pixel, views.defocus_u, views.defocus_v,
                     views.astig, views.phase, views.voltage_kv, views.cs_mm,
                     views.amp_contrast, views.bfactor)
 

@@ -58,6 +58,7 @@ class Views:
     cs_mm: float = CS_MM
     amp_contrast: float = AMP_CONTRAST
     bfactor: float = 0.0
+    pixel_a: float = 0.0    # A pixel of the CTF grid when `pixel` is in other units (0: pixel)
 
     @property
     def b(self) -> int:
