@@ -103,6 +103,11 @@ typedef struct {
   double cs_mm;           /* spherical aberration, mm */
   double amp_contrast;    /* amplitude contrast w in [0, 1) */
   double bfactor;         /* B-factor, Angstrom^2 (0 = no envelope) */
+  float pixel_a;          /* pixel size in Angstrom of the CTF's frequency grid
+                             (index k -> k / (D pixel_a)); 0 = the geometry's own
+                             pixel.  Lets the geometry use other length units,
+                             e.g. the box-normalised [-1/2, 1/2] domain of
+                             Sec. 4.1 (pixel 1/D), while the CTF stays physical. */
 } cs_ctf;
 
 /* Gradient outputs, same shapes as the cs_gaussians arrays (overwritten).
@@ -473,6 +478,65 @@ int cs_ctf_filter(cs_ctx *ctx, const float *images, const cs_ctf *ctf, int32_t B
  * (seed, offset) give identical noise. */
 int cs_add_noise(cs_ctx *ctx, float *images, int32_t B, int32_t D, float snr_db, uint64_t seed,
                  int64_t offset, void *stream);
+
+/* ----------------------------------------------------------------------
+ * Training loop of Alg. 1 with the settings of Sec. 4.1 (batch size 1,
+ * one learning rate, box-normalised units)
+ * ---------------------------------------------------------------------- */
+
+/* FourierShift (Alg. 1, centre alignment; Sec. 4.1 applies the published
+ * particle translations to the observed images by a phase shift in Fourier
+ * space).  Translates every image of images [B][D][D] by direction * t_b,
+ * t_b = shift[b] = (t_x, t_y) in the units of `pixel`, band-limited and
+ * circular: the content at image-plane position r moves to r + direction *
+ * t_b, i.e. a_c = direction t_x / p columns and a_r = -direction t_y / p
+ * rows on the raster of Eq. 13; out = Re F^-1(F(Y) exp(-2 pi i (k_c a_c +
+ * k_r a_r) / D)) with signed frequency indices, which on the Nyquist lines
+ * of even D is the factor cos(pi a) (cos(pi (a_c + a_r)) at the corner).
+ * direction = -1 centres images observed with translations t.  D even with
+ * prime factors 2 and 3, at most 512; out may alias images.  Errors:
+ * CS_ERR_INVALID_ARG (null pointer, B < 1, pixel <= 0, direction not +-1),
+ * CS_ERR_UNSUPPORTED (D). */
+int cs_fourier_shift(cs_ctx *ctx, const float *images, const float *shift, int64_t B, int32_t D,
+                     float pixel, float direction, float *out, void *stream);
+
+/* InitAttributes (Alg. 1) with the values of Sec. 4.1 in box units (domain
+ * [-1/2, 1/2]^3): from normal draws z [N][3] (device) writes the flat
+ * pre-activation parameters params [11 N] = means [N][3] | log_scales [N][3]
+ * | quats [N][4] | amps [N]: means 0.075 z, every scale pre-activation
+ * softplus^-1(0.0075), quaternion (1, 0, 0, 0), amplitude pre-activation
+ * softplus^-1(1 / (2 N)); to be rendered with the softplus activations
+ * (Sec. 3.3.1).  N >= 1. */
+int cs_init_attributes(cs_ctx *ctx, const float *z, int64_t n, float *params, void *stream);
+
+/* A training set for the batch-1 loop (device arrays; images already
+ * centred, e.g. by cs_fourier_shift with direction -1). */
+typedef struct {
+  const float *images; /* [M][D][D] observed images */
+  const float *rot;    /* [M][3][3] their world-to-view rotations W */
+  int64_t m;           /* M >= 1 */
+  int32_t d;           /* D, as for cs_loss_and_grad */
+  float pixel;         /* geometry pixel, e.g. 1/D in box units */
+} cs_dataset;
+
+/* The inner loop of Alg. 1 at batch size 1 (Sec. 4.1): for k = 0 .. count-1
+ * and image i = order[k] (host array, 0 <= i < M): Rasterize at rot[i],
+ * ApplyCTF with image i's CTF (ctf: per-image arrays of length M, with
+ * pixel_a for box units; NULL = none), Loss against images[i] (reduction,
+ * Sec. 3.3.5), gradients (App. A.2), then one Adam step of every parameter
+ * (step number step0 + k + 1; lr, b1, b2, eps) on the flat parameters
+ * params [11 N] (layout of cs_init_attributes, activations scale_act /
+ * amp_act) with moments adam_m, adam_v [11 N] (zero before the first step).
+ * loss (device [count], or NULL) receives each step's loss before its
+ * update.  The image, rotation and CTF values of a step are first copied
+ * into fixed buffers, so with opt->graph = 1 the loss path is one replayed
+ * HIP graph per step.  Enqueued on `stream`; identical inputs give
+ * identical bits, with or without the graph. */
+int cs_train_sequential(cs_ctx *ctx, float *params, float *adam_m, float *adam_v, int64_t n,
+                        int32_t scale_act, int32_t amp_act, const cs_dataset *data,
+                        const cs_ctf *ctf, const cs_options *opt, int32_t reduction,
+                        const int64_t *order, int64_t count, int64_t step0, float lr, float b1,
+                        float b2, float eps, float *loss, void *stream);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@ import os
 import threading
 from typing import Optional
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +40,13 @@ class CsCtf(ctypes.Structure):
     _fields_ = [("defocus_u", ctypes.c_void_p), ("defocus_v", ctypes.c_void_p),
                 ("astig", ctypes.c_void_p), ("phase", ctypes.c_void_p),
                 ("voltage_kv", ctypes.c_double), ("cs_mm", ctypes.c_double),
-                ("amp_contrast", ctypes.c_double), ("bfactor", ctypes.c_double)]
+                ("amp_contrast", ctypes.c_double), ("bfactor", ctypes.c_double),
+                ("pixel_a", ctypes.c_float)]
+
+
+class CsDataset(ctypes.Structure):
+    _fields_ = [("images", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("d", ctypes.c_int32), ("pixel", ctypes.c_float)]
 
 
 class CsGrads(ctypes.Structure):
@@ -82,7 +89,8 @@ EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_b
            "cs_pose_bank_size", "cs_pose_bank_rotations", "cs_pose_grid_search", "cs_pose_refine", "cs_add_noise", "cs_cnn_tensor",
            "cs_pose_batch_create", "cs_pose_batch_destroy", "cs_pose_batch_load",
            "cs_pose_batch_search", "cs_pose_batch_refine", "cs_ctf_filter",
-           "cs_voxelize", "cs_fsc")
+           "cs_voxelize", "cs_fsc", "cs_fourier_shift", "cs_init_attributes",
+           "cs_train_sequential")
 
 
 class CryoSplatError(RuntimeError):
@@ -162,10 +170,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_pose_batch_search.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.cs_voxelize.argtypes = [vp, P(CsGaussians), i32, f32, f32, vp, vp]
     lib.cs_fsc.argtypes = [vp, vp, vp, i32, vp, vp]
+    lib.cs_fourier_shift.argtypes = [vp, vp, vp, i64, i32, f32, f32, vp, vp]
+    lib.cs_init_attributes.argtypes = [vp, vp, i64, vp, vp]
+    lib.cs_train_sequential.argtypes = [vp, vp, vp, vp, i64, i32, i32, P(CsDataset), P(CsCtf),
+                                        P(CsOptions), i32, vp, i64, i64, f32, f32, f32, f32, vp,
+                                        vp]
     lib.cs_pose_batch_refine.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
     for name in ("cs_pose_batch_create", "cs_pose_batch_load", "cs_pose_batch_search",
-                 "cs_pose_batch_refine", "cs_ctf_filter", "cs_voxelize", "cs_fsc", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
+                 "cs_pose_batch_refine", "cs_ctf_filter", "cs_voxelize", "cs_fsc",
+                 "cs_fourier_shift", "cs_init_attributes", "cs_train_sequential", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
                  "cs_pose_grid_search", "cs_pose_refine"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("cs_cnn_create", "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward",
@@ -187,6 +201,7 @@ class Ctf:
     cs_mm: float = 2.7
     amp_contrast: float = 0.1
     bfactor: float = 0.0
+    pixel_a: float = 0.0  # Angstrom pixel of the CTF grid when the geometry uses other units
 
 
 @dataclasses.dataclass
@@ -279,10 +294,7 @@ class Library:
                     float(pixel))
         c = None
         if ctf is not None:
-            c = CsCtf(_ptr(ctf.defocus_u, "defocus_u", dev, (b,)), _ptr(ctf.defocus_v, "defocus_v", dev, (b,)),
-                      _ptr(ctf.astig, "astig", dev, (b,)), _ptr(ctf.phase, "phase", dev, (b,)),
-                      float(ctf.voltage_kv), float(ctf.cs_mm), float(ctf.amp_contrast),
-                      float(ctf.bfactor))
+            c = _ctf_struct(ctf, b, dev)
         o = None
         if options is not None:
             o = CsOptions(float(options.q_cut), int(options.tile), int(options.halo),
@@ -339,6 +351,72 @@ class Library:
                                          out.data_ptr(), torch.cuda.current_stream(dev).cuda_stream),
                     "cs_fsc")
         return out
+
+    def fourier_shift(self, images, shift, pixel, direction=1, out=None):
+        """Translate images [B][D][D] by direction * shift [B][2] (band-limited,
+        circular; cs_fourier_shift).  direction = -1 centres them."""
+        dev = images.device
+        B, D = images.shape[0], images.shape[-1]
+        _ptr(images, "images", dev, (B, D, D))
+        _ptr(shift, "shift", dev, (B, 2))
+        if out is None:
+            out = torch.empty_like(images)
+        _ptr(out, "out", dev, (B, D, D))
+        ctx = self.ctx(dev)
+        self._check(ctx, self.lib.cs_fourier_shift(ctx, images.data_ptr(), shift.data_ptr(), B, int(D),
+                                                   float(pixel), float(direction), out.data_ptr(),
+                                                   torch.cuda.current_stream(dev).cuda_stream),
+                    "cs_fourier_shift")
+        return out
+
+    def init_attributes(self, z, out=None):
+        """Flat initial pre-activation parameters [11 N] from normal draws
+        z [N][3] (cs_init_attributes)."""
+        dev = z.device
+        n = z.shape[0]
+        _ptr(z, "z", dev, (n, 3))
+        if out is None:
+            out = torch.empty(11 * n, device=dev, dtype=torch.float32)
+        _ptr(out, "params", dev, (11 * n,))
+        ctx = self.ctx(dev)
+        self._check(ctx, self.lib.cs_init_attributes(ctx, z.data_ptr(), n, out.data_ptr(),
+                                                     torch.cuda.current_stream(dev).cuda_stream),
+                    "cs_init_attributes")
+        return out
+
+    def train_sequential(self, params, adam_m, adam_v, images, rot, pixel, order, step0, lr,
+                         ctf=None, options=None, reduction="sum", b1=0.9, b2=0.999, eps=1e-8,
+                         scale_act="softplus", amp_act="softplus", loss=None):
+        """Batch-1 steps of Alg. 1 over the images in ``order`` (host int64
+        indices) on flat parameters [11 N] (cs_train_sequential)."""
+        dev = params.device
+        np_ = params.numel()
+        if np_ % 11:
+            raise ValueError("params must hold 11 values per Gaussian")
+        n = np_ // 11
+        for t, nm in ((params, "params"), (adam_m, "adam_m"), (adam_v, "adam_v")):
+            _ptr(t, nm, dev, (np_,))
+        M, D = images.shape[0], images.shape[-1]
+        data = CsDataset(_ptr(images, "images", dev, (M, D, D)), _ptr(rot, "rot", dev, (M, 3, 3)),
+                         M, int(D), float(pixel))
+        order = np.ascontiguousarray(order, dtype=np.int64)
+        c = _ctf_struct(ctf, M, dev)
+        o = None
+        if options is not None:
+            o = CsOptions(float(options.q_cut), int(options.tile), int(options.halo),
+                          int(options.budget), int(options.graph))
+        if loss is not None:
+            _ptr(loss, "loss", dev, (len(order),))
+        ctx = self.ctx(dev)
+        red = {"sum": 0, "mean": 1}[reduction]
+        rc = self.lib.cs_train_sequential(
+            ctx, params.data_ptr(), adam_m.data_ptr(), adam_v.data_ptr(), n, _SCALE_ACT[scale_act],
+            _AMP_ACT[amp_act], ctypes.byref(data), self._ref(c), self._ref(o), red,
+            order.ctypes.data_as(ctypes.c_void_p), len(order), int(step0), float(lr), float(b1),
+            float(b2), float(eps), loss.data_ptr() if loss is not None else None,
+            torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_train_sequential")
+        return loss
 
     @staticmethod
     def resolution(fsc, D, pixel, threshold=0.143):
@@ -725,11 +803,7 @@ class PoseBank:
     def _ctf(self, ctf, P):
         if ctf is None:
             return None
-        d = self.device
-        return CsCtf(_ptr(ctf.defocus_u, "defocus_u", d, (P,)), _ptr(ctf.defocus_v, "defocus_v", d, (P,)),
-                     _ptr(ctf.astig, "astig", d, (P,)), _ptr(ctf.phase, "phase", d, (P,)),
-                     float(ctf.voltage_kv), float(ctf.cs_mm), float(ctf.amp_contrast),
-                     float(ctf.bfactor))
+        return _ctf_struct(ctf, P, self.device)
 
     def _outs(self, P, S, ncols, want_scores):
         d = self.device
@@ -789,7 +863,7 @@ def _ctf_struct(ctf, P, device):
                  _ptr(ctf.defocus_v, "defocus_v", device, (P,)),
                  _ptr(ctf.astig, "astig", device, (P,)), _ptr(ctf.phase, "phase", device, (P,)),
                  float(ctf.voltage_kv), float(ctf.cs_mm), float(ctf.amp_contrast),
-                 float(ctf.bfactor))
+                 float(ctf.bfactor), float(ctf.pixel_a))
 
 
 class PoseBatch:

@@ -212,6 +212,8 @@ int validate(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf
     if (!(ctf->voltage_kv > 0.0)) return fail(ctx, CS_ERR_INVALID_ARG, "voltage must be positive");
     if (!(ctf->amp_contrast >= 0.0 && ctf->amp_contrast < 1.0))
       return fail(ctx, CS_ERR_INVALID_ARG, "amplitude contrast must be in [0, 1)");
+    if (!(ctf->pixel_a >= 0.0f) || !std::isfinite(ctf->pixel_a))
+      return fail(ctx, CS_ERR_INVALID_ARG, "CTF pixel size must be >= 0");
   }
   if (opt) {
     if (opt->tile != 0 && (opt->tile < 16 || opt->tile > 128))
@@ -249,6 +251,10 @@ Geom make_geom(const cs_gaussians *g, const cs_views *v, const cs_options *opt) 
 }  // namespace
 
 namespace cs {
+
+float ctf_pixel(const cs_ctf *ctf, float geometry_pixel) {
+  return (ctf && ctf->pixel_a > 0.f) ? ctf->pixel_a : geometry_pixel;
+}
 
 CtfDev make_ctf(const cs_ctf *ctf) {
   CtfDev c{};
@@ -421,7 +427,8 @@ int fft_setup(cs_ctx *ctx, const Geom &G, FftLaunch &F) {
 int launch_ctf_table(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   const Geom &G = P.G;
   const size_t n = (size_t)G.B * G.D * (G.D / 2 + 1);
-  TLAUNCH(k_ctf_table, dim3(cdiv(n, 256)), dim3(256), 0, st, G.D, G.pixel, make_ctf(P.ctf), G.B,
+  TLAUNCH(k_ctf_table, dim3(cdiv(n, 256)), dim3(256), 0, st, G.D, ctf_pixel(P.ctf, G.pixel),
+          make_ctf(P.ctf), G.B,
           (float *)(P.ws + P.L.ctf));
   return CS_OK;
 }
@@ -692,6 +699,14 @@ int time_problem(cs_ctx *ctx, const cs_problem &pr, int reps, hipStream_t st, do
 
 }  // namespace
 
+namespace cs {
+
+int run_loss(cs_ctx *ctx, const cs_problem &pr, bool use_graph, hipStream_t st) {
+  return run_loss_problems(ctx, &pr, 1, use_graph, st);
+}
+
+}  // namespace cs
+
 extern "C" {
 
 int cs_create(int device, cs_ctx **out) {
@@ -734,6 +749,7 @@ void cs_destroy(cs_ctx *ctx) {
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->aux) (void)hipFree(ctx->aux);
   if (ctx->vol) (void)hipFree(ctx->vol);
+  if (ctx->train) (void)hipFree(ctx->train);
   for (auto &kv : ctx->twiddles) (void)hipFree(kv.second);
   delete ctx;
 }

@@ -38,6 +38,9 @@ struct cs_ctx {
   // scratch of the voxelisation and FSC entry points
   void *vol = nullptr;
   size_t vol_bytes = 0;
+  // scratch of the training loop (gradients, staged image) and FourierShift
+  void *train = nullptr;
+  size_t train_bytes = 0;
 };
 
 namespace cs {
@@ -57,6 +60,9 @@ bool fft_plan(int L, FftPlan &P);                          // radix (4, 2, 3) pl
 double electron_wavelength_A(double kv);                  // relativistic, Angstrom
 int get_twiddles(cs_ctx *ctx, int L, const float2 **out);  // cached device table
 CtfDev make_ctf(const cs_ctf *ctf);                        // disabled when ctf is null
+float ctf_pixel(const cs_ctf *ctf, float geometry_pixel);  // pixel of the CTF's frequency grid
+// one loss-and-gradient problem, eager or through the context's graph cache
+int run_loss(cs_ctx *ctx, const cs_problem &pr, bool use_graph, hipStream_t st);
 
 }  // namespace cs
 

@@ -202,6 +202,8 @@ __global__ void k_ctf_table(int L, float pixel, CtfDev ctf, int B, float *table)
 __global__ void k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw,
                                const float *table);
 
+__global__ void k_fft_cols_shift(float2 *spec, FftPlan P, const float2 *tw, int cpw,
+                                 const float *shift, float inv_pixel, float sign);
 __global__ void k_fft_rows_inv(const float2 *spec, FftPlan P, const float2 *tw, int B,
                                float *dst);
 

@@ -140,10 +140,12 @@ k_ctf_table(int L, float pixel, CtfDev ctf, int B, float *table) {
 
 // ---------------------------------------------------------------------------
 // Column pass: for cpw adjacent half-spectrum columns per block, FFT over
-// rows, times the table H^ / D^2, inverse FFT over rows, in place.
+// rows, times a multiplier mul(ky, kx, z) of image blockIdx.y, inverse FFT
+// over rows, in place.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, const float *table) {
+template <class Mul>
+__device__ __forceinline__ void fft_cols_apply(float2 *spec, const FftPlan &P, const float2 *tw,
+                                               int cpw, const Mul &mul) {
   extern __shared__ float2 lds[];
   const int L = P.L, Dh = L / 2 + 1;
   const int b = blockIdx.y;
@@ -163,12 +165,7 @@ k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, const 
   float2 *x = lds + team * 2 * L, *y = x + L;
   float2 *res = fft_team(x, y, P, twl, t, ts, false);
   const int kx = kx0 + team;
-  const float *hcol = table + (size_t)b * L * Dh;
-  for (int ky = t; ky < L; ky += ts) {
-    const float h = (kx < Dh) ? hcol[(size_t)ky * Dh + kx] : 0.f;
-    const float2 z = res[ky];
-    res[ky] = make_float2(z.x * h, z.y * h);
-  }
+  for (int ky = t; ky < L; ky += ts) res[ky] = (kx < Dh) ? mul(ky, kx, res[ky]) : make_float2(0.f, 0.f);
   __syncthreads();
   float2 *other = (res == x) ? y : x;
   float2 *out = fft_team(res, other, P, twl, t, ts, true);
@@ -179,6 +176,58 @@ k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, const 
     const int kc = kx0 + c;
     if (kc < Dh) img[(size_t)r * Dh + kc] = lds[c * 2 * L + oofs + r];
   }
+}
+
+// times the table H^ / D^2 (Eq. 14)
+__global__ void __launch_bounds__(256)
+k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, const float *table) {
+  const int L = P.L, Dh = L / 2 + 1;
+  const float *hcol = table + (size_t)blockIdx.y * L * Dh;
+  fft_cols_apply(spec, P, tw, cpw, [&](int ky, int kx, float2 z) {
+    const float h = hcol[(size_t)ky * Dh + kx];
+    return make_float2(z.x * h, z.y * h);
+  });
+}
+
+// Translation of image b by (a_c, a_r) = (sign t_x / p, -sign t_y / p)
+// columns / rows (the row axis is y-flipped, Eq. 13): times
+// exp(-2 pi i (kx a_c + ky a_r) / L) / L^2 with signed frequency indices,
+// made Hermitian on the Nyquist lines of even L (the real part of the
+// complex inverse transform): cos(pi a) there in place of the exponential,
+// cos(pi (a_c + a_r)) at the corner.  Turns in FP64, one FP32 sincos.
+__global__ void __launch_bounds__(256)
+k_fft_cols_shift(float2 *spec, FftPlan P, const float2 *tw, int cpw, const float *shift,
+                 float inv_pixel, float sign) {
+  const int L = P.L, b = blockIdx.y;
+  const double ac = (double)(sign * shift[2 * b] * inv_pixel);
+  const double ar = -(double)(sign * shift[2 * b + 1] * inv_pixel);
+  const bool even = (L % 2) == 0;
+  const int half = L / 2;
+  const float norm = 1.f / ((float)L * (float)L);
+  fft_cols_apply(spec, P, tw, cpw, [&](int ky, int kx, float2 z) {
+    const bool nx = even && kx == half, ny = even && ky == half;
+    const int fy = ky < (L + 1) / 2 ? ky : ky - L;
+    double turns;
+    double amp = 1.0;
+    if (nx && ny) {
+      turns = 0.0;
+      amp = cos(M_PI * (ac + ar));
+    } else if (nx) {
+      turns = -(double)fy * ar / L;
+      amp = cos(M_PI * ac);
+    } else if (ny) {
+      turns = -(double)kx * ac / L;
+      amp = cos(M_PI * ar);
+    } else {
+      turns = -((double)kx * ac + (double)fy * ar) / L;
+    }
+    const float red = (float)((turns - rint(turns)) * (2.0 * M_PI));
+    float sn, cs;
+    sincosf(red, &sn, &cs);
+    const float m = (float)amp * norm;
+    const float re = cs * m, im = sn * m;
+    return make_float2(z.x * re - z.y * im, z.x * im + z.y * re);
+  });
 }
 
 // Hermitian-packed inverse of two half-spectrum rows into one complex row.

@@ -125,7 +125,8 @@ int ctf_filter_into(cs_ctx *ctx, int D, float pixel, const float *Y, const cs_ct
   int rc = get_twiddles(ctx, D, &tw);
   if (rc) return rc;
   const size_t n = (size_t)P * D * Dh;
-  hipLaunchKernelGGL(k_ctf_table, dim3(cdivu(n, 256)), dim3(256), 0, st, D, pixel, make_ctf(ctf), P,
+  hipLaunchKernelGGL(k_ctf_table, dim3(cdivu(n, 256)), dim3(256), 0, st, D, ctf_pixel(ctf, pixel),
+                     make_ctf(ctf), P,
                      table);
   LAUNCHCHK("k_ctf_table");
   const dim3 rgrid(cdivu(D / 2, kRowTeamsHost), P);
@@ -336,13 +337,15 @@ int cs_pose_batch_load(cs_pose_batch *q, const float *images, const cs_ctf *ctf,
   if (!images) return fail(ctx, CS_ERR_INVALID_ARG, "null images");
   if (P < 1 || P > q->cap) return fail(ctx, CS_ERR_INVALID_ARG, "particle count must be in [1, capacity]");
   if (ctf && (!ctf->defocus_u || !ctf->defocus_v)) return fail(ctx, CS_ERR_INVALID_ARG, "null defocus");
+  if (ctf && (!(ctf->pixel_a >= 0.f) || !std::isfinite(ctf->pixel_a)))
+    return fail(ctx, CS_ERR_INVALID_ARG, "CTF pixel size must be >= 0");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   if (q->D == kPrepD) {
     const float2 *tw = nullptr;
     int rc = get_twiddles(ctx, q->D, &tw);
     if (rc) return rc;
-    HIPCHK(pose_prep128(images, tw, q->pixel, make_ctf(ctf), P, q->F8, filtered, standardized,
+    HIPCHK(pose_prep128(images, tw, ctf_pixel(ctf, q->pixel), make_ctf(ctf), P, q->F8, filtered, standardized,
                         q->zb, q->w, q->yy, st));
   } else {
     int rc = ctf_filter_into(ctx, q->D, q->pixel, images, ctf, P, q->table, q->spec, q->Z, st);
@@ -527,6 +530,8 @@ int cs_ctf_filter(cs_ctx *ctx, const float *images, const cs_ctf *ctf, int32_t B
     return fail(ctx, CS_ERR_UNSUPPORTED, "D must be even with prime factors 2, 3 (<= 512)");
   if (!(pixel > 0.f)) return fail(ctx, CS_ERR_INVALID_ARG, "pixel size must be positive");
   if (ctf && (!ctf->defocus_u || !ctf->defocus_v)) return fail(ctx, CS_ERR_INVALID_ARG, "null defocus");
+  if (ctf && (!(ctf->pixel_a >= 0.f) || !std::isfinite(ctf->pixel_a)))
+    return fail(ctx, CS_ERR_INVALID_ARG, "CTF pixel size must be >= 0");
   HIPCHK(hipSetDevice(ctx->device));
   const size_t Dh = D / 2 + 1;
   const size_t tb = al256((size_t)B * D * Dh * 4), sb = al256((size_t)B * D * Dh * 8);

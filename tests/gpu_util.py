@@ -25,7 +25,8 @@ def view_args(v):
 def ctf_arg(v):
     return binding.Ctf(defocus_u=dev(v.defocus_u), defocus_v=dev(v.defocus_v),
                        astig=dev(v.astig), phase=dev(v.phase), voltage_kv=v.voltage_kv,
-                       cs_mm=v.cs_mm, amp_contrast=v.amp_contrast, bfactor=v.bfactor)
+                       cs_mm=v.cs_mm, amp_contrast=v.amp_contrast, bfactor=v.bfactor,
+                       pixel_a=v.pixel_a)
 
 
 def normwise(got, ref):

@@ -47,3 +47,9 @@ def test_null_context_arguments_are_rejected(lib):
     assert L.cs_cnn_forward_std(None, None, 1, None, None, None, None) == -1
     assert L.cs_pose_grid_search(None, None, None, 1, 2, None, None, None, None, None) == -1
     assert L.cs_cnn_param_count(None) == -1 and L.cs_pose_bank_size(None) == -1
+    assert L.cs_voxelize(None, None, 8, 1.0, 0.0, None, None) == -1
+    assert L.cs_fsc(None, None, None, 8, None, None) == -1
+    assert L.cs_fourier_shift(None, None, None, 1, 8, 1.0, 1.0, None, None) == -1
+    assert L.cs_init_attributes(None, None, 1, None, None) == -1
+    assert L.cs_train_sequential(None, None, None, None, 1, 1, 1, None, None, None, 0, None, 0, 0,
+                                 1e-3, 0.9, 0.999, 1e-8, None, None) == -1
