@@ -315,6 +315,60 @@ def run_volume(reps: int = 5):
             "resolution_A": binding.Library.resolution(curve.cpu().numpy(), D, p)}
 
 
+def run_trainer(steps: int = 1024, sizes=((256, 2048), (256, 10000), (256, 30000))):
+    """The paper-faithful loop of Alg. 1 at batch size 1 (Sec. 4.1): box
+    units, the paper's initialisation, Adam per particle.  Particles: a
+    domain mixture (20,000 Gaussians, 3 A widths) at Haar-random poses with
+    CTF (1.1 A pixels) and white noise at 0 dB, translations up to 2 px
+    (centred by FourierShift before training).  Per size: one warm-up pass,
+    then `steps` timed steps with the loss path replayed as a HIP graph,
+    and the same steps launched eagerly."""
+    import numpy as np
+    import torch
+
+    from paper_2508_04929_amd import binding, inputs, trainer
+
+    lib = binding.library()
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    out = []
+    for D, N in sizes:
+        rng = np.random.default_rng(7)
+        p_a = 1.1
+        L = D * p_a
+        gt = inputs.mixture_domains(rng, 20000, radius=0.2 * L, scale_mu=np.log(3.0))
+        amps = np.asarray(gt.amps, np.float64)
+        g = [t(np.asarray(gt.means, np.float64) / L), t(np.asarray(gt.log_scales, np.float64) - np.log(L)),
+             t(gt.quats), t(0.5 * amps / amps.sum())]
+        v = inputs.views(rng, steps, D, 1.0 / D)
+        rot, shift = t(v.rot), t(rng.uniform(-2, 2, size=(steps, 2)) / D)
+        ctf = binding.Ctf(t(v.defocus_u), t(v.defocus_v), t(v.astig), t(v.phase), v.voltage_kv,
+                          v.cs_mm, v.amp_contrast, v.bfactor, pixel_a=p_a)
+        images = lib.render(*g, rot, shift, D, 1.0 / D, ctf=ctf)
+        lib.add_noise(images, 0.0, seed=11)
+        data = trainer.Trainer.centre(lib, trainer.Dataset(images=images, rot=rot, shift=shift, ctf=ctf))
+        res = {"D": D, "N": N, "steps": steps}
+        for graph in (True, False):
+            tr = trainer.Trainer(lib, t(rng.standard_normal((N, 3))), graph=graph)
+            tr.epoch(data, rng.permutation(steps), 1e-3)          # warm-up pass
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            tr.epoch(data, rng.permutation(steps), 1e-3)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            key = "graph" if graph else "eager"
+            res[f"{key}_images_per_s"] = steps / (ms * 1e-3)
+            res[f"{key}_ms_per_step"] = ms / steps
+        out.append(res)
+        print(f"[bench] trainer D={D} N={N}: {res['graph_images_per_s']:.0f} img/s graphed, "
+              f"{res['eager_images_per_s']:.0f} eager", file=sys.stderr, flush=True)
+    return {"workload": ("batch-1 Adam training of Alg. 1 (box units, paper initialisation, "
+                         "softplus activations, CTF, 0 dB noise, FourierShift-centred particles)"),
+            "sizes": out}
+
+
 def run_batched(reps: int = 10, autotune: bool = True):
     """Uneven batching: 8 mixtures (N = 5k ... 150k) x 128 images, D in
     {128, 192, 256}, fwd + adjoint of all problems in one persistent launch
@@ -388,6 +442,8 @@ def main():
     ap.add_argument("--no-pose", dest="pose", action="store_false",
                     help="skip the learned-pose experiment (network trained on 200k renders, "
                          "then learned proposal + refinement vs grid search; about a minute)")
+    ap.add_argument("--no-trainer", dest="trainer", action="store_false",
+                    help="skip the batch-1 training-loop measurement")
     ap.add_argument("--no-volume", dest="volume", action="store_false",
                     help="skip the voxelisation / FSC measurement")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
@@ -409,6 +465,8 @@ def main():
               file=sys.stderr, flush=True)
     res = run(args)
     res["cpu_baseline"] = cpu
+    if args.trainer:
+        res["trainer"] = run_trainer()
     if args.volume:
         res["volume"] = run_volume()
         print(f"[bench] volume: voxelise {res['volume']['voxelize_ms']:.2f} ms, "

@@ -24,6 +24,17 @@ constexpr float kDefaultQCut = 27.631021115928547f;  // 2 ln 1e6
 constexpr int kDefaultTile = 64;
 constexpr int kDefaultHalo = 16;
 constexpr int kDefaultBudget = 2048;
+constexpr int kMinAutoBudget = 256;
+
+// Automatic work-item size: the default budget while N B Gaussian-image
+// pairs fill about a thousand work items, smaller (down to 256) for calls
+// with few images, which otherwise leave most of the chip idle (batch-1
+// training puts a whole mixture into a few tiles of one image).
+int auto_budget(int64_t N, int64_t B) {
+  int b = kDefaultBudget;
+  while (b > kMinAutoBudget && N * B < (int64_t)b * 1024) b >>= 1;
+  return b;
+}
 constexpr int kMaxD = 512;
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -166,6 +177,14 @@ int ensure_ws(cs_ctx *ctx, size_t need, hipStream_t stream) {
 
 namespace cs {
 
+int fft_cols_per_block(int D, int64_t B) {
+  int c = D > 256 ? 8 : 16;
+  // fewer columns per block (each column's transform is unchanged) until the
+  // column pass has a few hundred blocks: small batches would idle the chip
+  while (c > 2 && (int64_t)((D / 2 + c) / c) * B < 512) c >>= 1;
+  return c;
+}
+
 int get_twiddles(cs_ctx *ctx, int L, const float2 **out) {
   auto it = ctx->twiddles.find(L);
   if (it != ctx->twiddles.end()) { *out = it->second; return CS_OK; }
@@ -242,7 +261,7 @@ Geom make_geom(const cs_gaussians *g, const cs_views *v, const cs_options *opt) 
   G.ntx = (G.D + G.T - 1) / G.T;
   G.ntiles = G.ntx * G.ntx;
   G.K = G.ntiles + 1;
-  G.budget = (opt && opt->budget) ? opt->budget : kDefaultBudget;
+  G.budget = (opt && opt->budget) ? opt->budget : auto_budget(G.N, G.B);
   G.scale_act = g->scale_act;
   G.amp_act = g->amp_act;
   return G;
@@ -418,7 +437,7 @@ int fft_setup(cs_ctx *ctx, const Geom &G, FftLaunch &F) {
   if (rc) return rc;
   F.rgrid = dim3(cdiv(G.D / 2, 4), G.B);
   F.rlds = (size_t)(4 * 2 + 1) * G.D * 8;  // four row pairs (ping-pong) + twiddles
-  F.cpw = G.D > 256 ? 8 : 16;
+  F.cpw = fft_cols_per_block(G.D, G.B);
   F.cgrid = dim3(cdiv(G.D / 2 + 1, F.cpw), G.B);
   F.clds = (size_t)(F.cpw * 2 + 1) * G.D * 8;
   return CS_OK;
@@ -863,7 +882,7 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
         }
         if (rc) break;
       }
-      const int budgets[] = {1024, 4096, 8192};
+      const int budgets[] = {256, 512, 1024, 4096, 8192};
       for (int bgt : budgets) {
         if (rc) break;
         pr.opt.tile = best[0];

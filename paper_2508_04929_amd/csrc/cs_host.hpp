@@ -59,6 +59,7 @@ inline int fail(cs_ctx *c, int code, const char *fmt, ...) {
 bool fft_plan(int L, FftPlan &P);                          // radix (4, 2, 3) plan, L <= 512
 double electron_wavelength_A(double kv);                  // relativistic, Angstrom
 int get_twiddles(cs_ctx *ctx, int L, const float2 **out);  // cached device table
+int fft_cols_per_block(int D, int64_t B);                   // columns per block of the column pass
 CtfDev make_ctf(const cs_ctf *ctf);                        // disabled when ctf is null
 float ctf_pixel(const cs_ctf *ctf, float geometry_pixel);  // pixel of the CTF's frequency grid
 // one loss-and-gradient problem, eager or through the context's graph cache

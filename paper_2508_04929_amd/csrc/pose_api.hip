@@ -131,7 +131,7 @@ int ctf_filter_into(cs_ctx *ctx, int D, float pixel, const float *Y, const cs_ct
   LAUNCHCHK("k_ctf_table");
   const dim3 rgrid(cdivu(D / 2, kRowTeamsHost), P);
   const size_t rlds = (size_t)(kRowTeamsHost * 2 + 1) * D * 8;
-  const int cpw = D > 256 ? 8 : 16;
+  const int cpw = fft_cols_per_block(D, P);
   const dim3 cgrid(cdivu(Dh, cpw), P);
   const size_t clds = (size_t)(cpw * 2 + 1) * D * 8;
   hipLaunchKernelGGL(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, Y, P_, tw, P, spec);

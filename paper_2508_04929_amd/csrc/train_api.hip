@@ -44,11 +44,11 @@ int cs_fourier_shift(cs_ctx *ctx, const float *images, const float *shift, int64
   if (rc) return rc;
   float2 *spec = (float2 *)ctx->aux;
   const size_t rlds = (size_t)(kRowTeamsShift * 2 + 1) * D * 8;
-  const int cpw = D > 256 ? 8 : 16;
-  const size_t clds = (size_t)(cpw * 2 + 1) * D * 8;
   const size_t npix = (size_t)D * D;
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     const int nb = (int)std::min<int64_t>(chunk, B - b0);
+    const int cpw = fft_cols_per_block(D, nb);
+    const size_t clds = (size_t)(cpw * 2 + 1) * D * 8;
     const dim3 rgrid(cdivt(D / 2, kRowTeamsShift), nb);
     TLAUNCH(k_fft_rows_fwd, rgrid, dim3(256), rlds, st, images + b0 * npix, P, tw, nb, spec);
     TLAUNCH(k_fft_cols_shift, dim3(cdivt(Dh, cpw), nb), dim3(256), clds, st, spec, P, tw, cpw,
