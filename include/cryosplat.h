@@ -538,6 +538,23 @@ int cs_train_sequential(cs_ctx *ctx, float *params, float *adam_m, float *adam_v
                         const int64_t *order, int64_t count, int64_t step0, float lr, float b1,
                         float b2, float eps, float *loss, void *stream);
 
+/* Densification (Alg. 1: IsDoubleGaussians / SplitGaussian; App. C.1 gives
+ * no split rule).  Splits every Gaussian of the flat parameters params
+ * [11 N] (layout of cs_init_attributes, activations scale_act / amp_act)
+ * into two, written to out_params [22 N] (2N Gaussians, same layout): with
+ * k the axis of the largest scale (compared on the stored pre-activations,
+ * lowest index among equals), s_k its activated scale and u = R(q) e_k,
+ * the children sit at mu + (s_k / 2) u (index i) and mu - (s_k / 2) u
+ * (index N + i), with s_k' = s_k sqrt(3) / 2, amplitude A / 2 and the other
+ * scales and the quaternion unchanged, so each pair keeps the parent's
+ * mass, mean and covariance.  With adam_m, adam_v [11 N] and out_m, out_v
+ * [22 N] (all four, or none) both children inherit the parent's moments.
+ * Outputs must not overlap inputs or each other.  FP64 arithmetic, FP32
+ * results. */
+int cs_split_gaussians(cs_ctx *ctx, const float *params, const float *adam_m, const float *adam_v,
+                       int64_t n, int32_t scale_act, int32_t amp_act, float *out_params,
+                       float *out_m, float *out_v, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,7 +90,7 @@ EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_b
            "cs_pose_batch_create", "cs_pose_batch_destroy", "cs_pose_batch_load",
            "cs_pose_batch_search", "cs_pose_batch_refine", "cs_ctf_filter",
            "cs_voxelize", "cs_fsc", "cs_fourier_shift", "cs_init_attributes",
-           "cs_train_sequential")
+           "cs_train_sequential", "cs_split_gaussians")
 
 
 class CryoSplatError(RuntimeError):
@@ -172,6 +172,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_fsc.argtypes = [vp, vp, vp, i32, vp, vp]
     lib.cs_fourier_shift.argtypes = [vp, vp, vp, i64, i32, f32, f32, vp, vp]
     lib.cs_init_attributes.argtypes = [vp, vp, i64, vp, vp]
+    lib.cs_split_gaussians.argtypes = [vp, vp, vp, vp, i64, i32, i32, vp, vp, vp, vp]
     lib.cs_train_sequential.argtypes = [vp, vp, vp, vp, i64, i32, i32, P(CsDataset), P(CsCtf),
                                         P(CsOptions), i32, vp, i64, i64, f32, f32, f32, f32, vp,
                                         vp]
@@ -179,7 +180,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
     for name in ("cs_pose_batch_create", "cs_pose_batch_load", "cs_pose_batch_search",
                  "cs_pose_batch_refine", "cs_ctf_filter", "cs_voxelize", "cs_fsc",
-                 "cs_fourier_shift", "cs_init_attributes", "cs_train_sequential", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
+                 "cs_fourier_shift", "cs_init_attributes", "cs_train_sequential",
+                 "cs_split_gaussians", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
                  "cs_pose_grid_search", "cs_pose_refine"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("cs_cnn_create", "cs_cnn_get_params", "cs_cnn_set_params", "cs_cnn_forward",
@@ -383,6 +385,32 @@ class Library:
                                                      torch.cuda.current_stream(dev).cuda_stream),
                     "cs_init_attributes")
         return out
+
+    def split_gaussians(self, params, adam_m=None, adam_v=None, scale_act="softplus",
+                        amp_act="softplus"):
+        """Densify: flat parameters [11 N] -> [22 N] (and the Adam moments when
+        given), cs_split_gaussians.  Returns (params, m, v)."""
+        dev = params.device
+        np_ = params.numel()
+        if np_ % 11:
+            raise ValueError("params must hold 11 values per Gaussian")
+        n = np_ // 11
+        _ptr(params, "params", dev, (np_,))
+        mom = adam_m is not None or adam_v is not None
+        out = torch.empty(2 * np_, device=dev, dtype=torch.float32)
+        om = ov = None
+        if mom:
+            _ptr(adam_m, "adam_m", dev, (np_,))
+            _ptr(adam_v, "adam_v", dev, (np_,))
+            om, ov = torch.empty_like(out), torch.empty_like(out)
+        ctx = self.ctx(dev)
+        rc = self.lib.cs_split_gaussians(
+            ctx, params.data_ptr(), adam_m.data_ptr() if mom else None,
+            adam_v.data_ptr() if mom else None, n, _SCALE_ACT[scale_act], _AMP_ACT[amp_act],
+            out.data_ptr(), om.data_ptr() if mom else None, ov.data_ptr() if mom else None,
+            torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_split_gaussians")
+        return out, om, ov
 
     def train_sequential(self, params, adam_m, adam_v, images, rot, pixel, order, step0, lr,
                          ctf=None, options=None, reduction="sum", b1=0.9, b2=0.999, eps=1e-8,

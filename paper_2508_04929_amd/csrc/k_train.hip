@@ -45,6 +45,76 @@ k_train_gather(const float *images, const float *rot, TrainCtfSrc src, int64_t i
   }
 }
 
+// SplitGaussian (Alg. 1 densification), moment-preserving: the largest axis k
+// (compared on the stored pre-activations, lowest index among equals), its
+// scale s_k and direction u = R(q) e_k; children at mu +- (s_k / 2) u with
+// s_k' = s_k sqrt(3) / 2 and amplitude A / 2 (other scales and the
+// quaternion kept), so each pair keeps its parent's mass, mean and
+// covariance.  Output index i (+ side) and N + i (- side); the Adam
+// moments (if given) are copied to both children.  FP64 arithmetic.
+__device__ __forceinline__ double softplus_d(double x) { return x > 30.0 ? x : log1p(exp(x)); }
+
+__global__ void __launch_bounds__(256)
+k_split_gaussians(const float *p, const float *m, const float *v, int64_t n, int scale_act,
+                  int amp_act, float *q, float *qm, float *qv) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int64_t n2 = 2 * n;
+  const float *mu = p + 3 * i, *ls = p + 3 * n + 3 * i, *qt = p + 6 * n + 4 * i;
+  const float a = p[10 * n + i];
+  int k = 0;
+  float lk = ls[0];
+  if (ls[1] > lk) { k = 1; lk = ls[1]; }
+  if (ls[2] > lk) { k = 2; lk = ls[2]; }
+  const double sk = scale_act ? softplus_d((double)lk) : exp((double)lk);
+  double w = qt[0], x = qt[1], y = qt[2], z = qt[3];
+  const double nq = fmax(sqrt(w * w + x * x + y * y + z * z), 1e-12);
+  w /= nq; x /= nq; y /= nq; z /= nq;
+  double u0, u1, u2;  // column k of R(q)
+  if (k == 0) {
+    u0 = w * w + x * x - y * y - z * z; u1 = 2.0 * (x * y + w * z); u2 = 2.0 * (x * z - w * y);
+  } else if (k == 1) {
+    u0 = 2.0 * (x * y - w * z); u1 = w * w - x * x + y * y - z * z; u2 = 2.0 * (y * z + w * x);
+  } else {
+    u0 = 2.0 * (x * z + w * y); u1 = 2.0 * (y * z - w * x); u2 = w * w - x * x - y * y + z * z;
+  }
+  const double h = 0.5 * sk;
+  const double d[3] = {h * u0, h * u1, h * u2};
+  const double shrunk = 0.86602540378443865 * sk;  // sqrt(3) / 2
+  const float lk_new = (float)(scale_act ? log(expm1(shrunk)) : log(shrunk));
+  const double A = amp_act ? softplus_d((double)a) : (double)a;
+  const float a_new = (float)(amp_act ? log(expm1(0.5 * A)) : 0.5 * A);
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int64_t j = i + side * n;
+    const double sg = side ? -1.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      q[3 * j + c] = (float)((double)mu[c] + sg * d[c]);
+      q[3 * n2 + 3 * j + c] = c == k ? lk_new : ls[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q[6 * n2 + 4 * j + c] = qt[c];
+    q[10 * n2 + j] = a_new;
+    if (qm) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        qm[3 * j + c] = m[3 * i + c];
+        qv[3 * j + c] = v[3 * i + c];
+        qm[3 * n2 + 3 * j + c] = m[3 * n + 3 * i + c];
+        qv[3 * n2 + 3 * j + c] = v[3 * n + 3 * i + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        qm[6 * n2 + 4 * j + c] = m[6 * n + 4 * i + c];
+        qv[6 * n2 + 4 * j + c] = v[6 * n + 4 * i + c];
+      }
+      qm[10 * n2 + j] = m[10 * n + i];
+      qv[10 * n2 + j] = v[10 * n + i];
+    }
+  }
+}
+
 __global__ void k_train_record(const float *src, float *dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
 }

@@ -144,4 +144,33 @@ int cs_train_sequential(cs_ctx *ctx, float *params, float *adam_m, float *adam_v
   return CS_OK;
 }
 
+int cs_split_gaussians(cs_ctx *ctx, const float *params, const float *adam_m, const float *adam_v,
+                       int64_t n, int32_t scale_act, int32_t amp_act, float *out_params,
+                       float *out_m, float *out_v, void *stream) {
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  if (!params || !out_params) return fail(ctx, CS_ERR_INVALID_ARG, "null parameters");
+  if (n < 1) return fail(ctx, CS_ERR_INVALID_ARG, "N must be >= 1");
+  if (n > ((int64_t)1 << 40)) return fail(ctx, CS_ERR_UNSUPPORTED, "N too large");
+  const bool mom = adam_m || adam_v || out_m || out_v;
+  if (mom && !(adam_m && adam_v && out_m && out_v))
+    return fail(ctx, CS_ERR_INVALID_ARG, "Adam moments: give all four arrays or none");
+  if (scale_act != 0 && scale_act != 1) return fail(ctx, CS_ERR_INVALID_ARG, "bad scale_act");
+  if (amp_act != 0 && amp_act != 1) return fail(ctx, CS_ERR_INVALID_ARG, "bad amp_act");
+  const size_t in_b = (size_t)11 * n * 4, out_b = 2 * in_b;
+  auto overlap = [](const void *a, size_t na, const void *b, size_t nb) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return a && b && x < y + nb && y < x + na;
+  };
+  if (overlap(params, in_b, out_params, out_b) ||
+      (mom && (overlap(adam_m, in_b, out_m, out_b) || overlap(adam_v, in_b, out_v, out_b) ||
+               overlap(out_params, out_b, out_m, out_b) || overlap(out_params, out_b, out_v, out_b) ||
+               overlap(out_m, out_b, out_v, out_b))))
+    return fail(ctx, CS_ERR_INVALID_ARG, "outputs must not overlap the inputs or each other");
+  HIPCHK(hipSetDevice(ctx->device));
+  TLAUNCH(k_split_gaussians, dim3(cdivt(n, 256)), dim3(256), 0, (hipStream_t)stream, params,
+          adam_m, adam_v, n, scale_act, amp_act, out_params, mom ? out_m : nullptr,
+          mom ? out_v : nullptr);
+  return CS_OK;
+}
+
 }  // extern "C"

@@ -78,10 +78,18 @@ class Trainer:
         self.step += len(order)
         return loss
 
+    def densify(self):
+        """SplitGaussian for every Gaussian (Alg. 1): the count doubles; the
+        children inherit their parent's Adam moments."""
+        self.params, self.m, self.v = self.lib.split_gaussians(self.params, self.m, self.v)
+        self.n *= 2
+
     def fit(self, data: Dataset, epochs: int = 5, lr: float = 1e-3, gamma: float = 0.1,
-            seed: int = 0, record_loss: bool = False, on_epoch=None):
+            seed: int = 0, record_loss: bool = False, on_epoch=None, densify_after=()):
         """Alg. 1's outer loop: per epoch e a fresh random order of the set
-        and learning rate lr gamma^e.  Returns the per-step losses when asked."""
+        and learning rate lr gamma^e; after every epoch listed in
+        ``densify_after`` (IsDoubleGaussians) all Gaussians are split.
+        Returns the per-step losses when asked."""
         data = self.centre(self.lib, data)
         rng = np.random.default_rng(seed)
         losses = []
@@ -91,6 +99,8 @@ class Trainer:
             self.epoch(data, order, lr * gamma ** e, loss)
             if record_loss:
                 losses.append(loss)
+            if e in densify_after:
+                self.densify()
             if on_epoch is not None:
                 on_epoch(e, self)
         return torch.cat(losses) if record_loss else None

@@ -1,0 +1,107 @@
+"""Densification (SplitGaussian of Alg. 1) on the GPU against the FP64
+oracle: children within FP32 rounding of the oracle's (both activation
+choices, isotropic ties included), the Adam moments copied bit for bit,
+each pair's mass, mean and covariance equal to its parent's, argument
+checks through the C-ABI, and training continuing across a split."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import densify as o_den, model
+from paper_2508_04929_amd import binding, inputs, trainer
+
+from gpu_util import announce, ctf_arg, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _flat(g):
+    return np.concatenate([np.asarray(a, dtype=np.float32).ravel()
+                           for a in (g.means, g.log_scales, g.quats, g.amps)])
+
+
+@pytest.mark.parametrize("scale_act,amp_act", [("exp", "identity"), ("softplus", "softplus")])
+def test_split_matches_oracle(gpu_lib, scale_act, amp_act):
+    rng = np.random.default_rng(90)
+    n = 5000
+    g = inputs.mixture_anisotropic(rng, n, 30.0)
+    if scale_act == "softplus":
+        g.log_scales = np.log(np.expm1(rng.uniform(0.3, 4.0, size=(n, 3)))).astype(np.float32)
+        g.amps = np.log(np.expm1(rng.uniform(0.05, 2.0, size=n))).astype(np.float32)
+    g.log_scales[:50] = g.log_scales[:50, :1]          # isotropic rows: ties
+    g.log_scales[50:100, 2] = g.log_scales[50:100, 1]  # a tie between the last two axes
+    theta = _flat(g)
+    m = rng.standard_normal(11 * n).astype(np.float32)
+    v = rng.random(11 * n).astype(np.float32)
+    announce(f"split 5000 Gaussians ({scale_act}, {amp_act})")
+    out, om, ov = gpu_lib.split_gaussians(dev(theta), dev(m), dev(v), scale_act, amp_act)
+    ref = o_den.split_flat(theta, n, scale_act, amp_act)
+    got = host(out)
+    n2 = 2 * n
+    sl = {"means": slice(0, 3 * n2), "log_scales": slice(3 * n2, 6 * n2),
+          "quats": slice(6 * n2, 10 * n2), "amps": slice(10 * n2, 11 * n2)}
+    for name, s in sl.items():
+        err = np.abs(got[s] - ref[s])
+        tol = 3e-7 * np.maximum(np.abs(ref[s]), np.abs(ref[s]).max() if name == "means" else 0.0) + 1e-30
+        assert np.all(err <= tol), name
+    np.testing.assert_array_equal(host(om), o_den.duplicate_moments(m, n))
+    np.testing.assert_array_equal(host(ov), o_den.duplicate_moments(v, n))
+
+
+def test_children_keep_their_parents_moments(gpu_lib):
+    rng = np.random.default_rng(91)
+    n = 2000
+    g = inputs.mixture_anisotropic(rng, n, 20.0)
+    out, _, _ = gpu_lib.split_gaussians(dev(_flat(g)), scale_act="exp", amp_act="identity")
+    o = host(out)
+    n2 = 2 * n
+    mu, ls, q, a = (o[:3 * n2].reshape(n2, 3), o[3 * n2:6 * n2].reshape(n2, 3),
+                    o[6 * n2:10 * n2].reshape(n2, 4), o[10 * n2:])
+    S = model.covariance(ls, q)
+    d = 0.5 * (mu[:n] - mu[n:])
+    np.testing.assert_allclose(a[:n] + a[n:], g.amps, rtol=1e-6)
+    np.testing.assert_allclose(0.5 * (mu[:n] + mu[n:]), g.means, atol=1e-5)
+    S0 = model.covariance(np.asarray(g.log_scales, np.float64), g.quats)
+    err = np.abs(S[:n] + np.einsum("ni,nj->nij", d, d) - S0).max(axis=(1, 2))
+    assert np.all(err <= 1e-5 * np.abs(S0).max(axis=(1, 2)))
+
+
+def test_split_rejects_overlap_and_partial_moments(gpu_lib):
+    L = gpu_lib.lib
+    ctx = gpu_lib.ctx(torch.device("cuda", 0))
+    p = torch.zeros(11 * 8 * 3, device="cuda")
+    base = p.data_ptr()
+    # output overlapping the input
+    assert L.cs_split_gaussians(ctx, base, None, None, 8, 1, 1, base + 4 * 44, None, None,
+                                None) == -1
+    # moments given in part
+    q = torch.zeros(11 * 8 * 2, device="cuda")
+    assert L.cs_split_gaussians(ctx, base, base, None, 8, 1, 1, q.data_ptr(), None, None,
+                                None) == -1
+
+
+def test_training_continues_across_a_split(gpu_lib):
+    """1,000 Gaussians, 3 epochs over 800 noiseless particles with a split
+    after the first: the count doubles, the losses stay finite and the last
+    epoch's mean loss is below the first's."""
+    lib = gpu_lib
+    rng = np.random.default_rng(92)
+    D, p_a, M = 48, 3.0, 800
+    L = D * p_a
+    gt = inputs.mixture_domains(rng, 800, radius=0.2 * L, scale_mu=np.log(3.0))
+    amps = np.asarray(gt.amps, np.float64)
+    g = [dev(np.asarray(gt.means, np.float64) / L), dev(np.asarray(gt.log_scales, np.float64) - np.log(L)),
+         dev(gt.quats), dev(0.5 * amps / amps.sum())]
+    v = inputs.views(rng, M, D, 1.0 / D)
+    v.pixel_a = p_a
+    rot, ctf = dev(v.rot), ctf_arg(v)
+    images = lib.render(*g, rot, None, D, 1.0 / D, ctf=ctf)
+    tr = trainer.Trainer(lib, dev(rng.standard_normal((1000, 3))))
+    announce("training 3 epochs with a split after the first (N 1000 -> 2000)")
+    losses = host(tr.fit(trainer.Dataset(images=images, rot=rot, ctf=ctf), epochs=3, gamma=0.5,
+                         seed=3, record_loss=True, densify_after=(0,)))
+    assert tr.n == 2000 and tr.params.numel() == 22000
+    assert np.all(np.isfinite(losses))
+    assert losses[-M:].mean() < losses[:M].mean()

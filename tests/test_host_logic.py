@@ -53,3 +53,4 @@ def test_null_context_arguments_are_rejected(lib):
     assert L.cs_init_attributes(None, None, 1, None, None) == -1
     assert L.cs_train_sequential(None, None, None, None, 1, 1, 1, None, None, None, 0, None, 0, 0,
                                  1e-3, 0.9, 0.999, 1e-8, None, None) == -1
+    assert L.cs_split_gaussians(None, None, None, None, 1, 1, 1, None, None, None, None) == -1
