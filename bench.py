@@ -369,6 +369,38 @@ def run_trainer(steps: int = 1024, sizes=((256, 2048), (256, 10000), (256, 30000
             "sizes": out}
 
 
+def run_densify(n: int = 200000, reps: int = 20):
+    """SplitGaussian of every Gaussian with the Adam moments (Alg. 1
+    densification): N = 200,000 -> 400,000.  Algorithmic bytes: read the
+    parameters and both moments (3 x 11 N floats), write them for 2N."""
+    import numpy as np
+    import torch
+
+    from paper_2508_04929_amd import binding
+
+    lib = binding.library()
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    p = torch.randn(11 * n, device="cuda", generator=gen)
+    m = torch.randn(11 * n, device="cuda", generator=gen)
+    v = torch.rand(11 * n, device="cuda", generator=gen)
+    lib.split_gaussians(p, m, v)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lib.split_gaussians(p, m, v)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    nbytes = 3 * 11 * n * 4 * 3
+    return {"workload": f"split N={n} Gaussians (parameters and Adam moments) into {2 * n}",
+            "ms": ms, "bytes": nbytes, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 8e12,
+            "note": "median over calls; includes the library call's output allocation in torch"}
+
+
 def run_batched(reps: int = 10, autotune: bool = True):
     """Uneven batching: 8 mixtures (N = 5k ... 150k) x 128 images, D in
     {128, 192, 256}, fwd + adjoint of all problems in one persistent launch
@@ -467,6 +499,7 @@ def main():
     res["cpu_baseline"] = cpu
     if args.trainer:
         res["trainer"] = run_trainer()
+        res["densify"] = run_densify()
     if args.volume:
         res["volume"] = run_volume()
         print(f"[bench] volume: voxelise {res['volume']['voxelize_ms']:.2f} ms, "

@@ -391,7 +391,12 @@ int launch_persistent(cs_ctx *ctx, bool forward, const std::vector<const Plan *>
 int launch_forward_finish(cs_ctx *ctx, const Plan &P, float *Q, hipStream_t st) {
   const Geom &G = P.G;
   char *ws = P.ws;
-  TLAUNCH(k_canvas_reduce, dim3(G.ntiles, G.B), dim3(kBlock), 0, st,
+  // split each tile's pixels over up to 4 blocks when there are few tiles
+  // (one image): the per-pixel sums are unchanged
+  const int per_tile = (G.T * G.T / 4 + kBlock - 1) / kBlock;
+  const int zsplit = std::max(1, std::min(per_tile, (int)((512 + (int64_t)G.ntiles * G.B - 1) /
+                                                          ((int64_t)G.ntiles * G.B))));
+  TLAUNCH(k_canvas_reduce, dim3(G.ntiles, G.B, zsplit), dim3(kBlock), 0, st,
           (const float *)(ws + P.L.partials), (const int *)(ws + P.L.item_off),
           (const int4 *)(ws + P.L.items), G, Q);
   TLAUNCH(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),

@@ -164,7 +164,7 @@ k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, G
   const int px_per = vec ? 4 : 1;
   const int wq = wdt / px_per;
   const int nq = (r_hi - r_lo) * wq;
-  for (int q = threadIdx.x; q < nq; q += kBlock) {
+  for (int q = threadIdx.x + blockIdx.z * kBlock; q < nq; q += kBlock * gridDim.z) {
     const int i = r_lo + q / wq, j = c_lo + px_per * (q % wq);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int dy = -1; dy <= 1; ++dy) {

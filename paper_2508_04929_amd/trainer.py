@@ -4,9 +4,11 @@ size 1 with one learning rate, exponential decay per epoch.
 
 Host logic only (epoch loop, per-epoch orders, the decay schedule); every
 arithmetic step runs in libcryosplat: ``cs_init_attributes``,
-``cs_fourier_shift``, ``cs_train_sequential`` (which stages each image and
-replays the loss path as a HIP graph), ``cs_voxelize`` / ``cs_fsc`` for the
-read-out.
+``cs_fourier_shift``, ``cs_train_sequential`` (which stages each image, so
+that the loss path can also be replayed as a HIP graph), ``cs_split_gaussians``
+for densification, ``cs_voxelize`` / ``cs_fsc`` for the read-out.  Eager
+launches are the default: a step's GPU work outlasts its host-side launches,
+so a graph replay only adds its own fixed cost.
 """
 from __future__ import annotations
 
@@ -45,7 +47,7 @@ class Trainer:
     """Flat parameters [11 N] (means | log_scales | quats | amps, softplus
     activations) and Adam moments on one device."""
 
-    def __init__(self, lib: binding.Library, z: torch.Tensor, graph: bool = True,
+    def __init__(self, lib: binding.Library, z: torch.Tensor, graph: bool = False,
                  options: Optional[binding.Options] = None):
         self.lib = lib
         self.n = int(z.shape[0])
