@@ -197,9 +197,9 @@ def literal_grid_search(lib, gd, image, ctf_one: binding.Ctf, grid_rot: torch.Te
     return best
 
 
-def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, gamma=0.85,
+def run_c5(lib, *, n_train=200000, n_test=8192, epochs=12, batch=256, lr=1e-3, gamma=0.85,
            lam=0.1, snr_db=-20.0, seed=5, coarse=(4, 24), fine=(8, 48), shift_radius=2,
-           stages=((0, 6, 2), (1, 4, 2)), matched_filter=True, chunk=2048,
+           stages=((0, 6, 2), (1, 4, 2)), matched_filter=True, chunks=(2048, 4096, 8192),
            literal_particles=2, stage_sweep=(), use_graphs=True, log=print):
     """The learned-pose experiment: returns angular errors and throughputs.
 
@@ -209,7 +209,10 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
     both timed paths are replayed HIP graphs (the eager times are reported
     too).
     Both paths are timed from particle images in device memory to poses,
-    particle preparation (CTF filtering, shifted copies) included."""
+    particle preparation (CTF filtering, shifted copies) included, in
+    batches of each size in ``chunks``; each path's throughput is the one
+    at its fastest batch size (the grid search slows with larger batches,
+    the learned path speeds up), and every batch size gives the same poses."""
     dev = torch.device("cuda")
     g, tr, te = inputs.c5(seed, n_train, n_test)
     gd = mixture_on_device(g)
@@ -226,36 +229,52 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
     res["bank_build_s"] = time.perf_counter() - t0
     res["bank_sizes"] = [int(r.shape[0]) for r in rots]
     imgs = render_particles(lib, gd, ps_te, 0, n_test, snr_db, seed + 1000)
-    chunk = min(chunk, n_test)
-    pb = lib.pose_batch(D, pixel, chunk, shift_radius)
-    xbuf = torch.empty(chunk, D, D, device=dev, dtype=torch.bfloat16)
+    chunks = sorted({min(c, n_test) for c in chunks})
+    chunk = chunks[0]
+    pbs = {c: lib.pose_batch(D, pixel, c, shift_radius) for c in chunks}
+    xbuf = torch.empty(max(chunks), D, D, device=dev, dtype=torch.bfloat16)
 
-    def grid_all():
-        return torch.cat([grid_poses(pb, banks[0], imgs[a:min(n_test, a + chunk)],
-                                     ps_te.ctf(a, min(n_test, a + chunk)))[0]
-                          for a in range(0, n_test, chunk)])
+    def grid_all(c=chunk):
+        return torch.cat([grid_poses(pbs[c], banks[0], imgs[a:min(n_test, a + c)],
+                                     ps_te.ctf(a, min(n_test, a + c)))[0]
+                          for a in range(0, n_test, c)])
 
-    W_gs, t_gs_eager = timed(grid_all)
-    t_gs = t_gs_eager
-    if use_graphs:
-        g_grid = Graphed(grid_all)
-        W_gs2, t_gs = timed(g_grid)
-        if not torch.equal(W_gs2, W_gs):
-            raise RuntimeError("graph replay of the grid search differs from the eager run")
+    def per_chunk(make, ref, same):
+        """{chunk: (seconds, eager seconds)}; every batch size must give `ref`."""
+        out = {}
+        for c in chunks:
+            fn = make(c)
+            r, te_ = timed(fn)
+            tg = te_
+            if use_graphs:
+                r2, tg = timed(Graphed(fn))
+                if not same(r2, r):
+                    raise RuntimeError("graph replay differs from the eager run")
+            if not same(r, ref):
+                raise RuntimeError(f"batches of {c} give other poses than batches of {chunk}")
+            out[c] = (tg, te_)
+        return out
+
+    W_gs = grid_all()
+    t_by = per_chunk(lambda c: (lambda: grid_all(c)), W_gs, torch.equal)
+    c_gs = min(t_by, key=lambda c: t_by[c][0])
+    t_gs, t_gs_eager = t_by[c_gs]
     err_gs = angular_error_deg(W_gs, ps_te.rot)
     res["grid_search"] = {"median_deg": float(np.median(err_gs)), "mean_deg": float(err_gs.mean()),
-                          "images_per_s": n_test / t_gs, "seconds": t_gs,
-                          "images_per_s_eager": n_test / t_gs_eager}
-    log(f"grid search: median {np.median(err_gs):.2f} deg, {n_test / t_gs:.0f} img/s")
+                          "images_per_s": n_test / t_gs, "seconds": t_gs, "batch": c_gs,
+                          "images_per_s_eager": n_test / t_gs_eager,
+                          "images_per_s_by_batch": {str(c): n_test / v[0] for c, v in t_by.items()}}
+    log(f"grid search: median {np.median(err_gs):.2f} deg, {n_test / t_gs:.0f} img/s "
+        f"(batches of {c_gs})")
     st = [Stage(banks[b], nd, npc) for b, nd, npc in stages]
-    net = lib.network(D, max_batch=max(batch, chunk), seed=seed)
+    net = lib.network(D, max_batch=max(batch, max(chunks)), seed=seed)
 
-    def learned(st=st):
+    def learned(st=st, c=chunk):
         Ws, W0s = [], []
-        for a in range(0, n_test, chunk):
-            b = min(n_test, a + chunk)
-            W, _, W0 = learned_poses(lib, net, pb, imgs[a:b], ps_te.ctf(a, b), st, xbuf[:b - a],
-                                     matched_filter)
+        for a in range(0, n_test, c):
+            b = min(n_test, a + c)
+            W, _, W0 = learned_poses(lib, net, pbs[c], imgs[a:b], ps_te.ctf(a, b), st,
+                                     xbuf[:b - a], matched_filter)
             Ws.append(W)
             W0s.append(W0)
         return torch.cat(Ws), torch.cat(W0s)
@@ -276,28 +295,30 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
                        "seconds": t_train, "images_per_s": epochs * n_train / t_train,
                        "loss_first": hist[0][1] if hist else None,
                        "loss_last": hist[-1][1] if hist else None}
-    (W_t, W0_t), t_l_eager = timed(learned)
-    t_l = t_l_eager
-    if use_graphs:
-        g_learned = Graphed(learned)
-        (W_t2, W0_t2), t_l = timed(g_learned)
-        if not (torch.equal(W_t2, W_t) and torch.equal(W0_t2, W0_t)):
-            raise RuntimeError("graph replay of the learned path differs from the eager run")
+    W_t, W0_t = learned()
+    same2 = lambda a, b: torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    t_by = per_chunk(lambda c: (lambda: learned(st, c)), (W_t, W0_t), same2)
+    c_l = min(t_by, key=lambda c: t_by[c][0])
+    t_l, t_l_eager = t_by[c_l]
     err_t = angular_error_deg(W_t, ps_te.rot)
     err_pt = angular_error_deg(W0_t, ps_te.rot)
     res["learned"] = {"median_deg": float(np.median(err_t)), "mean_deg": float(err_t.mean()),
                       "proposal_median_deg": float(np.median(err_pt)),
-                      "images_per_s": n_test / t_l, "seconds": t_l,
+                      "images_per_s": n_test / t_l, "seconds": t_l, "batch": c_l,
                       "images_per_s_eager": n_test / t_l_eager,
+                      "images_per_s_by_batch": {str(c): n_test / v[0] for c, v in t_by.items()},
                       "stages": [list(s) for s in stages]}
+    res["speedup_same_batch"] = {str(c): res["learned"]["images_per_s_by_batch"][str(c)]
+                                 / res["grid_search"]["images_per_s_by_batch"][str(c)]
+                                 for c in chunks}
     log(f"learned: proposal {np.median(err_pt):.1f} deg, refined {np.median(err_t):.2f} deg, "
-        f"{n_test / t_l:.0f} img/s")
+        f"{n_test / t_l:.0f} img/s (batches of {c_l})")
     res["speedup_vs_grid_search"] = t_gs / t_l
     res["reaches_grid_search_error"] = bool(np.median(err_t) <= np.median(err_gs))
     sweep = []
     for stv in stage_sweep:
         sv = [Stage(banks[b], nd, npc) for b, nd, npc in stv]
-        fn_v = (lambda: learned(sv))
+        fn_v = (lambda: learned(sv, c_l))
         (W_v, _), t_v = timed(Graphed(fn_v) if use_graphs else fn_v)
         e_v = angular_error_deg(W_v, ps_te.rot)
         sweep.append({"stages": [list(x) for x in stv], "median_deg": float(np.median(e_v)),
@@ -317,6 +338,7 @@ def run_c5(lib, *, n_train=200000, n_test=2048, epochs=12, batch=256, lr=1e-3, g
         res["speedup_vs_literal_grid_search"] = (n_test / t_l) * t_lit
     for b in banks:
         b.close()
-    pb.close()
+    for pb in pbs.values():
+        pb.close()
     net.close()
     return res
