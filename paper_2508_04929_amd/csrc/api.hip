@@ -178,9 +178,11 @@ int ensure_ws(cs_ctx *ctx, size_t need, hipStream_t stream) {
 namespace cs {
 
 int fft_cols_per_block(int D, int64_t B) {
-  int c = D > 256 ? 8 : 16;
-  // fewer columns per block (each column's transform is unchanged) until the
-  // column pass has a few hundred blocks: small batches would idle the chip
+  // four columns per block (18 KB of LDS at D = 256: eight blocks per CU
+  // hide the latency of the strided column loads), two when a small batch
+  // would leave the pass with fewer than a few hundred blocks; each column's
+  // transform is the same whatever the blocking
+  int c = 4;
   while (c > 2 && (int64_t)((D / 2 + c) / c) * B < 512) c >>= 1;
   return c;
 }

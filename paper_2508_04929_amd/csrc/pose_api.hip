@@ -232,9 +232,9 @@ int cs_pose_bank_create(cs_ctx *ctx, const cs_gaussians *g, const float *rot, in
   const float2 *tw = nullptr;
   rc = get_twiddles(ctx, D, &tw);
   if (rc) return bail(rc);
-  const int cpw = D > 256 ? 8 : 16;
   for (int64_t k0 = 0; k0 < K; k0 += chunk) {
     const int kc = (int)std::min<int64_t>(chunk, K - k0);
+    const int cpw = fft_cols_per_block(D, kc);
     cs_views v{};
     v.rot = rot + 9 * k0;
     v.shift = nullptr;

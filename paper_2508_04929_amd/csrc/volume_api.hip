@@ -120,7 +120,7 @@ int cs_fsc(cs_ctx *ctx, const float *vol_a, const float *vol_b, int32_t D, float
   TLAUNCH(k_fsc_energy_scale, dim3(1), dim3(kEnergyBlocks), 0, st, (const double *)part, D, scale);
   const dim3 rgrid(cdivv(D / 2, kRowTeamsVol), D);
   const size_t rlds = (size_t)(kRowTeamsVol * 2 + 1) * D * 8;
-  const int cpw = D > 256 ? 8 : 16;
+  const int cpw = fft_cols_per_block(D, D);
   const size_t alds = (size_t)(cpw * 2 + 1) * D * 8;
   for (int v = 0; v < 2; ++v) {
     const float *src = v ? vol_b : vol_a;
