@@ -433,7 +433,7 @@ int launch_backward_finish(cs_ctx *ctx, const Plan &P, hipStream_t st) {
 struct FftLaunch {
   FftPlan P;
   const float2 *tw = nullptr;
-  dim3 rgrid, cgrid;
+  dim3 rgrid, cgrid, rblock;
   size_t rlds = 0, clds = 0;
   int cpw = 16;
 };
@@ -444,6 +444,12 @@ int fft_setup(cs_ctx *ctx, const Geom &G, FftLaunch &F) {
   if (rc) return rc;
   F.rgrid = dim3(cdiv(G.D / 2, 4), G.B);
   F.rlds = (size_t)(4 * 2 + 1) * G.D * 8;  // four row pairs (ping-pong) + twiddles
+  F.rblock = dim3(256);
+  if ((int64_t)F.rgrid.x * G.B < 512) {    // small batches: one row pair per block
+    F.rgrid = dim3(G.D / 2, G.B);
+    F.rlds = (size_t)(1 * 2 + 1) * G.D * 8;
+    F.rblock = dim3(64);
+  }
   F.cpw = fft_cols_per_block(G.D, G.B);
   F.cgrid = dim3(cdiv(G.D / 2 + 1, F.cpw), G.B);
   F.clds = (size_t)(F.cpw * 2 + 1) * G.D * 8;
@@ -466,10 +472,10 @@ int launch_ctf_roundtrip(cs_ctx *ctx, const Plan &P, const float *src, float *ds
   int rc = fft_setup(ctx, G, F);
   if (rc) return rc;
   float2 *spec = (float2 *)(P.ws + P.L.spec);
-  TLAUNCH(k_fft_rows_fwd, F.rgrid, dim3(256), F.rlds, st, src, F.P, F.tw, G.B, spec);
+  TLAUNCH(k_fft_rows_fwd, F.rgrid, F.rblock, F.rlds, st, src, F.P, F.tw, G.B, spec);
   TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw,
           (const float *)(P.ws + P.L.ctf));
-  TLAUNCH(k_fft_rows_inv, F.rgrid, dim3(256), F.rlds, st, (const float2 *)spec, F.P, F.tw, G.B, dst);
+  TLAUNCH(k_fft_rows_inv, F.rgrid, F.rblock, F.rlds, st, (const float2 *)spec, F.P, F.tw, G.B, dst);
   return CS_OK;
 }
 
@@ -487,14 +493,14 @@ int launch_loss(cs_ctx *ctx, const Plan &P, hipStream_t st) {
     if (rc) return rc;
     float2 *spec = (float2 *)(P.ws + P.L.spec);
     const float *table = (const float *)(P.ws + P.L.ctf);
-    TLAUNCH(k_fft_rows_fwd, F.rgrid, dim3(256), F.rlds, st, Q, F.P, F.tw, G.B, spec);
+    TLAUNCH(k_fft_rows_fwd, F.rgrid, F.rblock, F.rlds, st, Q, F.P, F.tw, G.B, spec);
     TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw, table);
-    TLAUNCH(k_fft_rows_inv_loss, F.rgrid, dim3(256), F.rlds, st, spec, F.P, F.tw, G.B, P.observed,
+    TLAUNCH(k_fft_rows_inv_loss, F.rgrid, F.rblock, F.rlds, st, spec, F.P, F.tw, G.B, P.observed,
             P.images_out, gscale, loss_part);
     parts = G.D / 2;
     if (P.bwd) {
       TLAUNCH(k_fft_cols_ctf, F.cgrid, dim3(256), F.clds, st, spec, F.P, F.tw, G.B, F.cpw, table);
-      TLAUNCH(k_fft_rows_inv, F.rgrid, dim3(256), F.rlds, st, (const float2 *)spec, F.P, F.tw, G.B, Q);
+      TLAUNCH(k_fft_rows_inv, F.rgrid, F.rblock, F.rlds, st, (const float2 *)spec, F.P, F.tw, G.B, Q);
     }
   } else {
     TLAUNCH(k_residual, dim3(G.D, G.B), dim3(256), 0, st, Q, P.observed, P.images_out, G.B, G.D,

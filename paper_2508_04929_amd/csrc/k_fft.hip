@@ -85,8 +85,9 @@ __device__ float2 *fft_team(float2 *x, float2 *y, const FftPlan &P, const float2
   return x;
 }
 
-// Rows per block in the row kernels: 4 teams of 64 threads, one row pair each.
-constexpr int kRowTeams = 4;
+// Row kernels: one team of 64 threads per row pair, blockDim.x / 64 teams
+// per block (the host picks fewer for small batches; each pair's transform
+// is the same either way).
 
 // ---------------------------------------------------------------------------
 // Forward row pass: spec[b][r][0..D/2] = rFFT(src[b][r][:]) for every row.
@@ -109,13 +110,13 @@ __global__ void __launch_bounds__(256)
 k_fft_rows_fwd(const float *src, FftPlan P, const float2 *tw, int B, float2 *spec) {
   extern __shared__ float2 lds[];
   const int L = P.L, Dh = L / 2 + 1;
-  const int team = threadIdx.x >> 6, t = threadIdx.x & 63;
-  const int pr = blockIdx.x * kRowTeams + team;  // row pair
+  const int teams = blockDim.x >> 6, team = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int pr = blockIdx.x * teams + team;  // row pair
   const int b = blockIdx.y;
   const bool valid = pr < L / 2;
   float2 *x = lds + team * 2 * L, *y = x + L;
-  float2 *twl = lds + kRowTeams * 2 * L;
-  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
+  float2 *twl = lds + teams * 2 * L;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) twl[k] = tw[k];
   const float *ra = src + ((size_t)b * L + 2 * pr) * L;
   for (int j = t; j < L; j += 64) x[j] = valid ? make_float2(ra[j], ra[L + j]) : make_float2(0.f, 0.f);
   __syncthreads();
@@ -256,13 +257,13 @@ __global__ void __launch_bounds__(256)
 k_fft_rows_inv(const float2 *spec, FftPlan P, const float2 *tw, int B, float *dst) {
   extern __shared__ float2 lds[];
   const int L = P.L, Dh = L / 2 + 1;
-  const int team = threadIdx.x >> 6, t = threadIdx.x & 63;
-  const int pr = blockIdx.x * kRowTeams + team;
+  const int teams = blockDim.x >> 6, team = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int pr = blockIdx.x * teams + team;
   const int b = blockIdx.y;
   const bool valid = pr < L / 2;
   float2 *x = lds + team * 2 * L, *y = x + L;
-  float2 *twl = lds + kRowTeams * 2 * L;
-  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
+  float2 *twl = lds + teams * 2 * L;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) twl[k] = tw[k];
   const float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
   pack_inverse(sa, sa + Dh, L, t, x, valid);
   __syncthreads();
@@ -287,13 +288,13 @@ k_fft_rows_inv_loss(float2 *spec, FftPlan P, const float2 *tw, int B, const floa
                     float *images_out, float grad_scale, float *loss_part) {
   extern __shared__ float2 lds[];
   const int L = P.L, Dh = L / 2 + 1;
-  const int team = threadIdx.x >> 6, t = threadIdx.x & 63;
-  const int pr = blockIdx.x * kRowTeams + team;
+  const int teams = blockDim.x >> 6, team = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int pr = blockIdx.x * teams + team;
   const int b = blockIdx.y;
   const bool valid = pr < L / 2;
   float2 *x = lds + team * 2 * L, *y = x + L;
-  float2 *twl = lds + kRowTeams * 2 * L;
-  for (int k = threadIdx.x; k < L; k += 256) twl[k] = tw[k];
+  float2 *twl = lds + teams * 2 * L;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) twl[k] = tw[k];
   float2 *sa = spec + ((size_t)b * L + 2 * pr) * Dh;
   pack_inverse(sa, sa + Dh, L, t, x, valid);
   __syncthreads();
