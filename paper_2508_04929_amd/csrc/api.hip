@@ -317,11 +317,14 @@ int launch_binning(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   const size_t hist_bytes = (size_t)kImgPerBinBlock * G.K * 4;
   TLAUNCH(k_bin_count, bgrid, dim3(kBlock), hist_bytes, st, gc, P.v.rot, P.v.shift, G,
           (int *)(ws + L.key), (int *)(ws + L.blk), L.nbx);
-  TLAUNCH(k_bin_blockscan, dim3((unsigned)BK), dim3(kBlock), 0, st, (int *)(ws + L.blk), L.nbx,
-          count);
+  // small problems scan their per-block counts inside k_scan
+  const bool fuse = BK <= 64;
+  if (!fuse)
+    TLAUNCH(k_bin_blockscan, dim3((unsigned)BK), dim3(kBlock), 0, st, (int *)(ws + L.blk), L.nbx,
+            count);
   TLAUNCH(k_scan, dim3(1), dim3(1024), 0, st, count, G, (int *)(ws + L.off),
           (int4 *)(ws + L.items), (int *)(ws + L.item_off), (int *)(ws + L.n_items),
-          (int *)(ws + L.queues));
+          (int *)(ws + L.queues), fuse ? (int *)(ws + L.blk) : (int *)nullptr, L.nbx);
   TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), (size_t)(kBlock / 64) * G.K * 4, st, gc, P.v.rot,
           P.v.shift, G, (const int *)(ws + L.key), (const int *)(ws + L.off),
           (const int *)(ws + L.blk), L.nbx, (float4 *)(ws + L.list));
@@ -509,7 +512,7 @@ int launch_loss(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   }
   TLAUNCH(k_loss_reduce, dim3(G.B), dim3(256), 0, st, (const float *)loss_part, G.B, parts,
           (float)scale, P.loss);
-  TLAUNCH(k_loss_total, dim3(1), dim3(256), 0, st, P.loss, G.B);
+  if (G.B > 1) TLAUNCH(k_loss_total, dim3(1), dim3(256), 0, st, P.loss, G.B);
   return CS_OK;
 }
 

@@ -157,8 +157,8 @@ __global__ void k_bin_count(const float4 *gc, const float *rot, const float *shi
 
 __global__ void k_bin_blockscan(int *blk, int nbx, int *count);
 
-__global__ void k_scan(const int *count, Geom G, int *off, int4 *items, int *item_off,
-                       int *n_items, int *queues);
+__global__ void k_scan(int *count, Geom G, int *off, int4 *items, int *item_off,
+                       int *n_items, int *queues, int *blk, int nbx);
 
 __global__ void k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G,
                               const int *key, const int *off, const int *blk, int nbx,

@@ -336,7 +336,11 @@ k_loss_reduce(const float *loss_part, int B, int parts, float scale, float *loss
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) loss[b] = (float)(scale * (red[0] + red[1] + red[2] + red[3]));
+  if (threadIdx.x == 0) {
+    const float v = (float)(scale * (red[0] + red[1] + red[2] + red[3]));
+    loss[b] = v;
+    if (B == 1) loss[1] = v;  // the total of one image (k_loss_total is skipped)
+  }
 }
 
 __global__ void __launch_bounds__(256) k_loss_total(float *loss, int B) {

@@ -177,10 +177,33 @@ __device__ int block_scan_1024(int val, int *sh, int &total) {
 // owner tile.  Also resets the work-queue counters.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(1024)
-k_scan(const int *count, Geom G, int *off, int4 *items, int *item_off, int *n_items,
-       int *queues) {
+k_scan(int *count, Geom G, int *off, int4 *items, int *item_off, int *n_items,
+       int *queues, int *blk, int nbx) {
   __shared__ int sh[16];
   const int total = G.B * G.K;
+  if (blk) {
+    // few (image, tile) entries: the per-entry scans of k_bin_blockscan, one
+    // wave per entry (the same integers, one launch fewer)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int e = wid; e < total; e += 16) {
+      int *row = blk + (size_t)e * nbx;
+      int carry = 0;
+      for (int base = 0; base < nbx; base += 64) {
+        const int x = base + lane;
+        const int v = x < nbx ? row[x] : 0;
+        int inc = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(inc, o, 64);
+          if (lane >= o) inc += y;
+        }
+        if (x < nbx) row[x] = carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+      }
+      if (lane == 0) count[e] = carry;
+    }
+    __syncthreads();
+  }
   const int seg = (total + 1023) / 1024;
   const int e0 = min(threadIdx.x * seg, total), e1 = min(e0 + seg, total);
   int s = 0, si = 0, sw = 0;
