@@ -223,8 +223,8 @@ def run(args):
             pg[name] = ms / n
     lib.set_timing(dev, False)
     # per launch: six pixel moments and the visibility key per (image, Gaussian),
-    # the Gaussian records, 8 partial sums per (image, block of 256)
-    pg_bytes = B * N * (24 + 4) + N * 48 + B * ((N + 255) // 256) * 32
+    # the Gaussian records, 8 partial sums per (image, block of 1,024 Gaussians)
+    pg_bytes = B * N * (24 + 4) + N * 48 + B * ((N + 1023) // 1024) * 32
     pose_grad = {
         "ms_per_step": ms_pose, "ms_per_step_without": None,
         "ms_per_launch": pg,

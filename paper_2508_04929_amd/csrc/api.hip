@@ -421,7 +421,7 @@ int launch_backward_finish(cs_ctx *ctx, const Plan &P, hipStream_t st) {
           P.g.log_scales, P.g.quats, P.g.amps, P.v.rot, P.v.shift, G, (const int *)(ws + P.L.key),
           mom, P.grads.means, P.grads.log_scales, P.grads.quats, P.grads.amps);
   if (P.grads.rot || P.grads.shift) {
-    const int nblk = cdiv(G.N, kBlock);
+    const int nblk = cdiv(G.N, kBlock * kPoseGauss);
     float *part = (float *)(ws + P.L.pose_part);
     TLAUNCH(k_pose_grad_part, dim3(nblk, cdiv(G.B, kPoseImg)), dim3(kBlock), 0, st,
             (const float4 *)(ws + P.L.gc), P.v.rot, P.v.shift, G, (const int *)(ws + P.L.key), mom,

@@ -182,7 +182,8 @@ __global__ void k_chain(const float4 *gc, const float *log_scales, const float *
                         const int *key, const float *mom, float *g_means, float *g_log_scales,
                         float *g_quats, float *g_amps);
 
-constexpr int kPoseImg = 8;  // images per block of k_pose_grad_part
+constexpr int kPoseImg = 8;    // images per block of k_pose_grad_part
+constexpr int kPoseGauss = 4;  // Gaussians per thread of k_pose_grad_part
 __global__ void k_pose_grad_part(const float4 *gc, const float *rot, const float *shift, Geom G,
                                  const int *key, const float *mom, float *part);
 __global__ void k_pose_grad_sum(const float *part, int B, int nblk, float *g_rot, float *g_shift);

@@ -458,38 +458,49 @@ __global__ void __launch_bounds__(kBlock)
 k_pose_grad_part(const float4 *gc, const float *rot, const float *shift, Geom G, const int *key,
                  const float *mom, float *part) {
   __shared__ float red[kBlock / 64][8];
-  const int n = blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  float4 g0 = make_float4(0, 0, 0, 0), g1 = g0, g2 = g0;
-  if (n < G.N) {
-    g0 = gc[3 * n];
-    g1 = gc[3 * n + 1];
-    g2 = gc[3 * n + 2];
+  const int nbase = blockIdx.x * kBlock * kPoseGauss + threadIdx.x;
+  // kPoseGauss Gaussians per thread (strided by the block size, so every load
+  // stays coalesced), their records read once for kPoseImg images
+  float4 g0[kPoseGauss], g1[kPoseGauss], g2[kPoseGauss];
+#pragma unroll
+  for (int j = 0; j < kPoseGauss; ++j) {
+    const int n = nbase + j * kBlock;
+    g0[j] = g1[j] = g2[j] = make_float4(0, 0, 0, 0);
+    if (n < G.N) {
+      g0[j] = gc[3 * n];
+      g1[j] = gc[3 * n + 1];
+      g2[j] = gc[3 * n + 2];
+    }
   }
-  // kPoseImg images per block: the Gaussian's record is read once
   const int b1 = min(G.B, (int)(blockIdx.y + 1) * kPoseImg);
   for (int b = blockIdx.y * kPoseImg; b < b1; ++b) {
     float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // t_x, t_y, P_0 (3), P_1 (3)
-    if (n < G.N && key[(size_t)b * G.N + n] >= 0) {
-      float p0[3], p1[3], tx, ty;
-      load_pose(rot, shift, b, p0, p1, tx, ty);
-      Proj P;
-      project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
-      const ScreenGrad sg = screen_grad(P, mom + ((size_t)b * G.N + n) * 6, G.pixel);
-      // Sigma p0, Sigma p1 (Sigma symmetric: the rows of P Sigma)
-      const float sp0[3] = {g1.x * p0[0] + g1.y * p0[1] + g1.z * p0[2],
-                            g1.y * p0[0] + g1.w * p0[1] + g2.x * p0[2],
-                            g1.z * p0[0] + g2.x * p0[1] + g2.y * p0[2]};
-      const float sp1[3] = {g1.x * p1[0] + g1.y * p1[1] + g1.z * p1[2],
-                            g1.y * p1[0] + g1.w * p1[1] + g2.x * p1[2],
-                            g1.z * p1[0] + g2.x * p1[1] + g2.y * p1[2]};
-      const float mu[3] = {g0.x, g0.y, g0.z};
-      v[0] = sg.dmx;
-      v[1] = sg.dmy;
+    float p0[3], p1[3], tx, ty;
+    load_pose(rot, shift, b, p0, p1, tx, ty);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        v[2 + k] = sg.dmx * mu[k] + 2.f * (sg.Sxx * sp0[k] + sg.Sxy * sp1[k]);
-        v[5 + k] = sg.dmy * mu[k] + 2.f * (sg.Sxy * sp0[k] + sg.Syy * sp1[k]);
+    for (int j = 0; j < kPoseGauss; ++j) {
+      const int n = nbase + j * kBlock;
+      if (n < G.N && key[(size_t)b * G.N + n] >= 0) {
+        Proj P;
+        project_one(g0[j], g1[j], make_float2(g2[j].x, g2[j].y), p0, p1, tx, ty, G, P);
+        const ScreenGrad sg = screen_grad(P, mom + ((size_t)b * G.N + n) * 6, G.pixel);
+        // Sigma p0, Sigma p1 (Sigma symmetric: the rows of P Sigma)
+        const float4 a = g1[j], c = g2[j];
+        const float sp0[3] = {a.x * p0[0] + a.y * p0[1] + a.z * p0[2],
+                              a.y * p0[0] + a.w * p0[1] + c.x * p0[2],
+                              a.z * p0[0] + c.x * p0[1] + c.y * p0[2]};
+        const float sp1[3] = {a.x * p1[0] + a.y * p1[1] + a.z * p1[2],
+                              a.y * p1[0] + a.w * p1[1] + c.x * p1[2],
+                              a.z * p1[0] + c.x * p1[1] + c.y * p1[2]};
+        const float mu[3] = {g0[j].x, g0[j].y, g0[j].z};
+        v[0] += sg.dmx;
+        v[1] += sg.dmy;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          v[2 + k] += sg.dmx * mu[k] + 2.f * (sg.Sxx * sp0[k] + sg.Sxy * sp1[k]);
+          v[5 + k] += sg.dmy * mu[k] + 2.f * (sg.Sxy * sp0[k] + sg.Syy * sp1[k]);
+        }
       }
     }
 #pragma unroll
