@@ -448,7 +448,9 @@ int cs_pose_batch_refine(cs_pose_bank *bank, cs_pose_batch *batch, const float *
  * q_n = (x - mu_n)^T Sigma_n^-1 (x - mu_n) <= q_cut (q_cut <= 0: the
  * renderer's default 2 ln 1e6); the integral along z is the identity-pose
  * image (Eq. 8) up to the raster's row flip.  D a multiple of 8, at most
- * 512.  Exact fixed-point sums: the result is reproducible bit for bit.
+ * 512.  Every term is truncated to a common fixed-point grid (2^-61 of the
+ * sum of |weights|) and the terms are summed exactly, so the result is the
+ * same bit for bit whatever the order of the Gaussians.
  * Reads the (brick, Gaussian) pair count back from the device, so the call
  * waits for the stream and cannot be captured in a graph. */
 int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, float q_cut,

@@ -30,10 +30,10 @@ __device__ __forceinline__ int clampi(float x, int lo, int hi) {
   return (int)x;
 }
 
-// Per Gaussian: mean and weight, inverse covariance (FP64 adjugate), the
-// brick range of its q <= q_cut box, and the brick counts.
+// Per Gaussian: mean and weight, inverse covariance (FP64 adjugate) and the
+// brick range of its q <= q_cut box.
 __global__ void __launch_bounds__(256)
-k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box, int *count) {
+k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box) {
   const int n = blockIdx.x * 256 + threadIdx.x;
   if (n >= V.N) return;
   const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
@@ -68,9 +68,32 @@ k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box, int *count) {
     return;
   }
   box[n] = make_int4(lo[0] | (hi[0] << 16), lo[1] | (hi[1] << 16), lo[2] | (hi[2] << 16), 1);
-  for (int bz = lo[2]; bz <= hi[2]; ++bz)
-    for (int by = lo[1]; by <= hi[1]; ++by)
-      for (int bx = lo[0]; bx <= hi[0]; ++bx) atomicAdd(&count[(bz * V.nb + by) * V.nb + bx], 1);
+}
+
+// Brick index of entry l of a Gaussian's brick box (x fastest).
+__device__ __forceinline__ int box_brick(int4 b, int l, int nb) {
+  const int x0 = b.x & 0xffff, nx = (b.x >> 16) - x0 + 1;
+  const int y0 = b.y & 0xffff, ny = (b.y >> 16) - y0 + 1;
+  const int z0 = b.z & 0xffff;
+  const int bx = x0 + l % nx, by = y0 + (l / nx) % ny, bz = z0 + l / (nx * ny);
+  return (bz * nb + by) * nb + bx;
+}
+
+__device__ __forceinline__ int box_size(int4 b) {
+  if (!b.w) return 0;
+  return ((b.x >> 16) - (b.x & 0xffff) + 1) * ((b.y >> 16) - (b.y & 0xffff) + 1) *
+         ((b.z >> 16) - (b.z & 0xffff) + 1);
+}
+
+// Brick counts: one wave per Gaussian, its lanes over the bricks of its box
+// (a large box is no longer one thread's serial chain of atomics).
+__global__ void __launch_bounds__(256)
+k_vox_count(const int4 *box, VoxGeom V, int *count) {
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (n >= V.N) return;
+  const int4 b = box[n];
+  const int m = box_size(b);
+  for (int l = lane; l < m; l += 64) atomicAdd(&count[box_brick(b, l, V.nb)], 1);
 }
 
 // Exclusive scan of the brick counts (one block) and the fixed-point scale
@@ -113,20 +136,17 @@ k_vox_scan(const int *count, int nbr, const float4 *rec, int N, int *off, double
   }
 }
 
+// Brick lists, one wave per Gaussian as in k_vox_count.
 __global__ void __launch_bounds__(256)
 k_vox_fill(const int4 *box, VoxGeom V, const int *off, int *cursor, int *list) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (n >= V.N) return;
-  const int4 bx4 = box[n];
-  if (!bx4.w) return;
-  const int x0 = bx4.x & 0xffff, x1 = bx4.x >> 16, y0 = bx4.y & 0xffff, y1 = bx4.y >> 16;
-  const int z0 = bx4.z & 0xffff, z1 = bx4.z >> 16;
-  for (int bz = z0; bz <= z1; ++bz)
-    for (int by = y0; by <= y1; ++by)
-      for (int bx = x0; bx <= x1; ++bx) {
-        const int k = (bz * V.nb + by) * V.nb + bx;
-        list[off[k] + atomicAdd(&cursor[k], 1)] = n;
-      }
+  const int4 b = box[n];
+  const int m = box_size(b);
+  for (int l = lane; l < m; l += 64) {
+    const int k = box_brick(b, l, V.nb);
+    list[off[k] + atomicAdd(&cursor[k], 1)] = n;
+  }
 }
 
 // w 2^k as a 64-bit integer, truncated toward zero, read off the float's

@@ -58,7 +58,8 @@ int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, floa
       TLAUNCH(k_build, dim3(cdivv(N, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
               g->quats, g->amps, G, gc, (int *)nullptr, 0);
       TLAUNCH(k_vox_prep, dim3(cdivv(N, 256)), dim3(256), 0, st, (const float4 *)gc, V, rec,
-              (int4 *)(w + o_box), cnt);
+              (int4 *)(w + o_box));
+      TLAUNCH(k_vox_count, dim3(cdivv(N, 4)), dim3(256), 0, st, (const int4 *)(w + o_box), V, cnt);
     }
     TLAUNCH(k_vox_scan, dim3(1), dim3(1024), 0, st, (const int *)cnt, nbr, (const float4 *)rec, N,
             (int *)(w + o_off), (double *)(w + o_scale));
@@ -86,7 +87,7 @@ int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, floa
   const double *scale = (const double *)(w + o_scale);
   int *list = (int *)(w + o_list);
   if (N > 0 && total > 0)
-    TLAUNCH(k_vox_fill, dim3(cdivv(N, 256)), dim3(256), 0, st, (const int4 *)(w + o_box), V, off,
+    TLAUNCH(k_vox_fill, dim3(cdivv(N, 4)), dim3(256), 0, st, (const int4 *)(w + o_box), V, off,
             (int *)(w + o_cur), list);
   TLAUNCH(k_vox_eval, dim3(nbr), dim3(256), 0, st, rec, (const int *)list, off, V, scale, vol);
   return CS_OK;
