@@ -14,9 +14,9 @@ struct VoxGeom {
   float q_cut;  // truncation of the squared Mahalanobis distance
 };
 
-__global__ void k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box);
+__global__ void k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box, double *wpart);
 __global__ void k_vox_count(const int4 *box, VoxGeom V, int *count);
-__global__ void k_vox_scan(const int *count, int nbr, const float4 *rec, int N, int *off,
+__global__ void k_vox_scan(const int *count, int nbr, const double *wpart, int nwp, int *off,
                            double *scale);
 __global__ void k_vox_fill(const int4 *box, VoxGeom V, const int *off, int *cursor, int *list);
 __global__ void k_vox_eval(const float4 *rec, const int *list, const int *off, VoxGeom V,

@@ -31,43 +31,52 @@ __device__ __forceinline__ int clampi(float x, int lo, int hi) {
 }
 
 // Per Gaussian: mean and weight, inverse covariance (FP64 adjugate) and the
-// brick range of its q <= q_cut box.
+// brick range of its q <= q_cut box; per block the sum of |w| (fixed-order
+// tree, FP64) for the fixed-point scale.
 __global__ void __launch_bounds__(256)
-k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box) {
+k_vox_prep(const float4 *gc, VoxGeom V, float4 *rec, int4 *box, double *wpart) {
+  __shared__ double red[256];
   const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= V.N) return;
-  const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
-  const double sxx = g1.x, sxy = g1.y, sxz = g1.z, syy = g1.w, syz = g2.x, szz = g2.y;
-  const double cxx = syy * szz - syz * syz, cxy = sxz * syz - sxy * szz, cxz = sxy * syz - sxz * syy;
-  const double cyy = sxx * szz - sxz * sxz, cyz = sxy * sxz - sxx * syz, czz = sxx * syy - sxy * sxy;
-  const double det = fmax(sxx * cxx + sxy * cxy + sxz * cxz, 1e-30);
-  const float w = (float)((double)g0.w * 0.063493635934240969 / sqrt(det));  // (2 pi)^-3/2
-  // quadratic form scaled by log2(e) / 2, cross terms doubled, so that
-  // exp(-q / 2) = 2^-(x^T B x) with B = (log2(e) / 2) Sigma^-1
-  const double f = 0.72134752044448170 / det;  // log2(e) / 2 / det
-  rec[3 * n] = make_float4(g0.x, g0.y, g0.z, w);
-  rec[3 * n + 1] = make_float4((float)(cxx * f), (float)(2.0 * cxy * f), (float)(2.0 * cxz * f),
-                               (float)(cyy * f));
-  rec[3 * n + 2] = make_float4((float)(2.0 * cyz * f), (float)(czz * f), 0.f, 0.f);
-  // axis-aligned box of the ellipsoid q <= q_cut: half extents sqrt(q_cut S_ii)
-  const float mu[3] = {g0.x, g0.y, g0.z};
-  const float hh[3] = {sqrtf(V.q_cut * g1.x), sqrtf(V.q_cut * g1.w), sqrtf(V.q_cut * g2.y)};
-  const float ip = 1.f / V.pixel;
-  int lo[3], hi[3];
-  bool empty = false;
+  double aw = 0.0;
+  if (n < V.N) {
+    const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
+    const double sxx = g1.x, sxy = g1.y, sxz = g1.z, syy = g1.w, syz = g2.x, szz = g2.y;
+    const double cxx = syy * szz - syz * syz, cxy = sxz * syz - sxy * szz, cxz = sxy * syz - sxz * syy;
+    const double cyy = sxx * szz - sxz * sxz, cyz = sxy * sxz - sxx * syz, czz = sxx * syy - sxy * sxy;
+    const double det = fmax(sxx * cxx + sxy * cxy + sxz * cxz, 1e-30);
+    const float w = (float)((double)g0.w * 0.063493635934240969 / sqrt(det));  // (2 pi)^-3/2
+    aw = fabs((double)w);
+    // quadratic form scaled by log2(e) / 2, cross terms doubled, so that
+    // exp(-q / 2) = 2^-(x^T B x) with B = (log2(e) / 2) Sigma^-1
+    const double f = 0.72134752044448170 / det;  // log2(e) / 2 / det
+    rec[3 * n] = make_float4(g0.x, g0.y, g0.z, w);
+    rec[3 * n + 1] = make_float4((float)(cxx * f), (float)(2.0 * cxy * f), (float)(2.0 * cxz * f),
+                                 (float)(cyy * f));
+    rec[3 * n + 2] = make_float4((float)(2.0 * cyz * f), (float)(czz * f), 0.f, 0.f);
+    // axis-aligned box of the ellipsoid q <= q_cut: half extents sqrt(q_cut S_ii)
+    const float mu[3] = {g0.x, g0.y, g0.z};
+    const float hh[3] = {sqrtf(V.q_cut * g1.x), sqrtf(V.q_cut * g1.w), sqrtf(V.q_cut * g2.y)};
+    const float ip = 1.f / V.pixel;
+    int lo[3], hi[3];
+    bool empty = false;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float a = ceilf((mu[k] - hh[k]) * ip + (float)V.c0);
-    const float b = floorf((mu[k] + hh[k]) * ip + (float)V.c0);
-    empty |= !(a <= b) || b < 0.f || a > (float)(V.D - 1);
-    lo[k] = clampi(a, 0, V.D - 1) / kBrick;
-    hi[k] = clampi(b, 0, V.D - 1) / kBrick;
+    for (int k = 0; k < 3; ++k) {
+      const float a = ceilf((mu[k] - hh[k]) * ip + (float)V.c0);
+      const float b = floorf((mu[k] + hh[k]) * ip + (float)V.c0);
+      empty |= !(a <= b) || b < 0.f || a > (float)(V.D - 1);
+      lo[k] = clampi(a, 0, V.D - 1) / kBrick;
+      hi[k] = clampi(b, 0, V.D - 1) / kBrick;
+    }
+    box[n] = empty ? make_int4(0, 0, 0, 0)
+                   : make_int4(lo[0] | (hi[0] << 16), lo[1] | (hi[1] << 16), lo[2] | (hi[2] << 16), 1);
   }
-  if (empty) {
-    box[n] = make_int4(0, 0, 0, 0);
-    return;
+  red[threadIdx.x] = aw;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
   }
-  box[n] = make_int4(lo[0] | (hi[0] << 16), lo[1] | (hi[1] << 16), lo[2] | (hi[2] << 16), 1);
+  if (threadIdx.x == 0) wpart[blockIdx.x] = red[0];
 }
 
 // Brick index of entry l of a Gaussian's brick box (x fastest).
@@ -97,9 +106,10 @@ k_vox_count(const int4 *box, VoxGeom V, int *count) {
 }
 
 // Exclusive scan of the brick counts (one block) and the fixed-point scale
-// of the voxel sums from the bound sum_n |w_n| (fixed-order FP64 sum).
+// of the voxel sums from the bound sum_n |w_n| (k_vox_prep's per-block
+// partials added in a fixed order, FP64).
 __global__ void __launch_bounds__(1024)
-k_vox_scan(const int *count, int nbr, const float4 *rec, int N, int *off, double *scale) {
+k_vox_scan(const int *count, int nbr, const double *wpart, int nwp, int *off, double *scale) {
   __shared__ int part[1024];
   __shared__ double wsum[1024];
   const int t = threadIdx.x;
@@ -109,7 +119,7 @@ k_vox_scan(const int *count, int nbr, const float4 *rec, int N, int *off, double
   for (int i = a; i < b; ++i) s += count[i];
   part[t] = s;
   double ws = 0.0;
-  for (int n = t; n < N; n += 1024) ws += fabs((double)rec[3 * n].w);
+  for (int i = t; i < nwp; i += 1024) ws += wpart[i];
   wsum[t] = ws;
   __syncthreads();
   for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan of the chunk sums

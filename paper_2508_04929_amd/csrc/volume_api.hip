@@ -40,7 +40,9 @@ int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, floa
   const size_t o_off = o_cnt + al256v((size_t)nbr * 4);
   const size_t o_cur = o_off + al256v((size_t)(nbr + 1) * 4);
   const size_t o_scale = o_cur + al256v((size_t)nbr * 4);
-  const size_t o_list = o_scale + 256;
+  const int nwp = (int)cdivv(N, 256);  // blocks of k_vox_prep: partial sums of |w|
+  const size_t o_wp = o_scale + 256;
+  const size_t o_list = o_wp + al256v((size_t)nwp * 8 + 8);
   int rc = grow(ctx, &ctx->vol, &ctx->vol_bytes, o_list + 256);
   if (rc) return rc;
   // per-Gaussian records, brick counts and offsets, fixed-point scale
@@ -57,12 +59,13 @@ int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, floa
       G.amp_act = g->amp_act;
       TLAUNCH(k_build, dim3(cdivv(N, kBlock)), dim3(kBlock), 0, st, g->means, g->log_scales,
               g->quats, g->amps, G, gc, (int *)nullptr, 0);
-      TLAUNCH(k_vox_prep, dim3(cdivv(N, 256)), dim3(256), 0, st, (const float4 *)gc, V, rec,
-              (int4 *)(w + o_box));
+      TLAUNCH(k_vox_prep, dim3(nwp), dim3(256), 0, st, (const float4 *)gc, V, rec,
+              (int4 *)(w + o_box), (double *)(w + o_wp));
       TLAUNCH(k_vox_count, dim3(cdivv(N, 4)), dim3(256), 0, st, (const int4 *)(w + o_box), V, cnt);
     }
-    TLAUNCH(k_vox_scan, dim3(1), dim3(1024), 0, st, (const int *)cnt, nbr, (const float4 *)rec, N,
-            (int *)(w + o_off), (double *)(w + o_scale));
+    TLAUNCH(k_vox_scan, dim3(1), dim3(1024), 0, st, (const int *)cnt, nbr,
+            (const double *)(w + o_wp), N > 0 ? nwp : 0, (int *)(w + o_off),
+            (double *)(w + o_scale));
     return CS_OK;
   };
   rc = prepare();
