@@ -54,3 +54,15 @@ def test_null_context_arguments_are_rejected(lib):
     assert L.cs_train_sequential(None, None, None, None, 1, 1, 1, None, None, None, 0, None, 0, 0,
                                  1e-3, 0.9, 0.999, 1e-8, None, None) == -1
     assert L.cs_split_gaussians(None, None, None, None, 1, 1, 1, None, None, None, None) == -1
+
+
+def test_flat_parameter_methods_reject_bad_lengths(lib):
+    """The binding checks the flat layout (11 values per Gaussian) before any
+    device call."""
+    import torch
+    bad = torch.zeros(12)
+    with pytest.raises(ValueError):
+        lib.split_gaussians(bad)
+    with pytest.raises(ValueError):
+        lib.train_sequential(bad, bad.clone(), bad.clone(), torch.zeros(1, 8, 8),
+                             torch.eye(3)[None], 1 / 8, [0], 0, 1e-3)
