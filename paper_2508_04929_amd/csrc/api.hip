@@ -417,7 +417,7 @@ int launch_backward_finish(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   TLAUNCH(k_big_bwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
           (const int *)(ws + P.L.off), (const int *)(ws + P.L.count),
           (const int *)(ws + P.L.n_items) + 1, G, P.GQ(), mom);
-  TLAUNCH(k_chain, dim3(cdiv(G.N, kBlock)), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.gc),
+  TLAUNCH(k_chain, dim3(cdiv(G.N, 64)), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.gc),
           P.g.log_scales, P.g.quats, P.g.amps, P.v.rot, P.v.shift, G, (const int *)(ws + P.L.key),
           mom, P.grads.means, P.grads.log_scales, P.grads.quats, P.grads.amps);
   if (P.grads.rot || P.grads.shift) {

@@ -350,13 +350,23 @@ __global__ void __launch_bounds__(kBlock)
 k_chain(const float4 *gc, const float *log_scales, const float *quats, const float *amps,
         const float *rot, const float *shift, Geom G, const int *key, const float *mom,
         float *g_means, float *g_log_scales, float *g_quats, float *g_amps) {
-  const int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= G.N) return;
-  const float4 g0 = gc[3 * n], g1 = gc[3 * n + 1], g2 = gc[3 * n + 2];
+  // 64 Gaussians per block; wave w of the four sums the images b = w mod 4
+  // (coalesced 64-Gaussian rows of every image, four times the waves of one
+  // thread per Gaussian), the partial sums meet in LDS in a fixed order
+  __shared__ float red[4][10][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  const bool live = n < G.N;
+  float4 g0 = make_float4(0, 0, 0, 0), g1 = g0, g2 = g0;
+  if (live) {
+    g0 = gc[3 * n];
+    g1 = gc[3 * n + 1];
+    g2 = gc[3 * n + 2];
+  }
   float dmu[3] = {0, 0, 0};
   float dS[6] = {0, 0, 0, 0, 0, 0};  // xx xy xz yy yz zz
   float dw_sum = 0.f;                // sum_b dL/dw * w / A  (= dL/dA)
-  for (int b = 0; b < G.B; ++b) {
+  for (int b = wv; live && b < G.B; b += 4) {
     if (key[(size_t)b * G.N + n] < 0) continue;
     float p0[3], p1[3], tx, ty;
     load_pose(rot, shift, b, p0, p1, tx, ty);
@@ -376,6 +386,19 @@ k_chain(const float4 *gc, const float *log_scales, const float *quats, const flo
     }
     dw_sum += m0 * rsqrtf(P.det) * 0.15915494309189535f;
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) red[wv][k][lane] = dmu[k];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) red[wv][3 + e][lane] = dS[e];
+  red[wv][9][lane] = dw_sum;
+  __syncthreads();
+  if (wv != 0 || !live) return;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dmu[k] = red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane];
+#pragma unroll
+  for (int e = 0; e < 6; ++e)
+    dS[e] = red[0][3 + e][lane] + red[1][3 + e][lane] + red[2][3 + e][lane] + red[3][3 + e][lane];
+  dw_sum = red[0][9][lane] + red[1][9][lane] + red[2][9][lane] + red[3][9][lane];
   // Sigma = M M^T, M = R diag(s)
   float s[3], dsdl[3];
 #pragma unroll
