@@ -530,10 +530,11 @@ typedef struct {
  * params [11 N] (layout of cs_init_attributes, activations scale_act /
  * amp_act) with moments adam_m, adam_v [11 N] (zero before the first step).
  * loss (device [count], or NULL) receives each step's loss before its
- * update.  The image, rotation and CTF values of a step are first copied
- * into fixed buffers, so with opt->graph = 1 the loss path is one replayed
- * HIP graph per step.  Enqueued on `stream`; identical inputs give
- * identical bits, with or without the graph. */
+ * update.  With opt->graph = 1 the image, rotation and CTF values of a
+ * step are first copied into fixed buffers, so that the loss path is one
+ * replayed HIP graph per step; otherwise they are read in place.  Enqueued
+ * on `stream`; identical inputs give identical bits, with or without the
+ * graph. */
 int cs_train_sequential(cs_ctx *ctx, float *params, float *adam_m, float *adam_v, int64_t n,
                         int32_t scale_act, int32_t amp_act, const cs_dataset *data,
                         const cs_ctf *ctf, const cs_options *opt, int32_t reduction,

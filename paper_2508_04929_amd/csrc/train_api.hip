@@ -129,9 +129,27 @@ int cs_train_sequential(cs_ctx *ctx, float *params, float *adam_m, float *adam_v
   pr.images_out = nullptr;
   const unsigned gblocks = std::min<unsigned>(cdivt((int64_t)npix, 256), 256);
   for (int64_t k = 0; k < count; ++k) {
-    float *rec = (loss && k > 0) ? loss + (k - 1) : nullptr;
-    TLAUNCH(k_train_gather, dim3(gblocks), dim3(256), 0, st, data->images, data->rot, src, order[k],
-            (int)npix, stage, (const float *)lossbuf, rec);
+    const int64_t i = order[k];
+    if (graph) {
+      // fixed pointers for the replayed graph: stage image i, record the
+      // previous step's loss
+      float *rec = (loss && k > 0) ? loss + (k - 1) : nullptr;
+      TLAUNCH(k_train_gather, dim3(gblocks), dim3(256), 0, st, data->images, data->rot, src, i,
+              (int)npix, stage, (const float *)lossbuf, rec);
+    } else {
+      // eager: read image i in place; the loss pair [image, total] goes to
+      // loss + k (the next step overwrites the total), the last step's to the
+      // scratch pair
+      pr.v.rot = data->rot + 9 * i;
+      pr.observed = data->images + i * (int64_t)npix;
+      if (ctf) {
+        sctf.defocus_u = ctf->defocus_u + i;
+        sctf.defocus_v = ctf->defocus_v + i;
+        sctf.astig = ctf->astig ? ctf->astig + i : nullptr;
+        sctf.phase = ctf->phase ? ctf->phase + i : nullptr;
+      }
+      pr.loss = (loss && k + 1 < count) ? loss + k : lossbuf;
+    }
     rc = run_loss(ctx, pr, graph, st);
     if (rc) return rc;
     const int64_t step = step0 + k + 1;
