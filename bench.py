@@ -312,7 +312,7 @@ def run_volume(reps: int = 5):
             "gaussians_per_s": gt.n / (ms_vox * 1e-3),
             "fsc_ms": ms_fsc,
             "fsc_bytes_min": 2 * D ** 3 * 4,
-            "resolution_A": binding.Library.resolution(curve.cpu().numpy(), D, p)}
+            "resolution_A": lib.resolution(curve, D, p)[0]}
 
 
 def run_trainer(steps: int = 1024, sizes=((256, 2048), (256, 10000), (256, 30000))):
@@ -399,14 +399,15 @@ def run_reconstruction(n: int = 10000, m: int = 10000, D: int = 128, p_a: float 
     lib.add_noise(images, snr_db, seed=22)
     Vgt = lib.voxelize(*g, D, 1.0 / D)
     tr = trainer.Trainer(lib, t(rng.standard_normal((n, 3))))
-    res0 = binding.Library.resolution(lib.fsc(tr.voxelize(D), Vgt).cpu().numpy(), D, p_a)
+    res0 = lib.resolution(lib.fsc(tr.voxelize(D), Vgt), D, p_a)[0]
     data = trainer.Dataset(images=images, rot=rot, shift=shift, ctf=ctf)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = tr.fit(data, epochs=epochs, lr=1e-3, gamma=gamma, seed=23, record_loss=True)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    curve = lib.fsc(tr.voxelize(D), Vgt).cpu().numpy()
+    curve_d = lib.fsc(tr.voxelize(D), Vgt)
+    curve = curve_d.cpu().numpy()
     floor, _, _ = lib.loss_and_grad(*g, rot, shift, D, 1.0 / D, images, ctf=ctf, want_grads=False)
     lo = losses.cpu().numpy()
     return {"workload": (f"N={n} Gaussians, paper initialisation, batch-1 Adam lr 1e-3 x {gamma}/epoch, "
@@ -416,7 +417,7 @@ def run_reconstruction(n: int = 10000, m: int = 10000, D: int = 128, p_a: float 
             "loss_first_epoch": float(lo[:m].mean()), "loss_last_epoch": float(lo[-m:].mean()),
             "loss_ground_truth": float(floor[-1]) / m,
             "fsc_resolution_A_initial": res0,
-            "fsc_resolution_A": binding.Library.resolution(curve, D, p_a),
+            "fsc_resolution_A": lib.resolution(curve_d, D, p_a)[0],
             "fsc_curve": [round(float(x), 4) for x in curve]}
 
 

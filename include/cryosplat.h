@@ -65,7 +65,8 @@ typedef enum {
   CS_ERR_INVALID_ARG = -1, /* null pointer, N < 0, B < 1, D < 1, pixel <= 0, ... */
   CS_ERR_UNSUPPORTED = -2, /* D not even with prime factors {2,3} when a CTF is used, D > 512 */
   CS_ERR_OOM = -3,         /* workspace allocation failed or exceeds CS_WORKSPACE_MAX bytes */
-  CS_ERR_HIP = -4          /* a HIP runtime call failed */
+  CS_ERR_HIP = -4,         /* a HIP runtime call failed */
+  CS_ERR_NONFINITE = -5    /* debug checks only: NaN or infinity in an input or output */
 } cs_status;
 
 typedef enum { CS_SUM = 0, CS_MEAN = 1 } cs_reduction;
@@ -115,7 +116,7 @@ typedef struct {
  * [B][2] are the gradients w.r.t. the views' rotation matrices (entry-wise,
  * the matrices taken as given, not constrained to SO(3); the third row does
  * not enter the image and gets 0) and shifts: the pose gradients that a
- * joint optimisation of poses and Gaussians needs (Sec. 6, future work),
+ * joint optimisation of poses and Gaussians needs (Sec. 5, limitation and future work),
  * from the same adjoint (App. A.2, Eq. 18 and 21):
  *   dL/dt = sum_n dL/dmu~_n,  dL/dP = sum_n (dL/dmu~_n mu_n^T + 2 dL/dSigma~_n P Sigma_n)
  * with P the first two rows of the rotation. */
@@ -229,6 +230,15 @@ int cs_pair_count(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v,
  * call's stream; enabling clears the accumulated totals.  Kernel names are
  * the library's stage names (e.g. "k_splat_fwd", "k_splat_bwd"). */
 int cs_set_timing(cs_ctx *ctx, int enable);
+
+/* Debug checks (also enabled at cs_create by CS_DEBUG_CHECKS=1 in the
+ * environment): after cs_render, cs_render_backward, cs_loss_and_grad and
+ * cs_loss_and_grad_multi have enqueued their work, every input and output
+ * array of the call is scanned on the device for NaN and infinity, the call
+ * synchronises its stream and returns CS_ERR_NONFINITE (inputs are reported
+ * before outputs) instead of CS_OK.  The outputs are still written.  Off by
+ * default: the scan and the synchronisation cost time on every call. */
+int cs_set_debug_checks(cs_ctx *ctx, int enable);
 
 /* Total milliseconds and launch count of stage `name` since timing was last
  * enabled (synchronises the recorded events).  Unknown names give 0. */
@@ -465,6 +475,15 @@ int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, floa
  * (reproducible). */
 int cs_fsc(cs_ctx *ctx, const float *vol_a, const float *vol_b, int32_t D, float *fsc,
            void *stream);
+
+/* Resolution read-out of an FSC curve (Sec. 4: the resolution at which the
+ * FSC of Eq. 10 falls below 0.143): fsc [D/2 + 1] (device, as cs_fsc writes
+ * it); shell [1] (device int32, may be NULL) receives the first shell
+ * k >= 1 with fsc[k] < threshold, or D/2 when there is none; resolution [1]
+ * (device float, may be NULL) receives D pixel / k in Angstrom.  At least
+ * one output must be given; D even, at most 512; pixel > 0. */
+int cs_fsc_resolution(cs_ctx *ctx, const float *fsc, int32_t D, float pixel, float threshold,
+                      int32_t *shell, float *resolution, void *stream);
 
 /* ApplyCTF of Alg. 1 for arbitrary images (App. A.2, Eq. 14):
  * out = F^-1(H^ . F images) [B][D][D], per-image CTF (NULL = identity);

@@ -21,7 +21,7 @@ then through Sigma = R diag(s)^2 R^T to s and the quaternion and through the
 activations to the stored parameters.
 
 The same per-image terms give the gradient w.r.t. the views themselves
-(the joint pose optimisation the paper leaves to future work, Sec. 6):
+(the joint pose optimisation the paper leaves to future work, Sec. 5):
 with P the first two rows of the view rotation W, mu~ = P mu + t and
 S~ = P Sigma P^T,
 

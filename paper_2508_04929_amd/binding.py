@@ -80,7 +80,7 @@ class CsProblem(ctypes.Structure):
 #: Entry points declared in include/cryosplat.h.
 EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_backward",
            "cs_loss_and_grad", "cs_loss_and_grad_multi", "cs_autotune", "cs_adam_step",
-           "cs_pair_count", "cs_set_timing", "cs_stage_time",
+           "cs_pair_count", "cs_set_timing", "cs_stage_time", "cs_set_debug_checks",
            "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_param_count", "cs_cnn_get_params",
            "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_forward_std", "cs_cnn_train_step",
            "cs_bf16_conv3x3s2_forward", "cs_bf16_conv3x3s2_dgrad", "cs_bf16_conv3x3s2_wgrad",
@@ -89,12 +89,20 @@ EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_b
            "cs_pose_bank_size", "cs_pose_bank_rotations", "cs_pose_grid_search", "cs_pose_refine", "cs_add_noise", "cs_cnn_tensor",
            "cs_pose_batch_create", "cs_pose_batch_destroy", "cs_pose_batch_load",
            "cs_pose_batch_search", "cs_pose_batch_refine", "cs_ctf_filter",
-           "cs_voxelize", "cs_fsc", "cs_fourier_shift", "cs_init_attributes",
-           "cs_train_sequential", "cs_split_gaussians")
+           "cs_voxelize", "cs_fsc", "cs_fsc_resolution", "cs_fourier_shift",
+           "cs_init_attributes", "cs_train_sequential", "cs_split_gaussians")
 
 
 class CryoSplatError(RuntimeError):
     pass
+
+
+class NonFiniteError(CryoSplatError):
+    """A call under debug checks found NaN or infinity (status CS_ERR_NONFINITE)."""
+
+
+#: status codes of include/cryosplat.h
+CS_ERR_INVALID_ARG, CS_ERR_UNSUPPORTED, CS_ERR_OOM, CS_ERR_HIP, CS_ERR_NONFINITE = -1, -2, -3, -4, -5
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -169,7 +177,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_pose_batch_load.argtypes = [vp, vp, P(CsCtf), i32, vp, vp, vp]
     lib.cs_pose_batch_search.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.cs_voxelize.argtypes = [vp, P(CsGaussians), i32, f32, f32, vp, vp]
+    lib.cs_set_debug_checks.argtypes = [vp, ctypes.c_int]
+    lib.cs_set_debug_checks.restype = ctypes.c_int
     lib.cs_fsc.argtypes = [vp, vp, vp, i32, vp, vp]
+    lib.cs_fsc_resolution.argtypes = [vp, vp, i32, f32, f32, vp, vp, vp]
     lib.cs_fourier_shift.argtypes = [vp, vp, vp, i64, i32, f32, f32, vp, vp]
     lib.cs_init_attributes.argtypes = [vp, vp, i64, vp, vp]
     lib.cs_split_gaussians.argtypes = [vp, vp, vp, vp, i64, i32, i32, vp, vp, vp, vp]
@@ -180,7 +191,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
     for name in ("cs_pose_batch_create", "cs_pose_batch_load", "cs_pose_batch_search",
                  "cs_pose_batch_refine", "cs_ctf_filter", "cs_voxelize", "cs_fsc",
-                 "cs_fourier_shift", "cs_init_attributes", "cs_train_sequential",
+                 "cs_fsc_resolution", "cs_fourier_shift", "cs_init_attributes", "cs_train_sequential",
                  "cs_split_gaussians", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
                  "cs_pose_grid_search", "cs_pose_refine"):
         getattr(lib, name).restype = ctypes.c_int
@@ -280,7 +291,8 @@ class Library:
     def _check(self, ctx, rc, what):
         if rc != 0:
             msg = self.lib.cs_last_error(ctx).decode(errors="replace")
-            raise CryoSplatError(f"{what} failed ({rc}): {msg}")
+            cls = NonFiniteError if rc == CS_ERR_NONFINITE else CryoSplatError
+            raise cls(f"{what} failed ({rc}): {msg}")
 
     # -- struct packing -------------------------------------------------
     @staticmethod
@@ -446,15 +458,19 @@ class Library:
         self._check(ctx, rc, "cs_train_sequential")
         return loss
 
-    @staticmethod
-    def resolution(fsc, D, pixel, threshold=0.143):
-        """Resolution in Angstrom: D p / k at the first shell k >= 1 where the
-        curve drops below the threshold (the last shell if it never does)."""
-        c = [float(x) for x in fsc]
-        for k in range(1, len(c)):
-            if c[k] < threshold:
-                return D * float(pixel) / k
-        return D * float(pixel) / (len(c) - 1)
+    def resolution(self, fsc, D, pixel, threshold=0.143):
+        """Resolution read-out of an FSC curve on the device (cs_fsc_resolution):
+        returns (resolution in Angstrom, shell index) as host numbers."""
+        dev = fsc.device
+        _ptr(fsc, "fsc", dev, (D // 2 + 1,))
+        out = torch.empty(2, device=dev, dtype=torch.float32)
+        ctx = self.ctx(dev)
+        shell = out[1:].view(torch.int32)
+        self._check(ctx, self.lib.cs_fsc_resolution(
+            ctx, fsc.data_ptr(), int(D), float(pixel), float(threshold), shell.data_ptr(),
+            out.data_ptr(), torch.cuda.current_stream(dev).cuda_stream), "cs_fsc_resolution")
+        h = out.cpu()
+        return float(h[0]), int(h[1:].view(torch.int32)[0])
 
     def _grads(self, dev, n, b, pose=False):
         """Fresh gradient outputs: the Gaussian parameters, and with pose the
@@ -591,6 +607,13 @@ class Library:
         self._check(ctx, rc, "cs_pair_count")
         return out
 
+
+    def set_debug_checks(self, device, enable: bool):
+        """Debug checks: calls scan their inputs and outputs for NaN / infinity,
+        synchronise, and fail with status CS_ERR_NONFINITE (NonFiniteError)."""
+        dev = self._device(device)
+        self._check(self.ctx(dev), self.lib.cs_set_debug_checks(self.ctx(dev), int(bool(enable))),
+                    "cs_set_debug_checks")
 
     def set_timing(self, device, enable: bool):
         ctx = self.ctx(torch.device(device))

@@ -522,6 +522,53 @@ int fill(cs_ctx *ctx, float *p, size_t n, hipStream_t st) {
   return CS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Debug checks (CS_ERR_NONFINITE): after a call's work, every input and
+// output array is scanned for NaN / infinity; the call then synchronises its
+// stream and reports the first class found (inputs before outputs).
+// ---------------------------------------------------------------------------
+struct CheckList {
+  std::vector<std::pair<const float *, int64_t>> in, out;
+  void input(const float *p, int64_t n) { if (p && n > 0) in.push_back({p, n}); }
+  void output(const float *p, int64_t n) { if (p && n > 0) out.push_back({p, n}); }
+  void gaussians(const cs_gaussians &g) {
+    input(g.means, 3 * g.n); input(g.log_scales, 3 * g.n); input(g.quats, 4 * g.n); input(g.amps, g.n);
+  }
+  void views(const cs_views &v) { input(v.rot, 9 * v.b); input(v.shift, 2 * v.b); }
+  void grads(const cs_grads &gr, int64_t n, int64_t b) {
+    output(gr.means, 3 * n); output(gr.log_scales, 3 * n); output(gr.quats, 4 * n);
+    output(gr.amps, n); output(gr.rot, 9 * b); output(gr.shift, 2 * b);
+  }
+};
+
+int run_debug_checks(cs_ctx *ctx, const CheckList &L, hipStream_t st) {
+  if (!ctx->debug_checks) return CS_OK;
+  if (!ctx->check_flag) HIPCHK(hipMalloc((void **)&ctx->check_flag, 256));
+  // 0.f has the bit pattern of integer 0: the fill kernel clears the flag
+  TLAUNCH(k_fill, dim3(1), dim3(kBlock), 0, st, (float *)ctx->check_flag, (int64_t)1, 0.f);
+  for (int cls = 0; cls < 2; ++cls)
+    for (const auto &a : cls ? L.out : L.in)
+      TLAUNCH(k_check_finite, dim3((unsigned)std::min<int64_t>(1024, cdiv(a.second, kBlock))),
+              dim3(kBlock), 0, st, a.first, a.second, 1 << cls, ctx->check_flag);
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, ctx->check_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h & 1) return fail(ctx, CS_ERR_NONFINITE, "debug checks: NaN or infinity in an input array");
+  if (h & 2) return fail(ctx, CS_ERR_NONFINITE, "debug checks: NaN or infinity in an output array");
+  return CS_OK;
+}
+
+CheckList loss_checks(const cs_problem &p) {
+  CheckList L;
+  L.gaussians(p.g);
+  L.views(p.v);
+  L.input(p.observed, p.v.b * (int64_t)p.v.d * p.v.d);
+  L.output(p.loss, p.v.b + 1);
+  L.grads(p.grads, p.g.n, p.v.b);
+  L.output(p.images_out, p.v.b * (int64_t)p.v.d * p.v.d);
+  return L;
+}
+
 // The whole launch sequence of a set of plans, in stage order.
 int enqueue(cs_ctx *ctx, std::vector<Plan> &plans, hipStream_t st) {
   int rc;
@@ -652,7 +699,11 @@ int run_loss_problems(cs_ctx *ctx, const cs_problem *problems, int count, bool u
   }
   int rc = place(ctx, plans, st);
   if (rc) return rc;
-  if (!use_graph) return enqueue(ctx, plans, st);
+  if (!use_graph) {
+    rc = enqueue(ctx, plans, st);
+    for (int i = 0; i < count && rc == CS_OK; ++i) rc = run_debug_checks(ctx, loss_checks(problems[i]), st);
+    return rc;
+  }
   const std::string key = signature(ctx, problems, count);
   auto it = ctx->graphs.find(key);
   if (it == ctx->graphs.end()) {
@@ -675,7 +726,8 @@ int run_loss_problems(cs_ctx *ctx, const cs_problem *problems, int count, bool u
     it = ctx->graphs.emplace(key, exec).first;
   }
   HIPCHK(hipGraphLaunch(it->second, st));
-  return CS_OK;
+  for (int i = 0; i < count && rc == CS_OK; ++i) rc = run_debug_checks(ctx, loss_checks(problems[i]), st);
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -760,6 +812,8 @@ int cs_create(int device, cs_ctx **out) {
     c->n_cu = prop.multiProcessorCount;
   const char *cap = std::getenv("CS_WORKSPACE_MAX");
   if (cap) c->ws_max = (size_t)std::strtoull(cap, nullptr, 10);
+  const char *dc = std::getenv("CS_DEBUG_CHECKS");
+  c->debug_checks = dc && std::strcmp(dc, "0") != 0 && dc[0] != 0;
   const char *tf = std::getenv("CS_AUTOTUNE_CACHE");
   if (tf) c->tune_file = tf;
   load_tune_file(c);
@@ -782,6 +836,7 @@ void cs_destroy(cs_ctx *ctx) {
     (void)hipEventDestroy(p.b);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->check_flag) (void)hipFree(ctx->check_flag);
   if (ctx->aux) (void)hipFree(ctx->aux);
   if (ctx->vol) (void)hipFree(ctx->vol);
   if (ctx->train) (void)hipFree(ctx->train);
@@ -810,7 +865,13 @@ int cs_render(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ct
   P.L = make_layout(P.G, P.fwd, false, ctf != nullptr);
   rc = place(ctx, plans, st);
   if (rc) return rc;
-  return enqueue(ctx, plans, st);
+  rc = enqueue(ctx, plans, st);
+  if (rc) return rc;
+  CheckList L;
+  L.gaussians(*g);
+  L.views(*v);
+  L.output(images, v->b * (int64_t)v->d * v->d);
+  return run_debug_checks(ctx, L, st);
 }
 
 int cs_render_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf *ctf,
@@ -835,7 +896,14 @@ int cs_render_backward(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, co
   P.L = make_layout(P.G, false, true, ctf != nullptr);
   rc = place(ctx, plans, st);
   if (rc) return rc;
-  return enqueue(ctx, plans, st);
+  rc = enqueue(ctx, plans, st);
+  if (rc) return rc;
+  CheckList L;
+  L.gaussians(*g);
+  L.views(*v);
+  L.input(d_images, v->b * (int64_t)v->d * v->d);
+  L.grads(*grads, g->n, v->b);
+  return run_debug_checks(ctx, L, st);
 }
 
 int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf *ctf,
@@ -959,6 +1027,12 @@ int cs_pair_count(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const c
           g->quats, g->amps, G, gc, (int *)nullptr, 0);
   TLAUNCH(k_pair_count, dim3(cdiv(G.N, kBlock), G.B), dim3(kBlock), 0, st, gc, v->rot, v->shift,
           G, (unsigned long long *)counts);
+  return CS_OK;
+}
+
+int cs_set_debug_checks(cs_ctx *ctx, int enable) {
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  ctx->debug_checks = enable != 0;
   return CS_OK;
 }
 

@@ -41,6 +41,10 @@ struct cs_ctx {
   // scratch of the training loop (gradients, staged image) and FourierShift
   void *train = nullptr;
   size_t train_bytes = 0;
+  // debug checks (CS_ERR_NONFINITE): device flag, enabled by cs_set_debug_checks
+  // or CS_DEBUG_CHECKS=1 in the environment at cs_create
+  bool debug_checks = false;
+  int *check_flag = nullptr;
 };
 
 namespace cs {

@@ -28,6 +28,8 @@ __global__ void k_fsc_shells(const float2 *fa, const float2 *fb, int D, const do
                              unsigned long long *sums);
 __global__ void k_fsc_final(const unsigned long long *sums, int ns, const double *scale,
                             float *fsc);
+__global__ void k_fsc_resolution(const float *fsc, int ns, int D, float pixel, float threshold,
+                                 int *shell, float *resolution);
 __global__ void k_fill_u64z(unsigned long long *p, int n);
 __global__ void k_fill_i32z(int *p, int n);
 

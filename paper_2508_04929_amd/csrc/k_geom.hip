@@ -468,7 +468,7 @@ k_chain(const float4 *gc, const float *log_scales, const float *quats, const flo
 
 // ---------------------------------------------------------------------------
 // Pose gradients (the joint pose optimisation the paper names as future work,
-// Sec. 6, from the same adjoint, App. A.2 Eq. 18 and 21).  With the
+// Sec. 5, from the same adjoint, App. A.2 Eq. 18 and 21).  With the
 // projection P = the first two rows of the view rotation W, mu~ = P mu + t
 // and Sigma~ = P Sigma P^T:
 //   dL/dt = sum_n dL/dmu~_n,
@@ -637,6 +637,16 @@ k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float 
 __global__ void __launch_bounds__(kBlock) k_fill(float *p, int64_t n, float value) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) p[i] = value;
+}
+
+// Debug checks: flag[0] |= bit when any of the n values is NaN or infinite.
+__global__ void __launch_bounds__(kBlock)
+k_check_finite(const float *p, int64_t n, int bit, int *flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    bad |= !isfinite(p[i]);
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, bit);
 }
 
 }  // namespace cs

@@ -327,6 +327,27 @@ k_fsc_final(const unsigned long long *sums, int ns, const double *scale, float *
   fsc[s] = den > 0.0 ? (float)(num / den) : 0.f;
 }
 
+// Resolution read-out of an FSC curve: the first shell k >= 1 whose
+// correlation is below the threshold (the last shell, D/2, when none is),
+// and D p / k in Angstrom.  One wave: a ballot over the shells in order.
+__global__ void __launch_bounds__(64)
+k_fsc_resolution(const float *fsc, int ns, int D, float pixel, float threshold, int *shell,
+                 float *resolution) {
+  int first = ns - 1;
+  for (int base = 1; base < ns; base += 64) {
+    const int k = base + (int)threadIdx.x;
+    const unsigned long long below = __ballot(k < ns && fsc[k] < threshold);
+    if (below) {
+      first = base + __ffsll((long long)below) - 1;
+      break;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (shell) *shell = first;
+    if (resolution) *resolution = (float)((double)D * (double)pixel / (double)first);
+  }
+}
+
 __global__ void __launch_bounds__(256) k_fill_u64z(unsigned long long *p, int n) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) p[i] = 0ull;

@@ -143,4 +143,17 @@ int cs_fsc(cs_ctx *ctx, const float *vol_a, const float *vol_b, int32_t D, float
   return CS_OK;
 }
 
+int cs_fsc_resolution(cs_ctx *ctx, const float *fsc, int32_t D, float pixel, float threshold,
+                      int32_t *shell, float *resolution, void *stream) {
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  if (!fsc || (!shell && !resolution)) return fail(ctx, CS_ERR_INVALID_ARG, "null curve or outputs");
+  if (D < 2 || D % 2 != 0 || D > 512) return fail(ctx, CS_ERR_UNSUPPORTED, "D must be even, at most 512");
+  if (!(pixel > 0.f)) return fail(ctx, CS_ERR_INVALID_ARG, "voxel size must be positive");
+  if (!(threshold == threshold)) return fail(ctx, CS_ERR_INVALID_ARG, "threshold is NaN");
+  HIPCHK(hipSetDevice(ctx->device));
+  TLAUNCH(k_fsc_resolution, dim3(1), dim3(64), 0, (hipStream_t)stream, fsc, D / 2 + 1, D, pixel,
+          threshold, (int *)shell, resolution);
+  return CS_OK;
+}
+
 }  // extern "C"

@@ -191,10 +191,10 @@ def test_end_to_end_reconstruction_improves_fsc(gpu_lib):
     tr = trainer.Trainer(lib, z)
     V0 = tr.voxelize(D)
     Vgt = lib.voxelize(g["means"], g["log_scales"], g["quats"], g["amps"], D, 1.0 / D)
-    res0 = binding.Library.resolution(host(lib.fsc(V0, Vgt)), D, p_a)
+    res0 = lib.resolution(lib.fsc(V0, Vgt), D, p_a)[0]
     announce("end-to-end: 5 epochs x 3000 particles, N=2000, D=64")
     losses = host(tr.fit(data, epochs=5, lr=1e-3, gamma=0.5, seed=1, record_loss=True))
-    res = binding.Library.resolution(host(lib.fsc(tr.voxelize(D), Vgt)), D, p_a)
+    res = lib.resolution(lib.fsc(tr.voxelize(D), Vgt), D, p_a)[0]
     first, last = losses[:M].mean(), losses[-M:].mean()
     # the noise floor: the ground truth's own loss on the same particles
     floor, _, _ = lib.loss_and_grad(g["means"], g["log_scales"], g["quats"], g["amps"], rot, shift,

@@ -110,10 +110,13 @@ def test_fsc_of_reconstruction_like_pair(gpu_lib):
                        g.amps.copy())
     D, p = 64, 1.0
     Va, Vb = _vox(gpu_lib, g, D, p), _vox(gpu_lib, h, D, p)
-    got = host(gpu_lib.fsc(Va, Vb))
+    got_d = gpu_lib.fsc(Va, Vb)
+    got = host(got_d)
     ref = o_vol.fsc(host(Va).astype(np.float32), host(Vb).astype(np.float32))
     assert np.abs(got - ref).max() <= 1e-5
-    assert binding.Library.resolution(got, D, p) == pytest.approx(o_vol.resolution(ref, D, p))
+    res, shell = gpu_lib.resolution(got_d, D, p)
+    assert res == pytest.approx(o_vol.resolution(ref, D, p), rel=1e-6)
+    assert res == pytest.approx(D * p / shell, rel=1e-6)
 
 
 def test_volume_full_size_sampled(gpu_lib):
@@ -144,7 +147,8 @@ def test_volume_full_size_sampled(gpu_lib):
     err_e = (np.log2(D ** 3) * 2.0 ** -24) ** 2 * total * n_s / D ** 3
     bound = 1e-5 + 4.0 * np.sqrt(err_e / np.maximum(np.minimum(da, db), 1e-300))
     worst = np.max(np.abs(got - ref) / bound)
+    res, _shell = gpu_lib.resolution(dev(got), D, p)
     announce(f"  max |FSC - oracle| / bound = {worst:.3f}; resolution "
-             f"{binding.Library.resolution(got, D, p):.2f} A (oracle {o_vol.resolution(ref, D, p):.2f} A)")
+             f"{res:.2f} A (oracle {o_vol.resolution(ref, D, p):.2f} A)")
     assert worst <= 1.0
-    assert binding.Library.resolution(got, D, p) == pytest.approx(o_vol.resolution(ref, D, p))
+    assert res == pytest.approx(o_vol.resolution(ref, D, p), rel=1e-6)

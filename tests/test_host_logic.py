@@ -66,3 +66,29 @@ def test_flat_parameter_methods_reject_bad_lengths(lib):
     with pytest.raises(ValueError):
         lib.train_sequential(bad, bad.clone(), bad.clone(), torch.zeros(1, 8, 8),
                              torch.eye(3)[None], 1 / 8, [0], 0, 1e-3)
+
+
+def test_status_codes_map_to_exceptions():
+    """The binding's error mapping, forced from the host with a stand-in
+    library object: CS_ERR_NONFINITE raises NonFiniteError (a CryoSplatError),
+    other negative codes CryoSplatError with the context's message."""
+    from paper_2508_04929_amd import binding
+
+    class Fake:
+        def cs_last_error(self, ctx):
+            return b"debug checks: NaN or infinity in an input array"
+
+    L = binding.Library(Fake())
+    L._check(None, 0, "ok call")
+    with pytest.raises(binding.NonFiniteError, match="input array"):
+        L._check(None, binding.CS_ERR_NONFINITE, "cs_render")
+    with pytest.raises(binding.CryoSplatError) as e:
+        L._check(None, binding.CS_ERR_INVALID_ARG, "cs_render")
+    assert not isinstance(e.value, binding.NonFiniteError)
+    # the header's enum carries the same value
+    src = open(os.path.join(ROOT, "include", "cryosplat.h")).read()
+    assert "CS_ERR_NONFINITE = -5" in src
+
+
+def test_debug_check_switch_rejects_null_context(lib):
+    assert lib.lib.cs_set_debug_checks(None, 1) == -1
