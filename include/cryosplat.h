@@ -174,6 +174,35 @@ int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v,
                      const float *observed, int32_t reduction, float *loss,
                      cs_grads *grads, float *images_out, void *stream);
 
+/* Size in bytes of the library's static device scratch (64 MiB), the
+ * largest workspace cs_loss_and_grad_noalloc can use. */
+#define CS_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* cs_loss_and_grad without any device allocation, for callers that cannot
+ * allocate: code under HIP stream capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and errors as
+ * cs_loss_and_grad, except:
+ *   - the workspace is a static device array of CS_NOALLOC_SCRATCH_BYTES
+ *     that the library holds on every device it runs on until the process
+ *     ends (its address is looked up once per device by cs_create); a call
+ *     whose workspace (about 32 B per Gaussian-image pair plus the canvases,
+ *     spectra and moments of its B images) does not fit returns CS_ERR_OOM
+ *     before anything is enqueued;
+ *   - opt->graph is ignored (the call never captures or instantiates a
+ *     graph itself; a caller may capture it into its own), stage timing is
+ *     off and debug checks are not run;
+ *   - every call on a device shares that device's scratch and leaves its
+ *     contents behind; the kernels clear what must start at zero, so calls
+ *     in sequence are independent, but calls that overlap in time on one
+ *     device (two streams, two threads, two contexts) race and give
+ *     undefined results.
+ * On success the call makes no device allocation: no hipMalloc or hipFree,
+ * no events, streams or graphs. */
+int cs_loss_and_grad_noalloc(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v,
+                             const cs_ctf *ctf, const cs_options *opt,
+                             const float *observed, int32_t reduction, float *loss,
+                             cs_grads *grads, float *images_out, void *stream);
+
 /* One independent rendering problem of a batched call: a mixture, its
  * images (each problem has its own D and pixel size), CTF (NULL = none),
  * launch options (zeros = defaults), observed images and outputs.  Loss and

@@ -79,7 +79,8 @@ class CsProblem(ctypes.Structure):
 
 #: Entry points declared in include/cryosplat.h.
 EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_backward",
-           "cs_loss_and_grad", "cs_loss_and_grad_multi", "cs_autotune", "cs_adam_step",
+           "cs_loss_and_grad", "cs_loss_and_grad_noalloc", "cs_loss_and_grad_multi",
+           "cs_autotune", "cs_adam_step",
            "cs_pair_count", "cs_set_timing", "cs_stage_time", "cs_set_debug_checks",
            "cs_cnn_create", "cs_cnn_destroy", "cs_cnn_param_count", "cs_cnn_get_params",
            "cs_cnn_set_params", "cs_cnn_forward", "cs_cnn_forward_std", "cs_cnn_train_step",
@@ -128,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cs_loss_and_grad.argtypes = [vp, P(CsGaussians), P(CsViews), P(CsCtf), P(CsOptions), vp,
                                      i32, vp, P(CsGrads), vp, vp]
     lib.cs_loss_and_grad.restype = ctypes.c_int
+    lib.cs_loss_and_grad_noalloc.argtypes = lib.cs_loss_and_grad.argtypes
+    lib.cs_loss_and_grad_noalloc.restype = ctypes.c_int
     lib.cs_loss_and_grad_multi.argtypes = [vp, P(CsProblem), i32, i32, vp]
     lib.cs_loss_and_grad_multi.restype = ctypes.c_int
     lib.cs_autotune.argtypes = [vp, P(CsProblem), i32, i32, vp]
@@ -498,10 +501,13 @@ class Library:
     def loss_and_grad(self, means, log_scales, quats, amps, rot, shift, D, pixel, observed,
                       ctf=None, options=None, reduction="sum", want_grads=True,
                       want_images=False, scale_act="exp", amp_act="identity", grads=None,
-                      loss=None, want_pose_grads=False):
+                      loss=None, want_pose_grads=False, images=None, noalloc=False):
         """Loss per image (+ total) and gradients; with want_pose_grads the
         gradients also hold "rot" [B][3][3] and "shift" [B][2]; a caller's
-        grads dict may hold any subset of the six outputs."""
+        grads dict may hold any subset of the six outputs.  With
+        noalloc=True the call goes to cs_loss_and_grad_noalloc (the library's
+        static scratch; pass preallocated loss, grads and images to keep the
+        whole call free of allocations)."""
         dev, n, b, g, v, c, o = self._pack(means, log_scales, quats, amps, rot, shift, D, pixel,
                                            ctf, options, scale_act, amp_act)
         _ptr(observed, "observed", dev, (b, D, D))
@@ -514,14 +520,17 @@ class Library:
                 grads, cg = self._grads(dev, n, b, want_pose_grads)
             else:
                 cg = _grads_struct(grads, dev, n, b)
-        images = torch.empty((b, D, D), device=dev, dtype=torch.float32) if want_images else None
+        if images is not None:
+            _ptr(images, "images", dev, (b, D, D))
+        elif want_images:
+            images = torch.empty((b, D, D), device=dev, dtype=torch.float32)
         ctx = self.ctx(dev)
-        rc = self.lib.cs_loss_and_grad(
-            ctx, ctypes.byref(g), ctypes.byref(v), self._ref(c), self._ref(o), observed.data_ptr(),
-            CS_MEAN if reduction == "mean" else CS_SUM, loss.data_ptr(), self._ref(cg),
-            images.data_ptr() if images is not None else None,
-            torch.cuda.current_stream(dev).cuda_stream)
-        self._check(ctx, rc, "cs_loss_and_grad")
+        fn = self.lib.cs_loss_and_grad_noalloc if noalloc else self.lib.cs_loss_and_grad
+        rc = fn(ctx, ctypes.byref(g), ctypes.byref(v), self._ref(c), self._ref(o),
+                observed.data_ptr(), CS_MEAN if reduction == "mean" else CS_SUM, loss.data_ptr(),
+                self._ref(cg), images.data_ptr() if images is not None else None,
+                torch.cuda.current_stream(dev).cuda_stream)
+        self._check(ctx, rc, "cs_loss_and_grad_noalloc" if noalloc else "cs_loss_and_grad")
         return loss, (grads if want_grads else None), images
 
     # -- batched problems -------------------------------------------------

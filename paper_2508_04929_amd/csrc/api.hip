@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -39,6 +40,43 @@ constexpr int kMaxD = 512;
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Static scratch of cs_loss_and_grad_noalloc: device memory that exists for
+// as long as the library is loaded, so that entry point needs no allocation.
+// In host code `scratch` is only a stand-in for the symbol; the device
+// address comes from hipGetSymbolAddress, once per device (every device
+// holds its own copy of the array).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)CS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_rc[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, which must be current.
+hipError_t scratch_address(int device, char **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch_rc[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? (char *)p : nullptr;
+    g_scratch_done[device] = true;
+  }
+  *out = g_scratch_ptr[device];
+  return g_scratch_rc[device];
+}
 
 }  // namespace
 
@@ -95,6 +133,7 @@ struct Plan {
   Geom G{};
   Layout L;
   char *ws = nullptr;  // this problem's workspace region
+  const float2 *tw = nullptr;  // FFT twiddles; null = the context's cached table
   bool fwd = false;    // runs the forward splat
   bool bwd = false;    // runs the adjoint
   // RENDER
@@ -191,14 +230,13 @@ int get_twiddles(cs_ctx *ctx, int L, const float2 **out) {
   auto it = ctx->twiddles.find(L);
   if (it != ctx->twiddles.end()) { *out = it->second; return CS_OK; }
   if (ctx->capturing) return fail(ctx, CS_ERR_HIP, "twiddle upload during graph capture");
-  std::vector<float2> h(L);
-  for (int k = 0; k < L; ++k) {
-    const double a = 2.0 * M_PI * (double)k / (double)L;
-    h[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
-  }
   float2 *d = nullptr;
   HIPCHK(hipMalloc(&d, sizeof(float2) * L));
-  HIPCHK(hipMemcpy(d, h.data(), sizeof(float2) * L, hipMemcpyHostToDevice));
+  // the same table kernel serves the static-scratch entry point, so both
+  // paths transform with identical twiddles
+  hipLaunchKernelGGL(k_twiddles, dim3(cdiv(L, 256)), dim3(256), 0, nullptr, L, d);
+  LAUNCHCHK("k_twiddles");
+  HIPCHK(hipStreamSynchronize(nullptr));
   ctx->twiddles[L] = d;
   *out = d;
   return CS_OK;
@@ -355,38 +393,43 @@ ProbDev prob_dev(const Plan &P) {
 // Persistent launches of the forward or adjoint splat over the given
 // problems: problems with the same canvas size share one launch (up to
 // kMaxProblems each), so that no problem runs at the occupancy of a larger
-// canvas; groups keep the problems' order.
-int launch_persistent(cs_ctx *ctx, bool forward, const std::vector<const Plan *> &all,
-                      hipStream_t st) {
-  std::vector<std::vector<const Plan *>> groups;
-  std::vector<int> sizes;
-  for (const Plan *pl : all) {
-    const int cs = pl->G.C * pl->G.S;
-    size_t g = 0;
-    while (g < sizes.size() && sizes[g] != cs) ++g;
-    if (g == sizes.size()) {
-      sizes.push_back(cs);
-      groups.emplace_back();
-    }
-    groups[g].push_back(pl);
+// canvas; groups keep the problems' order.  Allocates nothing.
+int launch_one_persistent(cs_ctx *ctx, bool forward, const MultiProb &MP, size_t lds,
+                          hipStream_t st) {
+  int grid = 0;
+  int rc = persistent_grid(ctx, forward ? (const void *)k_splat_fwd : (const void *)k_splat_bwd,
+                           lds, &grid);
+  if (rc) return rc;
+  if (forward) {
+    TLAUNCH(k_splat_fwd, dim3(grid), dim3(kBlock), lds, st, MP);
+  } else {
+    TLAUNCH(k_splat_bwd, dim3(grid), dim3(kBlock), lds, st, MP);
   }
-  for (const auto &ps : groups)
-  for (size_t c0 = 0; c0 < ps.size(); c0 += kMaxProblems) {
+  return CS_OK;
+}
+
+int launch_persistent(cs_ctx *ctx, bool forward, const Plan *const *all, int n, hipStream_t st) {
+  auto canvas = [&](int i) { return all[i]->G.C * all[i]->G.S; };
+  for (int i = 0; i < n; ++i) {
+    bool seen = false;  // canvas size already launched with an earlier group
+    for (int j = 0; j < i && !seen; ++j) seen = canvas(j) == canvas(i);
+    if (seen) continue;
     MultiProb MP{};
     size_t lds = 0;
-    MP.count = (int)std::min<size_t>(kMaxProblems, ps.size() - c0);
-    for (int i = 0; i < MP.count; ++i) {
-      MP.p[i] = prob_dev(*ps[c0 + i]);
-      lds = std::max(lds, (size_t)MP.p[i].G.C * MP.p[i].G.S * 4);
+    for (int k = i; k < n; ++k) {
+      if (canvas(k) != canvas(i)) continue;
+      MP.p[MP.count++] = prob_dev(*all[k]);
+      lds = std::max(lds, (size_t)canvas(k) * 4);
+      if (MP.count == kMaxProblems) {
+        int rc = launch_one_persistent(ctx, forward, MP, lds, st);
+        if (rc) return rc;
+        MP = MultiProb{};
+        lds = 0;
+      }
     }
-    int grid = 0;
-    int rc = persistent_grid(ctx, forward ? (const void *)k_splat_fwd : (const void *)k_splat_bwd,
-                             lds, &grid);
-    if (rc) return rc;
-    if (forward) {
-      TLAUNCH(k_splat_fwd, dim3(grid), dim3(kBlock), lds, st, MP);
-    } else {
-      TLAUNCH(k_splat_bwd, dim3(grid), dim3(kBlock), lds, st, MP);
+    if (MP.count) {
+      int rc = launch_one_persistent(ctx, forward, MP, lds, st);
+      if (rc) return rc;
     }
   }
   return CS_OK;
@@ -441,10 +484,13 @@ struct FftLaunch {
   int cpw = 16;
 };
 
-int fft_setup(cs_ctx *ctx, const Geom &G, FftLaunch &F) {
+int fft_setup(cs_ctx *ctx, const Geom &G, const float2 *tw, FftLaunch &F) {
   fft_plan(G.D, F.P);
-  int rc = get_twiddles(ctx, G.D, &F.tw);
-  if (rc) return rc;
+  F.tw = tw;
+  if (!F.tw) {
+    int rc = get_twiddles(ctx, G.D, &F.tw);
+    if (rc) return rc;
+  }
   F.rgrid = dim3(cdiv(G.D / 2, 4), G.B);
   F.rlds = (size_t)(4 * 2 + 1) * G.D * 8;  // four row pairs (ping-pong) + twiddles
   F.rblock = dim3(256);
@@ -472,7 +518,7 @@ int launch_ctf_table(cs_ctx *ctx, const Plan &P, hipStream_t st) {
 int launch_ctf_roundtrip(cs_ctx *ctx, const Plan &P, const float *src, float *dst, hipStream_t st) {
   const Geom &G = P.G;
   FftLaunch F;
-  int rc = fft_setup(ctx, G, F);
+  int rc = fft_setup(ctx, G, P.tw, F);
   if (rc) return rc;
   float2 *spec = (float2 *)(P.ws + P.L.spec);
   TLAUNCH(k_fft_rows_fwd, F.rgrid, F.rblock, F.rlds, st, src, F.P, F.tw, G.B, spec);
@@ -492,7 +538,7 @@ int launch_loss(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   int parts;
   if (P.ctf) {
     FftLaunch F;
-    int rc = fft_setup(ctx, G, F);
+    int rc = fft_setup(ctx, G, P.tw, F);
     if (rc) return rc;
     float2 *spec = (float2 *)(P.ws + P.L.spec);
     const float *table = (const float *)(P.ws + P.L.ctf);
@@ -569,10 +615,13 @@ CheckList loss_checks(const cs_problem &p) {
   return L;
 }
 
-// The whole launch sequence of a set of plans, in stage order.
-int enqueue(cs_ctx *ctx, std::vector<Plan> &plans, hipStream_t st) {
+// The whole launch sequence of a set of plans, in stage order.  `sel`
+// is caller storage for `count` plan pointers (the forward and adjoint
+// subsets); nothing is allocated here.
+int enqueue(cs_ctx *ctx, Plan *plans, int count, const Plan **sel, hipStream_t st) {
   int rc;
-  for (auto &P : plans) {
+  for (int i = 0; i < count; ++i) {
+    Plan &P = plans[i];
     if (P.ctf) {
       rc = launch_ctf_table(ctx, P, st);
       if (rc) return rc;
@@ -586,14 +635,15 @@ int enqueue(cs_ctx *ctx, std::vector<Plan> &plans, hipStream_t st) {
       if (rc) return rc;
     }
   }
-  std::vector<const Plan *> fw, bw;
-  for (auto &P : plans)
-    if (P.fwd) fw.push_back(&P);
-  if (!fw.empty()) {
-    rc = launch_persistent(ctx, true, fw, st);
+  int nsel = 0;
+  for (int i = 0; i < count; ++i)
+    if (plans[i].fwd) sel[nsel++] = &plans[i];
+  if (nsel) {
+    rc = launch_persistent(ctx, true, sel, nsel, st);
     if (rc) return rc;
   }
-  for (auto &P : plans) {
+  for (int i = 0; i < count; ++i) {
+    Plan &P = plans[i];
     if (P.mode == BACKWARD) continue;
     // pre-CTF image: the caller's buffer for a CTF-free render, else workspace
     float *Q = (P.mode == RENDER && !P.ctf) ? P.images : P.Q();
@@ -610,17 +660,23 @@ int enqueue(cs_ctx *ctx, std::vector<Plan> &plans, hipStream_t st) {
     }
     if (rc) return rc;
   }
-  for (auto &P : plans)
-    if (P.bwd) bw.push_back(&P);
-  if (!bw.empty()) {
-    rc = launch_persistent(ctx, false, bw, st);
+  nsel = 0;
+  for (int i = 0; i < count; ++i)
+    if (plans[i].bwd) sel[nsel++] = &plans[i];
+  if (nsel) {
+    rc = launch_persistent(ctx, false, sel, nsel, st);
     if (rc) return rc;
-    for (const Plan *P : bw) {
-      rc = launch_backward_finish(ctx, *P, st);
+    for (int i = 0; i < nsel; ++i) {
+      rc = launch_backward_finish(ctx, *sel[i], st);
       if (rc) return rc;
     }
   }
   return CS_OK;
+}
+
+int enqueue(cs_ctx *ctx, std::vector<Plan> &plans, hipStream_t st) {
+  std::vector<const Plan *> sel(plans.size());
+  return enqueue(ctx, plans.data(), (int)plans.size(), sel.data(), st);
 }
 
 // Workspace for all plans; assigns every plan its region and creates the
@@ -817,6 +873,9 @@ int cs_create(int device, cs_ctx **out) {
   const char *tf = std::getenv("CS_AUTOTUNE_CACHE");
   if (tf) c->tune_file = tf;
   load_tune_file(c);
+  // the static scratch's address on this device (cs_loss_and_grad_noalloc)
+  const hipError_t se = scratch_address(device, &c->scratch);
+  if (se != hipSuccess) c->scratch_err = hipGetErrorString(se);
   // allow canvases above 64 KiB of LDS
   (void)hipFuncSetAttribute((const void *)k_splat_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   (void)hipFuncSetAttribute((const void *)k_splat_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -923,6 +982,54 @@ int cs_loss_and_grad(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, cons
   if (grads) pr.grads = *grads;
   pr.images_out = images_out;
   return run_loss_problems(ctx, &pr, 1, opt && opt->graph, (hipStream_t)stream);
+}
+
+int cs_loss_and_grad_noalloc(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v,
+                             const cs_ctf *ctf, const cs_options *opt, const float *observed,
+                             int32_t reduction, float *loss, cs_grads *grads, float *images_out,
+                             void *stream) {
+  if (!ctx) return CS_ERR_INVALID_ARG;
+  if (!g || !v) return fail(ctx, CS_ERR_INVALID_ARG, "null gaussians or views");
+  cs_problem pr{};
+  pr.g = *g;
+  pr.v = *v;
+  pr.ctf = ctf;
+  if (opt) pr.opt = *opt;
+  pr.opt.graph = 0;
+  pr.observed = observed;
+  pr.reduction = reduction;
+  pr.loss = loss;
+  if (grads) pr.grads = *grads;
+  pr.images_out = images_out;
+  Plan P;
+  int rc = make_loss_plan(ctx, pr, P);
+  if (rc) return rc;
+  // scratch layout: [twiddle table][this call's workspace]
+  const size_t tw_bytes = ctf ? align_up(sizeof(float2) * (size_t)P.G.D) : 0;
+  const size_t need = tw_bytes + align_up(P.L.total);
+  if (need > kScratchBytes)
+    return fail(ctx, CS_ERR_OOM,
+                "cs_loss_and_grad_noalloc: this call needs %zu bytes of scratch; the static "
+                "scratch holds %zu (use cs_loss_and_grad)", need, kScratchBytes);
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!ctx->scratch)
+    return fail(ctx, CS_ERR_HIP, "static scratch unavailable on device %d: %s", ctx->device,
+                ctx->scratch_err.c_str());
+  hipStream_t st = (hipStream_t)stream;
+  P.ws = ctx->scratch + tw_bytes;
+  if (ctf) {
+    float2 *tw = (float2 *)ctx->scratch;
+    hipLaunchKernelGGL(k_twiddles, dim3(cdiv(P.G.D, 256)), dim3(256), 0, st, P.G.D, tw);
+    LAUNCHCHK("k_twiddles");
+    P.tw = tw;
+  }
+  // no stage timing here: its events would be allocations
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  const Plan *sel[1];
+  rc = enqueue(ctx, &P, 1, sel, st);
+  ctx->timing = timing;
+  return rc;
 }
 
 int cs_loss_and_grad_multi(cs_ctx *ctx, const cs_problem *problems, int32_t count,

@@ -45,6 +45,10 @@ struct cs_ctx {
   // or CS_DEBUG_CHECKS=1 in the environment at cs_create
   bool debug_checks = false;
   int *check_flag = nullptr;
+  // device address of the library's static scratch array on this context's
+  // device (cs_loss_and_grad_noalloc); null if the lookup at cs_create failed
+  char *scratch = nullptr;
+  std::string scratch_err;
 };
 
 namespace cs {

@@ -198,6 +198,8 @@ __global__ void k_fill(float *p, int64_t n, float value);
 
 __global__ void k_check_finite(const float *p, int64_t n, int bit, int *flag);
 
+__global__ void k_twiddles(int L, float2 *tw);
+
 __global__ void k_fft_rows_fwd(const float *src, FftPlan P, const float2 *tw, int B, float2 *spec);
 
 __global__ void k_ctf_table(int L, float pixel, CtfDev ctf, int B, float *table);

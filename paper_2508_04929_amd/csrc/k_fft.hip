@@ -7,7 +7,7 @@
 //             and the 1/D^2 normalisation, inverse FFT over rows
 //   rows:     inverse real FFT of every row (two rows packed again)
 // Every transform is a mixed-radix (4, 2, 3) Stockham FFT in LDS with
-// twiddles from a host-built FP64-accurate table.  Because H^ is real and
+// twiddles from an FP64-accurate table (k_twiddles).  Because H^ is real and
 // even, the same column pass is its own adjoint, so the loss gradient
 // G_Q = F^-1(H^ . F(G_X)) reuses the three passes; the row pass between the
 // two applications fuses the inverse rows of X, the residual X - Y, the
@@ -15,6 +15,16 @@
 #include "cs_ctf_dev.hpp"
 
 namespace cs {
+
+// Twiddle table of one transform length: tw[k] = exp(-2 pi i k / L),
+// evaluated in FP64 and rounded once to FP32.
+__global__ void __launch_bounds__(256) k_twiddles(int L, float2 *tw) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= L) return;
+  double sn, cn;
+  sincospi(2.0 * (double)k / (double)L, &sn, &cn);
+  tw[k] = make_float2((float)cn, (float)-sn);
+}
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
