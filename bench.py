@@ -27,12 +27,22 @@ METRIC = ("particle images/sec fwd+bwd (N=200k, D=256) and % roofline; "
           "pose-proposal speedup")
 Q_CUT = 27.631021115928547  # 2 ln 1e6, the library default
 
-# Nominal per-pair budget of the splat (one exp2 plus FMA-class ops) and the
-# chip rates it is priced at: 256 CUs at 2.4 GHz, transcendental at a
-# quarter of the 64-lane FP32 rate, FMA-class ops at the packed-FP32 rate.
+# Nominal per-pair budget of the splat (one exp2 plus FMA-class ops) priced
+# at chip rates: 256 CUs at 2.4 GHz, transcendental at a quarter of the
+# 64-lane FP32 rate, FMA-class ops at the packed-FP32 rate.  Reported as a
+# separately labelled ratio; the kernels evaluate no exp per pixel, so this
+# is a budget, not a ceiling.
 EXP_RATE = 256 * 16 * 2.4e9          # exp2 per second
 FMA_RATE = 256 * 128 * 2.4e9         # FP32 lane-ops per second (packed)
 PAIR_OPS = {"k_splat_fwd": 8, "k_splat_bwd": 20}
+# VALU issue ceiling: the published FP32 vector rate, 157.3 TFLOP/s = 256 CUs
+# x 128 lanes x 2 (FMA) x 2.4 GHz, i.e. two wave64 VALU instructions per CU
+# per cycle (the splat kernels are measured above one per CU per cycle, so
+# one is not a ceiling); a transcendental takes four issue slots.
+VALU_INSTR_RATE = 256 * 2 * 2.4e9    # wave64 VALU instructions per second
+TRANS_SLOTS = 4
+# LDS: 128 bytes per CU per cycle
+LDS_CYCLE_RATE = 256 * 2.4e9         # LDS cycles per second, all CUs
 
 
 def _source_digest(kernel: str) -> str:
@@ -45,23 +55,50 @@ def _source_digest(kernel: str) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, launches_per_step: int = 1):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size),
-    or None when the summary is missing or the kernel source has changed
-    since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "splat_hbm_traffic_c4.md")
+def _profile_record(name: str, tag: str):
+    """The `tag` JSON line of a committed rocprofv3 summary under profiles/,
+    or None when missing or taken on other splat sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = None
     with open(path) as fh:
         for line in fh:
-            if line.startswith("traffic-json: "):
-                rec = json.loads(line[len("traffic-json: "):])
-    if not rec or rec.get("source_sha1") != _source_digest(kernel):
+            if line.startswith(tag + ": "):
+                rec = json.loads(line[len(tag) + 2:])
+    if not rec or rec.get("source_sha1") != _source_digest(""):
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    return rec
+
+
+def measured_traffic(kernel: str, launches_per_step: int = 1):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy kernel of known size),
+    or None when the summary is missing or the kernel source has changed
+    since the counters were taken."""
+    rec = _profile_record("splat_hbm_traffic_c4.md", "traffic-json")
+    k = (rec or {}).get("kernels", {}).get(kernel)
     return None if k is None else float(k["bytes_per_launch"])
+
+
+def issue_ceiling(kernel: str):
+    """Hardware ceilings of a splat kernel from its committed instruction
+    counters (SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_LDS_IDX_ACTIVE per
+    launch, the launch's algorithmic pairs): pairs per second at the VALU
+    issue ceiling, and the LDS busy cycles per pair; None when missing or
+    stale."""
+    rec = _profile_record("splat_issue_counters_c4.md", "issue-json")
+    k = (rec or {}).get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    slots = k["valu_insts"] + (TRANS_SLOTS - 1) * k["trans_insts"]
+    out = {"valu_insts_per_pair": k["valu_insts"] / k["pairs"],
+           "valu_issue_slots_per_pair": slots / k["pairs"],
+           "pairs_per_s_at_issue_ceiling": VALU_INSTR_RATE * k["pairs"] / slots}
+    if k.get("lds_idx_active"):
+        out["lds_cycles_per_pair"] = k["lds_idx_active"] / k["pairs"]
+        out["pairs_per_s_at_lds_ceiling"] = LDS_CYCLE_RATE * k["pairs"] / k["lds_idx_active"]
+    return out
 
 
 def pair_peak(kernel: str) -> float:
@@ -240,17 +277,45 @@ def run(args):
     dom = max(("k_splat_fwd", "k_splat_bwd"), key=lambda k: stages.get(k, {}).get("ms_total", 0))
     d = stages[dom]
     achieved = pairs_step / (d["ms_per_launch"] * 1e-3)     # pairs per second
-    peak = pair_peak(dom)
-    roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9, "peak": peak / 1e9,
-            "unit": "Gpair/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
-            "pairs_per_launch": pairs_step,
-            "ms_per_launch": d["ms_per_launch"]}
+
+    def ceilings(kernel, ach):
+        """(peak pairs/s, ceiling record): the lower of the VALU issue and LDS
+        ceilings from the committed counters, None without them."""
+        c = issue_ceiling(kernel)
+        if c is None:
+            return None, None
+        peaks = {"valu_issue": c["pairs_per_s_at_issue_ceiling"]}
+        if "pairs_per_s_at_lds_ceiling" in c:
+            peaks["lds"] = c["pairs_per_s_at_lds_ceiling"]
+        limit = min(peaks, key=peaks.get)
+        c["binding"] = limit
+        c["frac_of_valu_issue"] = ach / peaks["valu_issue"]
+        if "lds" in peaks:
+            c["frac_of_lds"] = ach / peaks["lds"]
+        return peaks[limit], c
+
+    peak, ceil_rec = ceilings(dom, achieved)
+    nominal = pair_peak(dom)
+    roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e9,
+            "peak": None if peak is None else peak / 1e9, "unit": "Gpair/s",
+            "frac": None if peak is None else achieved / peak,
+            "traffic": measured_traffic(dom), "pairs_per_launch": pairs_step,
+            "ms_per_launch": d["ms_per_launch"], "ceiling": ceil_rec,
+            "nominal_budget": {"peak": nominal / 1e9, "frac": achieved / nominal,
+                               "note": "1 exp2 + FMA-class ops per pair at datasheet rates; "
+                                       "a budget, not a ceiling"}}
     other = "k_splat_bwd" if dom == "k_splat_fwd" else "k_splat_fwd"
     if other in stages:
         o = stages[other]
         ach_o = pairs_step / (o["ms_per_launch"] * 1e-3)
+        peak_o, ceil_o = ceilings(other, ach_o)
         roof["other_splat"] = {"kernel": other, "achieved": ach_o / 1e9,
-                               "peak": pair_peak(other) / 1e9, "frac": ach_o / pair_peak(other)}
+                               "peak": None if peak_o is None else peak_o / 1e9,
+                               "frac": None if peak_o is None else ach_o / peak_o,
+                               "ceiling": ceil_o, "ms_per_launch": o["ms_per_launch"],
+                               "traffic": measured_traffic(other),
+                               "nominal_budget": {"peak": pair_peak(other) / 1e9,
+                                                  "frac": ach_o / pair_peak(other)}}
     step_roof_s = pairs_step * (1 / pair_peak("k_splat_fwd") + 1 / pair_peak("k_splat_bwd"))
     result = {
         "metric": METRIC, "value": value, "unit": "images/s", "n_gpus": 1,
@@ -585,6 +650,7 @@ def main():
             "speedup_vs_grid_search": r["speedup_vs_grid_search"],
             "reaches_grid_search_error": r["reaches_grid_search_error"],
             "speedup_same_batch": r.get("speedup_same_batch"),
+            "learned_fallback": r.get("learned_fallback"),
             "grid_search": r["grid_search"], "learned": r["learned"],
             "untrained": r["untrained"], "training": r["training"],
             "literal_grid_search_images_per_s": r.get("literal_grid_search_images_per_s"),

@@ -480,6 +480,22 @@ int cs_pose_batch_refine(cs_pose_bank *bank, cs_pose_batch *batch, const float *
                          int32_t *best_shift, float *best_score, float *scores,
                          float *best_rotation, void *stream);
 
+/* Fit of each loaded particle's winning pose (outputs of a search or
+ * refinement on this batch): z[p] = (||Y||^2 - best_score[p]) / ||H Q_k||^2
+ * with k = best_rot[p], which equals 2 a - 1 for a = <S_t Q_k, H Y> /
+ * ||H Q_k||^2, the least-squares amplitude of the winning template in the
+ * particle (Sec. 3.3.5 squared error expanded as for the scores).  Near 1
+ * when the template at the winning pose explains the particle, lower when
+ * it does not; a learned proposal uses it to send particles back to the
+ * exhaustive search.  sigmas (may be NULL) receives the shortfall from a
+ * perfect fit in units of the noise spread of z at the true pose of a
+ * noise-dominated particle: s = (1 - z) ||H Q_k|| D / (2 ||Y||) (the spread
+ * of z is 2 sigma / ||H Q_k|| with sigma^2 about ||Y||^2 / D^2).  NaN where
+ * best_rot is outside the bank.  Device arrays [P] (P = the batch's last
+ * load). */
+int cs_pose_batch_confidence(cs_pose_bank *bank, cs_pose_batch *batch, const int32_t *best_rot,
+                             const float *best_score, float *z, float *sigmas, void *stream);
+
 /* The mixture read out as a volume (the voxelisation of the reconstruction
  * in the overview of Sec. 3): vol [D][D][D] (index [iz][iy][ix]) receives
  * sum_n A_n (2 pi)^-3/2 det(Sigma_n)^-1/2 exp(-q_n / 2) at (x, y, z) =

@@ -128,6 +128,23 @@ def scores_at(g, Y, particle, rotations, shifts_px, q_cut=None, use_ctf=True):
     return np.sum((X - np.asarray(Y, dtype=np.float64)[None]) ** 2, axis=(1, 2))
 
 
+def fit_statistic(g, Y, particle, rotation, shift_px, q_cut=None, use_ctf=True):
+    """Fit of one particle Y to the template at one pose (rotation [3][3],
+    shift [2] pixels), from the squared error of Sec. 3.3.5:
+        z = (||Y||^2 - score) / ||X||^2,  X = the CTF-modulated render,
+    which expands to 2 <X, Y> / ||X||^2 - 1 = 2 a - 1 with a the
+    least-squares amplitude of X in Y."""
+    rot = np.asarray(rotation, dtype=np.float64)[None]
+    shift = np.asarray(shift_px, dtype=np.float64)[None] * float(particle.pixel)
+    X = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, rot, shift, particle.D,
+                             particle.pixel, q_cut)
+    if use_ctf:
+        X = ctf_mod.apply_ctf(X, ctf_mod.ctf_grid_for(particle)[0])
+    Y = np.asarray(Y, dtype=np.float64)
+    score = np.sum((X[0] - Y) ** 2)
+    return (np.sum(Y ** 2) - score) / np.sum(X[0] ** 2)
+
+
 # ---------------------------------------------------------------- refinement
 
 def refine_candidates(proposal, bank_rot, n_psi, n_dir, n_psi_c):

@@ -89,7 +89,8 @@ EXPORTS = ("cs_create", "cs_destroy", "cs_last_error", "cs_render", "cs_render_b
            "cs_pose_head", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_destroy",
            "cs_pose_bank_size", "cs_pose_bank_rotations", "cs_pose_grid_search", "cs_pose_refine", "cs_add_noise", "cs_cnn_tensor",
            "cs_pose_batch_create", "cs_pose_batch_destroy", "cs_pose_batch_load",
-           "cs_pose_batch_search", "cs_pose_batch_refine", "cs_ctf_filter",
+           "cs_pose_batch_search", "cs_pose_batch_refine", "cs_pose_batch_confidence",
+           "cs_ctf_filter",
            "cs_voxelize", "cs_fsc", "cs_fsc_resolution", "cs_fourier_shift",
            "cs_init_attributes", "cs_train_sequential", "cs_split_gaussians")
 
@@ -191,9 +192,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                         P(CsOptions), i32, vp, i64, i64, f32, f32, f32, f32, vp,
                                         vp]
     lib.cs_pose_batch_refine.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.cs_pose_batch_confidence.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.cs_ctf_filter.argtypes = [vp, vp, P(CsCtf), i32, i32, f32, vp, vp]
     for name in ("cs_pose_batch_create", "cs_pose_batch_load", "cs_pose_batch_search",
-                 "cs_pose_batch_refine", "cs_ctf_filter", "cs_voxelize", "cs_fsc",
+                 "cs_pose_batch_refine", "cs_pose_batch_confidence", "cs_ctf_filter",
+                 "cs_voxelize", "cs_fsc",
                  "cs_fsc_resolution", "cs_fourier_shift", "cs_init_attributes", "cs_train_sequential",
                  "cs_split_gaussians", "cs_cnn_tensor", "cs_add_noise", "cs_pose_grid", "cs_pose_bank_create", "cs_pose_bank_rotations",
                  "cs_pose_grid_search", "cs_pose_refine"):
@@ -1008,6 +1011,27 @@ class PoseBatch:
             out["rot_idx"].data_ptr(), out["shift_idx"].data_ptr(), out["score"].data_ptr(),
             PoseBank._p(out["scores"]), out["rot"].data_ptr(), self._s()), "cs_pose_batch_refine")
         return out
+
+
+    def confidence(self, bank: "PoseBank", out, z=None, sigmas=None, want_sigmas=False):
+        """Fit statistic z [P] of the winning poses in `out` (a search or
+        refinement result of this batch on `bank`): 2 a - 1 with a the
+        least-squares amplitude of the winning template in the particle.
+        With want_sigmas (or a sigmas tensor) also the shortfall (1 - z) in
+        units of z's noise spread; returns (z, sigmas) then."""
+        P = self.P
+        _ptr(out["rot_idx"], "rot_idx", self.device, (P,), torch.int32)
+        _ptr(out["score"], "score", self.device, (P,))
+        if z is None:
+            z = torch.empty(P, device=self.device)
+        _ptr(z, "z", self.device, (P,))
+        if sigmas is None and want_sigmas:
+            sigmas = torch.empty(P, device=self.device)
+        _ptr(sigmas, "sigmas", self.device, (P,))
+        self.owner._check(self.ctx, self.lib.cs_pose_batch_confidence(
+            bank.h, self.h, out["rot_idx"].data_ptr(), out["score"].data_ptr(), z.data_ptr(),
+            PoseBank._p(sigmas), self._s()), "cs_pose_batch_confidence")
+        return (z, sigmas) if sigmas is not None else z
 
 
 class Network:

@@ -119,7 +119,7 @@ enum Mode { RENDER, BACKWARD, LOSS };
 struct Layout {
   size_t gc = 0, key = 0, count = 0, off = 0, blk = 0, item_off = 0, n_items = 0, queues = 0,
          items = 0, list = 0, partials = 0, Q = 0, spec = 0, ctf = 0, mom = 0, loss_part = 0,
-         pose_part = 0;
+         pose_part = 0, wabs = 0;
   size_t total = 0;
   int max_items = 0;
   int nbx = 0;  // Gaussian blocks of the binning kernels
@@ -171,6 +171,7 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
   L.queues = take(16);
   L.items = take((size_t)L.max_items * 16 + 16);
   L.list = take(BN * 32 + 32);
+  L.wabs = take(BN * 4 + 16);
   if (need_partials) L.partials = take((size_t)L.max_items * G.C * G.C * 4);
   L.Q = take((size_t)G.B * G.D * G.D * 4);
   if (need_fft) {
@@ -365,7 +366,7 @@ int launch_binning(cs_ctx *ctx, const Plan &P, hipStream_t st) {
           (int *)(ws + L.queues), fuse ? (int *)(ws + L.blk) : (int *)nullptr, L.nbx);
   TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), (size_t)(kBlock / 64) * G.K * 4, st, gc, P.v.rot,
           P.v.shift, G, (const int *)(ws + L.key), (const int *)(ws + L.off),
-          (const int *)(ws + L.blk), L.nbx, (float4 *)(ws + L.list));
+          (const int *)(ws + L.blk), L.nbx, (float4 *)(ws + L.list), (float *)(ws + L.wabs));
   return CS_OK;
 }
 
@@ -383,6 +384,7 @@ ProbDev prob_dev(const Plan &P) {
   d.list = (const float4 *)(P.ws + P.L.list);
   d.items = (const int4 *)(P.ws + P.L.items);
   d.n_items = (const int *)(P.ws + P.L.n_items);
+  d.wabs = (const float *)(P.ws + P.L.wabs);
   d.queue = (int *)(P.ws + P.L.queues);
   d.partials = (float *)(P.ws + P.L.partials);
   d.GQ = P.GQ();

@@ -57,6 +57,7 @@ struct ProbDev {
   const float4 *list;   // splat records
   const int4 *items;    // work items
   const int *n_items;   // [0] item count, [1] wide-record count
+  const float *wabs;    // |w| of every record, in list order
   int *queue;           // [0] forward, [1] backward work-queue counter
   float *partials;      // forward partial canvases
   const float *GQ;      // dL/dQ (backward)
@@ -162,7 +163,7 @@ __global__ void k_scan(int *count, Geom G, int *off, int4 *items, int *item_off,
 
 __global__ void k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G,
                               const int *key, const int *off, const int *blk, int nbx,
-                              float4 *list);
+                              float4 *list, float *wabs);
 
 __global__ void k_splat_fwd(MultiProb MP);
 

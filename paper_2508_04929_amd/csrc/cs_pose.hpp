@@ -67,6 +67,10 @@ hipError_t fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipS
 hipError_t fill_u16(unsigned short *p, int64_t n, hipStream_t st);
 hipError_t pose_decode(const unsigned long long *best, int P, int S, int *rot_idx, int *shift_idx,
                        float *score, const float *bank_rot, float *rot_out, hipStream_t st);
+hipError_t pose_confidence(const unsigned short *bank, int64_t ldb, int64_t boff, int64_t K,
+                           const unsigned short *w, int F8, int D, const float *yy,
+                           const int *rot_idx, const float *score, int P, float *z, float *sig,
+                           hipStream_t st);
 hipError_t pose_gemm_store(const PoseGemmArgs &a, hipStream_t st);
 hipError_t pose_gemm_score(const PoseGemmArgs &a, hipStream_t st);
 hipError_t pose_gemm_refine(const PoseGemmArgs &a, int P, hipStream_t st);

@@ -251,7 +251,7 @@ k_scan(int *count, Geom G, int *off, int4 *items, int *item_off, int *n_items,
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, const int *key,
-              const int *off, const int *blk, int nbx, float4 *list) {
+              const int *off, const int *blk, int nbx, float4 *list, float *wabs) {
   extern __shared__ int wcnt[];  // [kBlock/64][K] per-wave bin counts
   const int n = blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -294,6 +294,9 @@ k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, co
       list[2 * (size_t)pos] = make_float4(P.u, P.v, P.al, P.be);
       list[2 * (size_t)pos + 1] =
           make_float4(P.ga, P.w, __int_as_float(n), __int_as_float(i0 | (i1 << 16)));
+      // |w| beside the record, in list order: the forward splat sums it per
+      // work item for its fixed-point scale without reading the records twice
+      wabs[pos] = fabsf(P.w);
     }
     __syncthreads();
   }

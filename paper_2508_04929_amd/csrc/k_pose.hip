@@ -165,6 +165,43 @@ k_pose_decode(const unsigned long long *best, int P, int S, int *rot_idx, int *s
   }
 }
 
+// Fit statistic of each particle's winning pose (block = particle):
+//   E = ||H Q_k||^2 = sum_f w[p][f] |Q^_k(f)|^2   (same bfloat16 operands
+//       and Parseval weights as the scores), k = rot_idx[p]
+//   z = (||Y||^2 - score) / E = 2 <S_t Q_k, H Y> / ||H Q_k||^2 - 1,
+// i.e. 2 a - 1 with a the least-squares amplitude of the winning template
+// in the particle; and (optional) its shortfall from a perfect fit in units
+// of the noise spread of z at the true pose of a noise-dominated particle,
+//   s = (1 - z) sqrt(E) D / (2 ||Y||)     (std of z = 2 sigma / ||H Q_k||,
+//                                           sigma^2 ~ ||Y||^2 / D^2).
+// NaN where no rotation won or E is not positive.
+__global__ void __launch_bounds__(256)
+k_pose_confidence(const unsigned short *bank, int64_t ldb, int64_t boff, int64_t K,
+                  const unsigned short *w, int F8, int D, const float *yy, const int *rot_idx,
+                  const float *score, float *z, float *sig) {
+  const int p = blockIdx.x;
+  const int k = rot_idx[p];
+  __shared__ float red[4];
+  float acc = 0.f;
+  if (k >= 0 && k < K) {
+    const unsigned short *q = bank + (size_t)k * ldb + boff;
+    const unsigned short *wp = w + (size_t)p * F8;
+    for (int f = threadIdx.x; f < F8; f += 256) acc += pbf2f(wp[f]) * pbf2f(q[f]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float E = (red[0] + red[1]) + (red[2] + red[3]);
+    const bool ok = k >= 0 && k < K && E > 0.f;
+    const float zp = ok ? (yy[p] - score[p]) / E : __int_as_float(0x7fc00000);
+    z[p] = zp;
+    if (sig) sig[p] = ok && yy[p] > 0.f ? (1.f - zp) * sqrtf(E) * (float)D / (2.f * sqrtf(yy[p]))
+                                       : __int_as_float(0x7fc00000);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // TN GEMM on MFMA: C[m][n] = sum_k A[m][k] B[n][k], bfloat16 operands with
 // K contiguous, FP32 accumulation (v_mfma_f32_16x16x32_bf16), K a multiple
@@ -666,6 +703,15 @@ hipError_t pose_decode(const unsigned long long *best, int P, int S, int *rot_id
                        float *score, const float *bank_rot, float *rot_out, hipStream_t st) {
   hipLaunchKernelGGL(k_pose_decode, dim3(pcdiv(P, 256)), dim3(256), 0, st, best, P, S, rot_idx,
                      shift_idx, score, bank_rot, rot_out);
+  return hipGetLastError();
+}
+
+hipError_t pose_confidence(const unsigned short *bank, int64_t ldb, int64_t boff, int64_t K,
+                           const unsigned short *w, int F8, int D, const float *yy,
+                           const int *rot_idx, const float *score, int P, float *z, float *sig,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_pose_confidence, dim3(P), dim3(256), 0, st, bank, ldb, boff, K, w, F8, D, yy,
+                     rot_idx, score, z, sig);
   return hipGetLastError();
 }
 

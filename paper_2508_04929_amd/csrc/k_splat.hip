@@ -21,30 +21,33 @@
 
 namespace cs {
 
-struct Span {
-  int j0, j1;
-  float di;
-};
-
 // Hardware exp2/sqrt (v_exp_f32 / v_sqrt_f32, about 1 ulp; results below
 // 2^-126 flush to zero, far under the 1e-6 truncation of every term).
 __device__ __forceinline__ float hexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float hsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Exact column span of row i for the ellipse q <= q_cut, clipped to
-// [clo, chi].  Returns false for an empty row.
-__device__ __forceinline__ bool row_span(float u, float v, float al, float be, float det_s,
-                                         float inv_al, float qk, int i, int clo, int chi,
-                                         Span &s) {
-  const float di = (float)i - v;
-  const float disc = al * qk - det_s * di * di;
+// Exact column span of the row at vertical offset di = i - v for the
+// ellipse q <= q_cut, clipped to [clo, chi]: first column j0 and length L
+// (false for an empty row).  aqk = al * qk.  The span ends are converted to
+// integers before clamping (finite here: al > 0 and the record fits its
+// canvas).
+__device__ __forceinline__ bool row_span(float u, float di, float al, float be, float det_s,
+                                         float inv_al, float aqk, int clo, int chi, int &j0,
+                                         int &L) {
+  const float disc = aqk - det_s * di * di;
   if (!(disc >= 0.f)) return false;
   const float h = hsqrt(disc) * inv_al;
   const float cen = u - be * di * inv_al;
-  s.j0 = clamp_px(ceilf(cen - h), clo, chi + 1);
-  s.j1 = clamp_px(floorf(cen + h), clo - 1, chi);
-  s.di = di;
-  return s.j0 <= s.j1;
+  j0 = max((int)ceilf(cen - h), clo);
+  L = min((int)floorf(cen + h), chi) - j0 + 1;
+  return L > 0;
+}
+
+// Row of flat index x in rows of length n: x / n through a float reciprocal
+// (exact while x < 2^20 and n <= 1024: the quotient (x + 1/2) / n stays at
+// least 1 / (2 n) away from an integer, far above the rounding error).
+__device__ __forceinline__ int row_of(int x, float inv_n) {
+  return (int)(((float)x + 0.5f) * inv_n);
 }
 
 __device__ __forceinline__ int next_item(int *queue, int *slot) {
@@ -57,7 +60,8 @@ __device__ __forceinline__ int next_item(int *queue, int *slot) {
 // Forward: partial canvas of one work item.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
-  extern __shared__ int icanvas[];  // C rows of stride S (fixed point)
+  extern __shared__ int4 smem4[];     // 16-byte aligned dynamic LDS
+  int *icanvas = (int *)smem4;        // C rows of stride S (fixed point)
   __shared__ int slot;
   __shared__ float wsum[kBlock / 64];
   // drain the problems' queues in order: blocks that find one exhausted move on
@@ -72,11 +76,14 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
   for (;;) {
     const int it = next_item(queue, &slot);
     if (it >= nitems) break;
-    for (int i = threadIdx.x; i < CS; i += kBlock) icanvas[i] = 0;
+    for (int i = threadIdx.x; i < CS / 4; i += kBlock) smem4[i] = make_int4(0, 0, 0, 0);
+    for (int i = (CS & ~3) + threadIdx.x; i < CS; i += kBlock) icanvas[i] = 0;
     const int4 itm = items[it];
-    // fixed-point scale: 2^e with 2^e * sum|w| <= 2^30
+    // fixed-point scale: 2^e with 2^e * sum|w| <= 2^30 (the item's |w| are
+    // contiguous beside the list, summed in a fixed order)
+    const float *wa = MP.p[p].wabs + itm.z;
     float aw = 0.f;
-    for (int g = threadIdx.x; g < itm.w; g += kBlock) aw += fabsf(list[2 * (size_t)(itm.z + g) + 1].y);
+    for (int g = threadIdx.x; g < itm.w; g += kBlock) aw += wa[g];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) aw += __shfl_xor(aw, o, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = aw;
@@ -92,6 +99,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
     const int R0 = ty * G.T - G.halo, C0 = tx * G.T - G.halo;
     const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
     const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
+    __syncthreads();  // canvas cleared
     for (int g = threadIdx.x; g < itm.w; g += kBlock) {
       const size_t rec = 2 * (size_t)(itm.z + g);
       const float4 r0 = list[rec], r1 = list[rec + 1];
@@ -100,15 +108,18 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
       const int i0 = max(rows & 0xffff, rlo), i1 = min(rows >> 16, rhi);
       const float det_s = al * ga - be * be;
       const float inv_al = 1.f / al;
+      const float aqk = al * G.qk;
       const float K = hexp2(-2.f * al);
-      for (int i = i0; i <= i1; ++i) {
-        Span s;
-        if (!row_span(u, v, al, be, det_s, inv_al, G.qk, i, clo, chi, s)) continue;
-        const float dj = (float)s.j0 - u;
-        float e = w * hexp2(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
-        float r = hexp2(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
-        int *px = icanvas + (i - R0) * G.S + (s.j0 - C0);
-        const int L = s.j1 - s.j0 + 1;
+      float fi = (float)i0;
+      int rowo = (i0 - R0) * G.S - C0;  // canvas offset of (row i, column 0)
+      for (int i = i0; i <= i1; ++i, fi += 1.f, rowo += G.S) {
+        const float di = fi - v;
+        int j0, L;
+        if (!row_span(u, di, al, be, det_s, inv_al, aqk, clo, chi, j0, L)) continue;
+        const float dj = (float)j0 - u;
+        float e = w * hexp2(-(al * dj * dj + 2.f * be * dj * di + ga * di * di));
+        float r = hexp2(-(al * (2.f * dj + 1.f) + 2.f * be * di));
+        int *px = icanvas + rowo + j0;
         const int L4 = L & ~3;
         int k = 0;
         for (; k < L4; k += 4) {
@@ -121,17 +132,21 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
           atomicAdd(px + k + 2, v2);
           atomicAdd(px + k + 3, v3);
         }
-        for (; k < L; ++k) {
-          atomicAdd(px + k, __float2int_rn(e));
-          e *= r;
-          r *= K;
+        if (k < L) {  // 1 to 3 trailing pixels
+          const int v0 = __float2int_rn(e); e *= r; r *= K;
+          const int v1 = __float2int_rn(e); e *= r;
+          const int v2 = __float2int_rn(e);
+          atomicAdd(px + k, v0);
+          if (k + 1 < L) atomicAdd(px + k + 1, v1);
+          if (k + 2 < L) atomicAdd(px + k + 2, v2);
         }
       }
     }
     __syncthreads();
     float *out = partials + (size_t)it * G.C * G.C;
+    const float inv_c = 1.f / (float)G.C;
     for (int i = threadIdx.x; i < G.C * G.C; i += kBlock) {
-      const int r = i / G.C, c = i - r * G.C;
+      const int r = row_of(i, inv_c), c = i - r * G.C;
       out[i] = (float)icanvas[r * G.S + c] * inv_scale;
     }
     __syncthreads();
@@ -269,8 +284,9 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
     const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
     const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
     const float *src = GQ + (size_t)b * G.D * G.D;
+    const float inv_s = 1.f / (float)G.S;
     for (int q = threadIdx.x; q < G.C * G.S; q += kBlock) {
-      const int r = q / G.S, c = q - r * G.S;
+      const int r = row_of(q, inv_s), c = q - r * G.S;
       const int i = R0 + r, j = C0 + c;
       gq[q] = (c < G.C && i >= 0 && i < G.D && j >= 0 && j < G.D) ? src[(size_t)i * G.D + j] : 0.f;
     }
@@ -284,18 +300,22 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
       const int i0 = max(rows & 0xffff, rlo), i1 = min(rows >> 16, rhi);
       const float det_s = al * ga - be * be;
       const float inv_al = 1.f / al;
+      const float aqk = al * G.qk;
       const float K = hexp2(-2.f * al);
       float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f;
-      for (int i = i0; i <= i1; ++i) {
-        Span s;
-        if (!row_span(u, v, al, be, det_s, inv_al, G.qk, i, clo, chi, s)) continue;
-        const float dj = (float)s.j0 - u;
-        float e = hexp2(-(al * dj * dj + 2.f * be * dj * s.di + ga * s.di * s.di));
-        float r = hexp2(-(al * (2.f * dj + 1.f) + 2.f * be * s.di));
-        const float *px = gq + (i - R0) * G.S + (s.j0 - C0);
-        const int L = s.j1 - s.j0 + 1;
-        // Prefix-sum moments over t_k = G_Q e, k = 0 .. L-1:
-        //   a0 = sum t_k, a1 = sum t_k (L-k), a2 = sum t_k (L-k)(L-k+1)/2
+      float fi = (float)i0;
+      int rowo = (i0 - R0) * G.S - C0;  // canvas offset of (row i, column 0)
+      for (int i = i0; i <= i1; ++i, fi += 1.f, rowo += G.S) {
+        const float di = fi - v;
+        int j0, L;
+        if (!row_span(u, di, al, be, det_s, inv_al, aqk, clo, chi, j0, L)) continue;
+        const float dj = (float)j0 - u;
+        float e = hexp2(-(al * dj * dj + 2.f * be * dj * di + ga * di * di));
+        float r = hexp2(-(al * (2.f * dj + 1.f) + 2.f * be * di));
+        const float *px = gq + rowo + j0;
+        // Prefix-sum moments over t_k = G_Q e, k = 0 .. M-1 (M steps, t_k = 0
+        // for k >= L):
+        //   a0 = sum t_k, a1 = sum t_k (M-k), a2 = sum t_k (M-k)(M-k+1)/2
         float a0 = 0.f, a1 = 0.f, a2 = 0.f;
         const int L4 = L & ~3;
         int k = 0;
@@ -310,22 +330,32 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
           t = g3 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
         }
-        for (; k < L; ++k) {
-          const float t = px[k] * e;
-          e *= r;
-          r *= K;
+        int M = L4;
+        if (k < L) {
+          // 1 to 3 trailing pixels as three steps with G_Q = 0 past the span
+          // (the reads stay inside the row: spans end at column C - 1 of a
+          // row of stride C + 4)
+          const float g0 = px[k];
+          const float g1 = k + 1 < L ? px[k + 1] : 0.f;
+          const float g2 = k + 2 < L ? px[k + 2] : 0.f;
+          float t = g0 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
+          t = g1 * e; e *= r;
+          a0 += t; a1 += a0; a2 += a1;
+          t = g2 * e;
+          a0 += t; a1 += a0; a2 += a1;
+          M = L4 + 3;
         }
-        // sum t dj = c a0 - a1, sum t dj^2 = c^2 a0 - 2 c a1 + 2 a2 - a1, c = dj0 + L
-        const float c = dj + (float)L;
+        // sum t dj = c a0 - a1, sum t dj^2 = c^2 a0 - 2 c a1 + 2 a2 - a1, c = dj0 + M
+        const float c = dj + (float)M;
         const float sdj = c * a0 - a1;
-        const float sdj2 = c * c * a0 - 2.f * c * a1 + 2.f * a2 - a1;
+        const float sdj2 = c * (c * a0 - 2.f * a1) + 2.f * a2 - a1;
         m0 += a0;
         m1 += sdj;
-        m2 += a0 * s.di;
+        m2 += a0 * di;
         m3 += sdj2;
-        m4 += sdj * s.di;
-        m5 += a0 * s.di * s.di;
+        m4 += sdj * di;
+        m5 += a0 * di * di;
       }
       float *o = mom + ((size_t)b * G.N + n) * 6;
       o[0] = m0; o[1] = m1; o[2] = m2; o[3] = m3; o[4] = m4; o[5] = m5;

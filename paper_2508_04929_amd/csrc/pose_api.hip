@@ -452,6 +452,19 @@ int cs_pose_batch_refine(cs_pose_bank *b, cs_pose_batch *q, const float *proposa
   return CS_OK;
 }
 
+int cs_pose_batch_confidence(cs_pose_bank *b, cs_pose_batch *q, const int32_t *best_rot,
+                             const float *best_score, float *z, float *sigmas, void *stream) {
+  if (!q) return CS_ERR_INVALID_ARG;
+  cs_ctx *ctx = q->ctx;
+  int rc = check_batch(ctx, b, q);
+  if (rc) return rc;
+  if (!best_rot || !best_score || !z) return fail(ctx, CS_ERR_INVALID_ARG, "null argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(pose_confidence(b->data, b->Kext, b->npx, b->K, q->w, q->F8, q->D, q->yy, best_rot,
+                         best_score, q->P, z, sigmas, (hipStream_t)stream));
+  return CS_OK;
+}
+
 // Convenience forms on raw images: chunks through a batch owned by the bank.
 static int bank_batch(cs_pose_bank *b, int r, cs_pose_batch **q) {
   cs_ctx *ctx = b->ctx;

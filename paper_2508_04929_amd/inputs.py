@@ -260,3 +260,11 @@ def c5(seed: int = 5, n_train: int = 200000, n_test: int = 2048, n: int = 20000,
     train = pose_views(rtr, n_train, D, 1.5)
     test = pose_views(rte, n_test, D, 1.5)
     return g, train, test
+
+
+def c5_validation(seed: int = 5, n_val: int = 2048, D: int = 128):
+    """Held-out validation particles of the learned-pose workload (a fourth
+    stream of the same seed; the mixture, training and test draws of c5 are
+    unchanged): same pose, shift and defocus distributions."""
+    rva = streams(seed, 4)[3]
+    return pose_views(rva, n_val, D, 1.5)

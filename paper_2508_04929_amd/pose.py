@@ -12,8 +12,14 @@ Pipeline of the learned path for a batch of particles:
      the current estimate (nearest bank directions x in-plane angles x
      (2r+1)^2 shifts) with the renderer's squared-error score; the best
      candidate seeds the next stage.
+  3. fit statistics of the final pose: z = 2 a - 1 (a the least-squares
+     amplitude of the winning template in the particle) and its shortfall
+     from a perfect fit in units of its noise spread; particles whose
+     statistic falls past a threshold go back to the exhaustive grid search.
 The exhaustive grid search over the coarse bank is the fallback and the
-judge of angular error.
+judge of angular error.  The threshold is calibrated on held-out
+validation particles: the smallest fallback fraction whose mean angular
+error comes within a margin of the grid search's on the same particles.
 """
 from __future__ import annotations
 
@@ -125,7 +131,50 @@ def learned_poses(lib, net: binding.Network, batch: binding.PoseBatch, images, c
     for st in stages:
         out = batch.refine(st.bank, proposal=W, n_dir=st.n_dir, n_psi_c=st.n_psi_c)
         W = out["rot"]
-    return W, (out["shift_idx"] if out is not None else None), W0
+    z, sig = (batch.confidence(stages[-1].bank, out, want_sigmas=True) if stages
+              else (None, None))
+    return W, (out["shift_idx"] if out is not None else None), W0, z, sig
+
+
+def fallback_search(batch: binding.PoseBatch, bank: binding.PoseBank, images, ps: "PoseSet",
+                    W: torch.Tensor, z: torch.Tensor, tau: float, chunk: int) -> int:
+    """Exhaustive search (in batches of `chunk`) of the particles whose fit
+    statistic is below tau (or undefined); their rows of W are replaced by
+    the grid-search rotations.  Returns the number of particles searched."""
+    idx = torch.nonzero(~(z >= tau)).flatten()
+    n = int(idx.numel())
+    for a in range(0, n, chunk):
+        sel = idx[a:a + chunk]
+        ctf = binding.Ctf(defocus_u=ps.defocus.index_select(0, sel),
+                          defocus_v=ps.defocus.index_select(0, sel),
+                          astig=ps.zeros.index_select(0, sel), phase=ps.zeros.index_select(0, sel))
+        batch.load(images.index_select(0, sel).contiguous(), ctf)
+        W.index_copy_(0, sel, batch.search(bank)["rot"])
+    return n
+
+
+def calibrate_threshold(z: np.ndarray, err_learned: np.ndarray, err_grid: np.ndarray,
+                        margin_deg: float = 0.5) -> Tuple[float, float]:
+    """Smallest fallback set (the lowest-z particles) whose mean angular
+    error, with those particles taking their grid-search error, is within
+    margin_deg of the grid search's mean.  Returns (threshold, fraction):
+    particles with z < threshold fall back."""
+    z = np.where(np.isfinite(z), z, -np.inf)
+    order = np.argsort(z, kind="stable")
+    n = len(z)
+    target = err_grid.mean() + margin_deg
+    total = err_learned.sum()
+    for k in range(n + 1):
+        if total / n <= target:
+            if k == 0:
+                return float(z[order[0]]) if n else 0.0, 0.0
+            hi = z[order[k]] if k < n else np.inf
+            lo = z[order[k - 1]]
+            return float(0.5 * (lo + hi)) if np.isfinite(hi) else float("inf"), k / n
+        if k < n:
+            j = order[k]
+            total += err_grid[j] - err_learned[j]
+    return float("inf"), 1.0
 
 
 def grid_poses(batch: binding.PoseBatch, bank: binding.PoseBank, images, ctf: binding.Ctf):
@@ -200,7 +249,8 @@ def literal_grid_search(lib, gd, image, ctf_one: binding.Ctf, grid_rot: torch.Te
 def run_c5(lib, *, n_train=200000, n_test=8192, epochs=12, batch=256, lr=1e-3, gamma=0.85,
            lam=0.1, snr_db=-20.0, seed=5, coarse=(4, 24), fine=(8, 48), shift_radius=2,
            stages=((0, 6, 2), (1, 4, 2)), matched_filter=True, chunks=(2048, 4096, 8192),
-           literal_particles=2, stage_sweep=(), use_graphs=True, log=print):
+           literal_particles=2, stage_sweep=(), use_graphs=True, n_val=2048,
+           fallback_margin_deg=1.0, log=print):
     """The learned-pose experiment: returns angular errors and throughputs.
 
     stages: (bank 0 = coarse / 1 = fine, n_dir, n_psi_c) per refinement stage;
@@ -269,17 +319,19 @@ def run_c5(lib, *, n_train=200000, n_test=8192, epochs=12, batch=256, lr=1e-3, g
     st = [Stage(banks[b], nd, npc) for b, nd, npc in stages]
     net = lib.network(D, max_batch=max(batch, max(chunks)), seed=seed)
 
-    def learned(st=st, c=chunk):
-        Ws, W0s = [], []
-        for a in range(0, n_test, c):
-            b = min(n_test, a + c)
-            W, _, W0 = learned_poses(lib, net, pbs[c], imgs[a:b], ps_te.ctf(a, b), st,
-                                     xbuf[:b - a], matched_filter)
+    def learned(st=st, c=chunk, images=imgs, ps=ps_te, n=n_test):
+        Ws, W0s, zs, ss = [], [], [], []
+        for a in range(0, n, c):
+            b = min(n, a + c)
+            W, _, W0, z, sg = learned_poses(lib, net, pbs[c], images[a:b], ps.ctf(a, b), st,
+                                            xbuf[:b - a], matched_filter)
             Ws.append(W)
             W0s.append(W0)
-        return torch.cat(Ws), torch.cat(W0s)
+            zs.append(z)
+            ss.append(sg)
+        return torch.cat(Ws), torch.cat(W0s), torch.cat(zs), torch.cat(ss)
 
-    W_u, W0_u = learned()
+    W_u, W0_u, _, _ = learned()
     err_u = angular_error_deg(W_u, ps_te.rot)
     err_pu = angular_error_deg(W0_u, ps_te.rot)
     res["untrained"] = {"median_deg": float(np.median(err_u)),
@@ -295,7 +347,7 @@ def run_c5(lib, *, n_train=200000, n_test=8192, epochs=12, batch=256, lr=1e-3, g
                        "seconds": t_train, "images_per_s": epochs * n_train / t_train,
                        "loss_first": hist[0][1] if hist else None,
                        "loss_last": hist[-1][1] if hist else None}
-    W_t, W0_t = learned()
+    W_t, W0_t, _, _ = learned()
     same2 = lambda a, b: torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
     t_by = per_chunk(lambda c: (lambda: learned(st, c)), (W_t, W0_t), same2)
     c_l = min(t_by, key=lambda c: t_by[c][0])
@@ -315,11 +367,71 @@ def run_c5(lib, *, n_train=200000, n_test=8192, epochs=12, batch=256, lr=1e-3, g
         f"{n_test / t_l:.0f} img/s (batches of {c_l})")
     res["speedup_vs_grid_search"] = t_gs / t_l
     res["reaches_grid_search_error"] = bool(np.median(err_t) <= np.median(err_gs))
+
+    # fallback: threshold on the fit statistic, calibrated on validation
+    # particles (same distributions, separate stream) against the grid search
+    ps_va = PoseSet.from_views(inputs.c5_validation(seed, n_val, D))
+    imgs_va = render_particles(lib, gd, ps_va, 0, n_val, snr_db, seed + 2000)
+    W_va_g = torch.cat([grid_poses(pbs[chunk], banks[0], imgs_va[a:min(n_val, a + chunk)],
+                                   ps_va.ctf(a, min(n_val, a + chunk)))[0]
+                        for a in range(0, n_val, chunk)])
+    W_va_l, _, z_va, s_va = learned(st, chunk, imgs_va, ps_va, n_val)
+    e_va_g = angular_error_deg(W_va_g, ps_va.rot)
+    e_va_l = angular_error_deg(W_va_l, ps_va.rot)
+    # both statistics as "low = poor fit"; the one that needs the smaller
+    # validation fallback at the margin is used, the other reported
+    stats_va = {"z": z_va.cpu().numpy(), "neg_sigmas": -s_va.cpu().numpy()}
+    tradeoff = {name: {str(m): calibrate_threshold(v, e_va_l, e_va_g, m)[1]
+                       for m in (0.5, 1.0, 2.0, 4.0)} for name, v in stats_va.items()}
+    cal = {name: calibrate_threshold(v, e_va_l, e_va_g, fallback_margin_deg)
+           for name, v in stats_va.items()}
+    stat = min(cal, key=lambda k: cal[k][1])
+    tau, frac_va = cal[stat]
+    log(f"fallback on {stat} < {tau:.4f}: {100 * frac_va:.1f}% of validation particles "
+        f"(validation mean error learned {e_va_l.mean():.2f}, grid {e_va_g.mean():.2f} deg; "
+        f"fractions by margin {tradeoff})")
+    pfb = {c: lib.pose_batch(D, pixel, c, shift_radius) for c in chunks}
+
+    def with_fallback(c, graphed):
+        def fn():
+            W, W0, z, sg = graphed() if graphed is not None else learned(st, c)
+            W = W.clone()
+            n_fb = fallback_search(pfb[c], banks[0], imgs, ps_te, W, z if stat == "z" else -sg,
+                                   tau, c)
+            return W, n_fb
+        return fn
+
+    fb_by, W_f, n_f = {}, None, 0
+    for c in chunks:
+        fn = with_fallback(c, Graphed(lambda c=c: learned(st, c)) if use_graphs else None)
+        (W_c, n_c), t_c = timed(fn)
+        if W_f is None:
+            W_f, n_f = W_c, n_c
+        elif not torch.equal(W_c, W_f):
+            raise RuntimeError(f"batches of {c} give other fallback poses than batches of {chunk}")
+        fb_by[c] = t_c
+    err_f = angular_error_deg(W_f, ps_te.rot)
+    c_f = min(fb_by, key=fb_by.get)
+    res["learned_fallback"] = {
+        "statistic": stat, "threshold": tau, "margin_deg": fallback_margin_deg,
+        "validation_fallback_fraction_by_margin": tradeoff,
+        "fallback_fraction_validation": frac_va, "fallback_fraction": n_f / n_test,
+        "validation_mean_deg": {"learned": float(e_va_l.mean()), "grid": float(e_va_g.mean())},
+        "median_deg": float(np.median(err_f)), "mean_deg": float(err_f.mean()),
+        "images_per_s": n_test / fb_by[c_f], "batch": c_f,
+        "images_per_s_by_batch": {str(c): n_test / t for c, t in fb_by.items()},
+        "speedup_same_batch": {str(c): (n_test / fb_by[c])
+                               / res["grid_search"]["images_per_s_by_batch"][str(c)]
+                               for c in chunks}}
+    log(f"learned + fallback: {100 * n_f / n_test:.1f}% searched, median {np.median(err_f):.2f} deg, "
+        f"mean {err_f.mean():.2f} deg (grid {err_gs.mean():.2f}), {n_test / fb_by[c_f]:.0f} img/s")
+    for pb in pfb.values():
+        pb.close()
     sweep = []
     for stv in stage_sweep:
         sv = [Stage(banks[b], nd, npc) for b, nd, npc in stv]
         fn_v = (lambda: learned(sv, c_l))
-        (W_v, _), t_v = timed(Graphed(fn_v) if use_graphs else fn_v)
+        (W_v, _, _, _), t_v = timed(Graphed(fn_v) if use_graphs else fn_v)
         e_v = angular_error_deg(W_v, ps_te.rot)
         sweep.append({"stages": [list(x) for x in stv], "median_deg": float(np.median(e_v)),
                       "images_per_s": n_test / t_v, "speedup_vs_grid_search": t_gs / t_v})

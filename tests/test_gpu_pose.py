@@ -316,14 +316,15 @@ def test_graphed_pose_paths_match_eager(gpu_lib, D):
     stages = [pose.Stage(b1, 3, 2), pose.Stage(b2, 3, 2)]
     learned = lambda: pose.learned_poses(gpu_lib, net, batch, imgs, ctf, stages, xbuf)
     grid = lambda: pose.grid_poses(batch, b1, imgs, ctf)
-    W_e, s_e, W0_e = [t.clone() for t in learned()]
+    W_e, s_e, W0_e, z_e, f_e = [t.clone() for t in learned()]
     Wg_e, sg_e = [t.clone() for t in grid()]
     gl, gg = pose.Graphed(learned), pose.Graphed(grid)
     for rep in range(3):
-        W, s, W0 = gl()
+        W, s, W0, z, f = gl()
         Wg, sg = gg()
         torch.cuda.synchronize()
         assert torch.equal(W, W_e) and torch.equal(s, s_e) and torch.equal(W0, W0_e), rep
+        assert torch.equal(z, z_e) and torch.equal(f, f_e), rep
         assert torch.equal(Wg, Wg_e) and torch.equal(sg, sg_e), rep
         # eager work between replays: a search with another bank, then a sync
         batch.load(imgs, ctf)
@@ -331,3 +332,44 @@ def test_graphed_pose_paths_match_eager(gpu_lib, D):
         torch.cuda.synchronize()
     for h in (b1, b2, batch, net):
         h.close()
+
+
+def test_fit_statistic_matches_oracle(gpu_lib):
+    """cs_pose_batch_confidence at the winning pose of a grid search against
+    the oracle's fit statistic at that pose; the error bound carries the
+    bfloat16 bound of the score and of the template energy over to z."""
+    announce("fit statistic of the winning pose vs oracle, D=48")
+    rng = np.random.default_rng(915)
+    g = inputs.mixture_anisotropic(rng, 300, 12.0)
+    D, pixel, P, r = 48, 1.5, 4, 2
+    G = o_pose.grid(1, 8).astype(np.float32)
+    v, Y = _particles(g, P, D, pixel, rng, shift_px=[[0, 0], [1, -2], [-1, 1], [2, 2]])
+    bank = gpu_lib.pose_bank(**mixture_args(g), rot=dev(G), n_psi=8, D=D, pixel=pixel)
+    batch = gpu_lib.pose_batch(D, pixel, P, shift_radius=r)
+    batch.load(dev(Y), ctf_arg(v))
+    out = batch.search(bank)
+    z = host(batch.confidence(bank, out))
+    z2, sg = batch.confidence(bank, out, want_sigmas=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(z2), z)
+    sg = host(sg)
+    dxs, dys = o_pose.shift_offsets(r)
+    rel = 2 * U_BF16 + U_BF16 ** 2 + D * D * 2.0 ** -24
+    for p in range(P):
+        k, s = int(out["rot_idx"][p]), int(out["shift_idx"][p])
+        vp = v.subset([p])
+        ref = o_pose.fit_statistic(g, Y[p], vp, _f64(G[k]), [dxs[s], dys[s]])
+        X = model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, _f64(G[k])[None],
+                                 np.zeros((1, 2)), D, pixel)
+        from oracle import ctf as o_ctf
+        E = np.sum(o_ctf.apply_ctf(X, o_ctf.ctf_grid_for(vp)[0]) ** 2)
+        bound = _bf16_bound(g, Y[p], vp, _f64(G[k])[None], r)[0, s]
+        tol = (bound + rel * E * abs(ref)) / E + 1e-6
+        announce(f"  particle {p}: z {z[p]:.5f} vs oracle {ref:.5f} (bound {tol:.1e})")
+        assert abs(z[p] - ref) <= tol, p
+        # shortfall in noise spreads: (1 - z) ||H Q|| D / (2 ||Y||)
+        f = np.sqrt(E) * D / (2.0 * np.sqrt(np.sum(_f64(Y[p]) ** 2)))
+        s_ref = (1.0 - ref) * f
+        assert abs(sg[p] - s_ref) <= tol * f + rel * abs(s_ref) + 1e-6, p
+    bank.close()
+    batch.close()

@@ -37,8 +37,8 @@ def test_training_gains_over_untrained_network(gpu_lib):
     batch = gpu_lib.pose_batch(D, pixel, 256, shift_radius=1)
     xbuf = torch.empty(256, D, D, device="cuda", dtype=torch.bfloat16)
     st = [pose.Stage(bank, 4, 3)]
-    W_t, _, P_t = pose.learned_poses(gpu_lib, net, batch, imgs, ps_te.ctf(0, 256), st, xbuf)
-    W_u, _, P_u = pose.learned_poses(gpu_lib, untrained, batch, imgs, ps_te.ctf(0, 256), st,
+    W_t, _, P_t, _, _ = pose.learned_poses(gpu_lib, net, batch, imgs, ps_te.ctf(0, 256), st, xbuf)
+    W_u, _, P_u, _, _ = pose.learned_poses(gpu_lib, untrained, batch, imgs, ps_te.ctf(0, 256), st,
                                      xbuf)
     e_u = np.median(pose.angular_error_deg(P_u, ps_te.rot))
     e_t = np.median(pose.angular_error_deg(P_t, ps_te.rot))

@@ -108,3 +108,30 @@ def test_refinement_psi_rule_and_candidates():
     k = 5 * n_psi + 7
     c = pose.refine_candidates(bank[k], bank, n_psi, 3, 3)
     assert k in c[:3]
+
+
+def _fit_case(seed=31):
+    rng = np.random.default_rng(seed)
+    g = inputs.mixture_anisotropic(rng, 40, 6.0)
+    v = inputs.views(rng, 1, 24, 1.5)
+    W = pose.grid(1, 4)[5]
+    X = pose.model.render_pre_ctf(g.means, g.log_scales, g.quats, g.amps, W[None],
+                                  np.array([[1.0, -1.0]]) * 1.5, v.D, v.pixel)
+    X = pose.ctf_mod.apply_ctf(X, pose.ctf_mod.ctf_grid_for(v)[0])[0]
+    return g, v, W, X, rng
+
+
+def test_fit_statistic_closed_forms():
+    """z = 2 c - 1 for a particle equal to c times the template at the
+    pose (c = 1: exact fit; c = 0: an empty particle gives -1), and
+    z = 2 a - 1 with a = <X, Y> / ||X||^2 for any particle."""
+    g, v, W, X, rng = _fit_case()
+    for c in (1.0, 0.5, 2.0, 0.0):
+        z = pose.fit_statistic(g, c * X, v, W, [1.0, -1.0])
+        assert abs(z - (2 * c - 1)) <= 1e-12 * max(1.0, abs(2 * c - 1))
+    N = rng.standard_normal(X.shape)
+    Y = 0.7 * X + 0.1 * np.abs(X).max() * N
+    a = np.sum(X * Y) / np.sum(X * X)
+    assert abs(pose.fit_statistic(g, Y, v, W, [1.0, -1.0]) - (2 * a - 1)) <= 1e-12
+    # a template at another shift fits worse than the particle's own
+    assert pose.fit_statistic(g, X, v, W, [0.0, 0.0]) < 1.0 - 1e-3

@@ -67,3 +67,4 @@ def test_centring_is_skipped_without_translations_and_orders_are_seeded():
     tb = [c[1] for c in b.calls if c[0] == "train"]
     assert all(np.array_equal(x, y) for x, y in zip(ta, tb))
     assert [c for c in a.calls if c[0] == "train"][0][6].graph == 1
+
