@@ -81,13 +81,13 @@ def measured_traffic(kernel: str, launches_per_step: int = 1):
     return None if k is None else float(k["bytes_per_launch"])
 
 
-def issue_ceiling(kernel: str):
+def issue_ceiling(kernel: str, profile: str = "splat_issue_counters_c4.md"):
     """Hardware ceilings of a splat kernel from its committed instruction
     counters (SQ_INSTS_VALU, SQ_INSTS_VALU_TRANS_F32, SQ_LDS_IDX_ACTIVE per
     launch, the launch's algorithmic pairs): pairs per second at the VALU
     issue ceiling, and the LDS busy cycles per pair; None when missing or
     stale."""
-    rec = _profile_record("splat_issue_counters_c4.md", "issue-json")
+    rec = _profile_record(profile, "issue-json")
     k = (rec or {}).get("kernels", {}).get(kernel)
     if k is None:
         return None
@@ -108,35 +108,61 @@ def pair_peak(kernel: str) -> float:
 
 # --------------------------------------------------------------- CPU oracle
 
-def _oracle_worker(args):
-    """One image of the workload through the FP64 oracle (loss + gradient)."""
-    b, seed = args
+_W = {}
+
+
+def _oracle_init(workload, barrier):
+    """Pool worker set-up: the workload's seeded inputs, built once per worker."""
+    import numpy as np
+    from paper_2508_04929_amd import inputs
+    if workload == "c1":
+        g, v, _gt = inputs.c1()
+    elif workload == "c2":
+        g, v, _gt, _rn = inputs.c2()
+    else:
+        g, v, _gt, _rn = inputs.c4()
+    _W.update(g=g, v=v, workload=workload, rng=np.random.default_rng(1234))
+    _W["barrier"] = barrier
+
+
+def _oracle_ready(_):
+    _W["barrier"].wait()
+
+
+def _oracle_task(b):
+    """One image of the workload through the FP64 oracle: forward + CTF + loss
+    (c1: forward and loss only), else also the analytic gradient."""
     import numpy as np
     from oracle import objective
-    from paper_2508_04929_amd import inputs
-    g, v, _gt, _rn = inputs.c4()
+    g, v = _W["g"], _W["v"]
     vs = v.subset([b])
-    rng = np.random.default_rng(seed + b)
-    Y = rng.standard_normal((1, v.D, v.D)) * 1e-4   # observed values do not change the work
-    t0 = time.perf_counter()
-    objective.loss_and_grad(g, vs, Y, q_cut=Q_CUT)
-    return time.perf_counter() - t0
+    Y = _W["rng"].standard_normal((1, v.D, v.D)) * 1e-4   # the values do not change the work
+    if _W["workload"] == "c1":
+        objective.forward(g, vs, Y, q_cut=Q_CUT)
+    else:
+        objective.loss_and_grad(g, vs, Y, q_cut=Q_CUT)
 
 
-def cpu_baseline(n_images: int):
+def cpu_baseline(n_images: int, workload: str = "c4"):
+    """The FP64 oracle on n_images images of a workload, one image per task in
+    a process pool over the host's cores; throughput = images / pool wall
+    time (inputs built in every worker before the clock starts)."""
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16, n_images)
     ctx = mp.get_context("spawn")
-    with ctx.Pool(cores) as pool:
-        times = pool.map(_oracle_worker, [(b, 1234) for b in range(n_images)])
-    # workers run concurrently: throughput = images / (images per core x mean time)
-    per_core = -(-n_images // cores)
-    wall = per_core * (sum(times) / len(times))
+    barrier = ctx.Barrier(cores)
+    with ctx.Pool(cores, initializer=_oracle_init, initargs=(workload, barrier)) as pool:
+        pool.map(_oracle_ready, range(cores), chunksize=1)
+        t0 = time.perf_counter()
+        pool.map(_oracle_task, range(n_images), chunksize=1)
+        wall = time.perf_counter() - t0
+    what = {"c1": "N=1,000, D=64, forward + CTF + loss",
+            "c2": "N=20,000, D=128, forward + CTF + loss + analytic gradient",
+            "c4": "N=200,000, D=256, forward + CTF + loss + analytic gradient"}[workload]
     return {"value": n_images / wall, "unit": "images/s", "cores": cores, "kind": "oracle",
-            "sample": (f"{n_images} of the 64 images (N=200,000, D=256), FP64 numpy oracle, "
-                       f"forward + CTF + loss + analytic gradient with the same q_cut as the "
-                       f"GPU; {cores} worker processes, mean {sum(times) / len(times):.1f} s "
-                       f"per image")}
+            "sample": (f"{n_images} images of the workload ({what}), FP64 numpy oracle with "
+                       f"the same q_cut as the GPU, one image per task on {cores} worker "
+                       f"processes; {wall:.1f} s pool wall time")}
 
 
 # ------------------------------------------------------------------- GPU
@@ -338,6 +364,106 @@ def run(args):
     return result
 
 
+def run_small(workload: str, steps: int = 20, warmup: int = 3, cpu_images: int = 16):
+    """The other two single-mixture workloads:
+    c2: N=20,000 anisotropic Gaussians, 256 images of 128^2 at 1.5 A with
+        shifts, CTF, observed = ground-truth render + noise at -20 dB;
+        forward + loss + adjoint + Adam per step;
+    c1: N=1,000 isotropic Gaussians, 16 images of 64^2 at 3 A, CTF; forward +
+        squared-error loss only.
+    Images/s with inputs resident, the splat kernels' pairs/s (against the
+    ceilings of a committed counter summary of this workload when there is
+    one) and the FP64 oracle on cpu_images images."""
+    import numpy as np
+    import torch
+
+    from paper_2508_04929_amd import binding, inputs
+
+    lib = binding.library()
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+    if workload == "c1":
+        g, v, gt = inputs.c1()
+    else:
+        g, v, gt, _rn = inputs.c2()
+    N, B, D, p = g.n, v.b, v.D, v.pixel
+    prm = [t(g.means), t(g.log_scales), t(g.quats), t(g.amps)]
+    rot, shift = t(v.rot), t(v.shift)
+    ctf = binding.Ctf(t(v.defocus_u), t(v.defocus_v), t(v.astig), t(v.phase),
+                      v.voltage_kv, v.cs_mm, v.amp_contrast, v.bfactor)
+    X = lib.render(t(gt.means), t(gt.log_scales), t(gt.quats), t(gt.amps), rot, shift, D, p, ctf=ctf)
+    if workload == "c2":
+        gen = torch.Generator(device=dev).manual_seed(4)
+        sd = torch.sqrt(X.double().var() / 10 ** (-20 / 10)).float()
+        Y = (X + sd * torch.randn(X.shape, device=dev, generator=gen)).contiguous()
+    else:
+        Y = X
+    pairs = int(lib.pair_count(*prm, rot, shift, D, p).sum().item())
+    flat = torch.cat([x.reshape(-1) for x in prm]).contiguous()
+    sizes = [3 * N, 3 * N, 4 * N, N]
+    views = lambda buf: [buf[o:o + n].view(*x.shape) for o, n, x in
+                         zip(np.cumsum([0] + sizes[:-1]), sizes, prm)]
+    params = views(flat)
+    gflat = torch.zeros_like(flat)
+    grads = dict(zip(("means", "log_scales", "quats", "amps"), views(gflat)))
+    m, vv = torch.zeros_like(flat), torch.zeros_like(flat)
+    loss = torch.empty(B + 1, device=dev)
+    k = [0]
+
+    def step():
+        if workload == "c1":
+            lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
+                              want_grads=False, loss=loss)
+        else:
+            lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
+                              grads=grads, loss=loss)
+            k[0] += 1
+            lib.adam_step(flat, gflat, m, vv, k[0], lr=1e-3)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    lib.set_timing(dev, True)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    stages = {}
+    for name in binding.STAGES:
+        ms, n = lib.stage_time(dev, name)
+        if n:
+            stages[name] = ms / n
+    lib.set_timing(dev, False)
+    splat = {}
+    for kern in ("k_splat_fwd", "k_splat_bwd"):
+        if kern not in stages:
+            continue
+        ach = pairs / (stages[kern] * 1e-3)
+        c = issue_ceiling(kern, f"splat_issue_counters_{workload}.md")
+        rec = {"ms_per_launch": stages[kern], "pairs_per_s": ach,
+               "nominal_budget_frac": ach / pair_peak(kern), "ceiling": c}
+        if c is not None:
+            peaks = {"valu_issue": c["pairs_per_s_at_issue_ceiling"]}
+            if "pairs_per_s_at_lds_ceiling" in c:
+                peaks["lds"] = c["pairs_per_s_at_lds_ceiling"]
+            lim = min(peaks, key=peaks.get)
+            rec.update(bound=lim, frac=ach / peaks[lim])
+        splat[kern] = rec
+    out = {"workload": ("N=20,000 anisotropic Gaussians, 256 images D=128, p=1.5 A, shifts, CTF, "
+                        "-20 dB; forward + loss + adjoint + Adam" if workload == "c2" else
+                        "N=1,000 isotropic Gaussians, 16 images D=64, p=3 A, CTF; forward + "
+                        "squared-error loss"),
+           "images_per_s": B / dt, "ms_per_step": dt * 1e3, "pairs_per_step": pairs,
+           "splat": splat, "stages_ms_per_step": stages}
+    if cpu_images > 0:
+        out["cpu_baseline"] = cpu_baseline(min(cpu_images, B), workload)
+    return out
+
+
 def run_volume(reps: int = 5):
     """The reconstruction read out as a volume and compared (Sec. 3 overview,
     Sec. 4 Eq. 10): voxelise the N = 200,000 training mixture and its ground
@@ -500,13 +626,13 @@ def run_densify(n: int = 200000, reps: int = 20):
     p = torch.randn(11 * n, device="cuda", generator=gen)
     m = torch.randn(11 * n, device="cuda", generator=gen)
     v = torch.rand(11 * n, device="cuda", generator=gen)
-    lib.split_gaussians(p, m, v)
+    out = lib.split_gaussians(p, m, v)   # the outputs, reused by the timed calls
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        lib.split_gaussians(p, m, v)
+        lib.split_gaussians(p, m, v, out=out)
         e1.record()
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
@@ -515,7 +641,7 @@ def run_densify(n: int = 200000, reps: int = 20):
     return {"workload": f"split N={n} Gaussians (parameters and Adam moments) into {2 * n}",
             "ms": ms, "bytes": nbytes, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
             "frac_of_hbm_peak": nbytes / (ms * 1e-3) / 8e12,
-            "note": "median over calls; includes the library call's output allocation in torch"}
+            "note": "median over calls into preallocated outputs (no allocation timed)"}
 
 
 def run_batched(reps: int = 10, autotune: bool = True):
@@ -557,7 +683,33 @@ def run_batched(reps: int = 10, autotune: bool = True):
                               pr.pixel, pr.observed, ctf=pr.ctf, options=pr.options,
                               reduction="mean", grads=pr.grads, loss=pr.loss)
 
-    out = {}
+    # per-kernel HIP-event times of one eager batched call (the splat kernels
+    # run one launch per canvas size over all problems)
+    lib.set_timing(dev, True)
+    lib.loss_and_grad_multi(probs, use_graph=False)
+    torch.cuda.synchronize()
+    stages = {}
+    for name in binding.STAGES:
+        ms, n = lib.stage_time(dev, name)
+        if n:
+            stages[name] = {"ms": ms, "launches": n}
+    lib.set_timing(dev, False)
+    splat = {}
+    for kern in ("k_splat_fwd", "k_splat_bwd"):
+        if kern not in stages:
+            continue
+        ach = pairs / (stages[kern]["ms"] * 1e-3)
+        c = issue_ceiling(kern, "splat_issue_counters_c3.md")
+        rec = {"ms": stages[kern]["ms"], "launches": stages[kern]["launches"], "pairs_per_s": ach,
+               "nominal_budget_frac": ach / pair_peak(kern), "ceiling": c}
+        if c is not None:
+            peaks = {"valu_issue": c["pairs_per_s_at_issue_ceiling"]}
+            if "pairs_per_s_at_lds_ceiling" in c:
+                peaks["lds"] = c["pairs_per_s_at_lds_ceiling"]
+            lim = min(peaks, key=peaks.get)
+            rec.update(bound=lim, frac=ach / peaks[lim])
+        splat[kern] = rec
+    out = {"splat": splat, "stages_ms": {k: v["ms"] for k, v in stages.items()}}
     for name, fn in (("batched", batched), ("separate", separate)):
         fn()
         torch.cuda.synchronize()
@@ -599,6 +751,10 @@ def main():
                     help="skip the uneven-batching measurement (8 mixtures in one launch)")
     ap.add_argument("--no-pose-sweep", dest="pose_sweep", action="store_false",
                     help="skip the extra refinement configurations of the pose leg")
+    ap.add_argument("--no-small", dest="small", action="store_false",
+                    help="skip the N=20,000 (256 x 128^2) and N=1,000 (16 x 64^2) workloads")
+    ap.add_argument("--only-small", action="store_true",
+                    help="run only the N=20,000 and N=1,000 workloads (counter profiling)")
     ap.add_argument("--pose-train", type=int, default=200000)
     ap.add_argument("--pose-epochs", type=int, default=12)
     ap.add_argument("--pose-test", type=int, default=8192)
@@ -607,6 +763,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(multi-GPU data parallelism is described, not built)"}))
         sys.exit(2)
+    if args.only_small:
+        print(json.dumps({k: run_small(k, args.steps, args.warmup, args.cpu_images)
+                          for k in ("c2", "c1")}))
+        return
     cpu = None
     if args.cpu_images > 0 and int(os.environ.get("RANK", "0")) == 0:
         cpu = cpu_baseline(args.cpu_images)
@@ -614,6 +774,11 @@ def main():
               file=sys.stderr, flush=True)
     res = run(args)
     res["cpu_baseline"] = cpu
+    if args.small:
+        for k in ("c2", "c1"):
+            res[k] = run_small(k, cpu_images=args.cpu_images)
+            print(f"[bench] {k}: {res[k]['images_per_s']:.0f} images/s", file=sys.stderr,
+                  flush=True)
     if args.trainer:
         res["trainer"] = run_trainer()
         res["densify"] = run_densify()

@@ -405,9 +405,10 @@ class Library:
         return out
 
     def split_gaussians(self, params, adam_m=None, adam_v=None, scale_act="softplus",
-                        amp_act="softplus"):
+                        amp_act="softplus", out=None):
         """Densify: flat parameters [11 N] -> [22 N] (and the Adam moments when
-        given), cs_split_gaussians.  Returns (params, m, v)."""
+        given), cs_split_gaussians.  Returns (params, m, v); `out` may hold
+        the three [22 N] output tensors (None entries are allocated)."""
         dev = params.device
         np_ = params.numel()
         if np_ % 11:
@@ -415,12 +416,17 @@ class Library:
         n = np_ // 11
         _ptr(params, "params", dev, (np_,))
         mom = adam_m is not None or adam_v is not None
-        out = torch.empty(2 * np_, device=dev, dtype=torch.float32)
+        o_p, o_m, o_v = out if out is not None else (None, None, None)
+        out = o_p if o_p is not None else torch.empty(2 * np_, device=dev, dtype=torch.float32)
+        _ptr(out, "out", dev, (2 * np_,))
         om = ov = None
         if mom:
             _ptr(adam_m, "adam_m", dev, (np_,))
             _ptr(adam_v, "adam_v", dev, (np_,))
-            om, ov = torch.empty_like(out), torch.empty_like(out)
+            om = o_m if o_m is not None else torch.empty_like(out)
+            ov = o_v if o_v is not None else torch.empty_like(out)
+            _ptr(om, "out_m", dev, (2 * np_,))
+            _ptr(ov, "out_v", dev, (2 * np_,))
         ctx = self.ctx(dev)
         rc = self.lib.cs_split_gaussians(
             ctx, params.data_ptr(), adam_m.data_ptr() if mom else None,
