@@ -121,3 +121,20 @@ def test_uneven_batch_real_mixtures(gpu_lib):
     for k, (pr, (g, v, Y)) in enumerate(zip(probs, host_side)):
         announce(f"  mixture {k}: adjoint (autotuned options) on images 5 and 90 vs oracle")
         _check_adjoint(gpu_lib, g, v, (5, 90), seed=150 + k, options=pr.options)
+
+
+def test_headline_pair_count_vs_oracle(gpu_lib):
+    """The pair count that prices the headline roofline (N = 200,000, 64
+    images of 256^2): cs_pair_count over all 64 images, images 0 and 63
+    against the oracle's exact count (Eq. 8 splat with q <= q_cut; FP32 and
+    FP64 may place pixels sitting on the cut on different sides)."""
+    from oracle import model as o_model
+    g, v, _gt, _rn = inputs.c4()
+    announce("headline pair count, images 0 and 63 vs oracle")
+    got = host(gpu_lib.pair_count(**mixture_args(g), **view_args(v)))
+    assert got.shape == (64,)
+    for b in (0, 63):
+        ref = o_model.pair_count(g.means, g.log_scales, g.quats, v.rot[b:b + 1], v.shift[b:b + 1],
+                                 v.D, v.pixel, Q_MATCHED)[0]
+        announce(f"  image {b}: {int(got[b])} vs {int(ref)}")
+        assert abs(got[b] - ref) <= 1e-5 * ref + 2
