@@ -1129,7 +1129,7 @@ class Network:
 
 #: Kernel stages the library may launch (names reported by stage_time).
 STAGES = ("k_build", "k_bin_count", "k_bin_blockscan", "k_scan", "k_bin_scatter", "k_ctf_table", "k_splat_fwd", "k_canvas_reduce",
-          "k_big_fwd", "k_fft_rows_fwd", "k_fft_cols_ctf", "k_fft_rows_inv_loss", "k_fft_rows_inv",
+          "k_big_prep", "k_big_fwd", "k_big_add", "k_fft_rows_fwd", "k_fft_cols_ctf", "k_fft_rows_inv_loss", "k_fft_rows_inv",
           "k_residual", "k_loss_reduce", "k_loss_total", "k_splat_bwd", "k_big_bwd", "k_chain", "k_adam",
           "k_fill", "k_pair_count", "k_pose_grad_part", "k_pose_grad_sum")
 

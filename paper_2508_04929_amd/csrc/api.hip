@@ -119,7 +119,7 @@ enum Mode { RENDER, BACKWARD, LOSS };
 struct Layout {
   size_t gc = 0, key = 0, count = 0, off = 0, blk = 0, item_off = 0, n_items = 0, queues = 0,
          items = 0, list = 0, partials = 0, Q = 0, spec = 0, ctf = 0, mom = 0, loss_part = 0,
-         pose_part = 0, wabs = 0;
+         pose_part = 0, wabs = 0, wscale = 0, wideq = 0;
   size_t total = 0;
   int max_items = 0;
   int nbx = 0;  // Gaussian blocks of the binning kernels
@@ -172,7 +172,11 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
   L.items = take((size_t)L.max_items * 16 + 16);
   L.list = take(BN * 32 + 32);
   L.wabs = take(BN * 4 + 16);
-  if (need_partials) L.partials = take((size_t)L.max_items * G.C * G.C * 4);
+  if (need_partials) {
+    L.partials = take((size_t)L.max_items * G.C * G.C * 4);
+    L.wscale = take((size_t)G.B * 8);
+    L.wideq = take((size_t)G.B * G.D * G.D * 8);
+  }
   L.Q = take((size_t)G.B * G.D * G.D * 4);
   if (need_fft) {
     L.spec = take((size_t)G.B * G.D * (G.D / 2 + 1) * 8);
@@ -449,9 +453,15 @@ int launch_forward_finish(cs_ctx *ctx, const Plan &P, float *Q, hipStream_t st) 
   TLAUNCH(k_canvas_reduce, dim3(G.ntiles, G.B, zsplit), dim3(kBlock), 0, st,
           (const float *)(ws + P.L.partials), (const int *)(ws + P.L.item_off),
           (const int4 *)(ws + P.L.items), G, Q);
+  double *wscale = (double *)(ws + P.L.wscale);
+  long long *wq = (long long *)(ws + P.L.wideq);
+  TLAUNCH(k_big_prep, dim3(G.B), dim3(kBlock), 0, st, (const int *)(ws + P.L.off),
+          (const int *)(ws + P.L.count), (const float *)(ws + P.L.wabs), G, wscale, wq);
   TLAUNCH(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
           (const int *)(ws + P.L.off), (const int *)(ws + P.L.count),
-          (const int *)(ws + P.L.n_items) + 1, G, Q);
+          (const int *)(ws + P.L.n_items) + 1, G, (const double *)wscale, wq);
+  TLAUNCH(k_big_add, dim3(cdiv((size_t)G.D * G.D, 4 * kBlock), G.B), dim3(kBlock), 0, st,
+          (const int *)(ws + P.L.count), G, (const double *)wscale, (const long long *)wq, Q);
   return CS_OK;
 }
 

@@ -11,7 +11,8 @@
 //   k_splat_fwd    per work item: additive splat (Eq. 9) into an LDS canvas
 //                  covering the owner tile plus a halo -> partial canvases
 //   k_canvas_reduce per tile: sum of the overlapping partial canvases -> Q
-//   k_big_fwd      Gaussians wider than the halo, straight into Q
+//   k_big_*        Gaussians wider than the halo: 64-bit fixed-point sums
+//                  per image (order-free), then added to Q
 //   FFT kernels    X = F^-1(H^ . F Q), residual, loss, G_Q = F^-1(H^ . F G_X)
 //                  (Eq. 14, Sec. 3.3.5; H^ real and even -> self-adjoint)
 //   k_splat_bwd    per work item: per-(image, Gaussian) pixel moments of
@@ -170,8 +171,14 @@ __global__ void k_splat_fwd(MultiProb MP);
 __global__ void k_canvas_reduce(const float *partials, const int *item_off, const int4 *items,
                                 Geom G, float *Q);
 
+__global__ void k_big_prep(const int *off, const int *count, const float *wabs, Geom G,
+                           double *wscale, long long *wq);
+
 __global__ void k_big_fwd(const float4 *list, const int *off, const int *count,
-                          const int *n_wide, Geom G, float *Q);
+                          const int *n_wide, Geom G, const double *wscale, long long *wq);
+
+__global__ void k_big_add(const int *count, Geom G, const double *wscale, const long long *wq,
+                          float *Q);
 
 __global__ void k_splat_bwd(MultiProb MP);
 

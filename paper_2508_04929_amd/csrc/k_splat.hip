@@ -234,13 +234,48 @@ __device__ __forceinline__ void wide_box(const float4 r0, const float4 r1, const
   j1 = clamp_px(floorf(r0.x + hx), -1, G.D - 1);
 }
 
+// Wide records are summed in 64-bit fixed point so that the result does not
+// depend on the order of the device atomics: per image, the scale is the
+// power of two 2^e with 2^e * sum|w| < 2^61 over the image's wide records
+// (their |w| summed in a fixed order), every term is rounded to an integer
+// and the integer image is added to Q once all terms are in.
+// k_big_prep: one block per image: the scale, and the integer image cleared.
+__global__ void __launch_bounds__(kBlock)
+k_big_prep(const int *off, const int *count, const float *wabs, Geom G, double *wscale,
+           long long *wq) {
+  const int b = blockIdx.x;
+  const int e = b * G.K + G.ntiles;
+  const int cnt = count[e], start = off[e];
+  if (cnt == 0) return;
+  __shared__ double red[kBlock / 64];
+  double a = 0.0;
+  for (int k = threadIdx.x; k < cnt; k += kBlock) a += (double)wabs[start + k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  long long *img = wq + (size_t)b * G.D * G.D;
+  for (int i = threadIdx.x; i < G.D * G.D; i += kBlock) img[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+    int ex = 0;
+    if (tot > 0.0) frexp(tot, &ex);  // tot < 2^ex
+    wscale[b] = ldexp(1.0, 61 - ex);
+  }
+}
+
+// k_big_fwd: one block per wide record, threads over its pixel box, exp per
+// pixel, 64-bit integer atomics into the image's integer sum.
 __global__ void __launch_bounds__(kBlock)
 k_big_fwd(const float4 *list, const int *off, const int *count, const int *n_wide, Geom G,
-          float *Q) {
+          const double *wscale, long long *wq) {
   if (*n_wide == 0) return;
   for (int b = 0; b < G.B; ++b) {
     const int e = b * G.K + G.ntiles;
     const int cnt = count[e], start = off[e];
+    if (cnt == 0) continue;
+    const double S = wscale[b];
+    unsigned long long *img = (unsigned long long *)(wq + (size_t)b * G.D * G.D);
     for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
       const float4 r0 = list[2 * (size_t)(start + k)], r1 = list[2 * (size_t)(start + k) + 1];
       int i0, i1, j0, j1;
@@ -252,9 +287,25 @@ k_big_fwd(const float4 *list, const int *off, const int *count, const int *n_wid
         const int i = i0 + (int)(q / wdt), j = j0 + (int)(q % wdt);
         const float dj = (float)j - r0.x, di = (float)i - r0.y;
         const float qq = r0.z * dj * dj + 2.f * r0.w * dj * di + r1.x * di * di;
-        if (qq <= G.qk) atomicAdd(&Q[((size_t)b * G.D + i) * G.D + j], r1.y * exp2f(-qq));
+        if (qq <= G.qk) {
+          const long long v = __double2ll_rn((double)(r1.y * exp2f(-qq)) * S);
+          atomicAdd(&img[(size_t)i * G.D + j], (unsigned long long)v);
+        }
       }
     }
+  }
+}
+
+// k_big_add: Q += integer sum / scale for images with wide records.
+__global__ void __launch_bounds__(kBlock)
+k_big_add(const int *count, Geom G, const double *wscale, const long long *wq, float *Q) {
+  const int b = blockIdx.y;
+  if (count[b * G.K + G.ntiles] == 0) return;
+  const double inv = 1.0 / wscale[b];
+  const size_t n = (size_t)G.D * G.D;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+    const long long v = wq[(size_t)b * n + i];
+    if (v) Q[(size_t)b * n + i] += (float)((double)v * inv);
   }
 }
 

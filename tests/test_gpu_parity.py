@@ -290,6 +290,28 @@ def test_forward_is_bitwise_deterministic(gpu_lib):
         assert np.array_equal(host(ga[k]), host(gb[k])), k
 
 
+def test_wide_path_is_bitwise_deterministic_and_matches_oracle(gpu_lib):
+    """A two-pixel halo sends most records down the wide path, whose
+    footprints overlap heavily: repeated renders and adjoints must agree bit
+    for bit (64-bit fixed-point sums per image), and match the oracle."""
+    rng = np.random.default_rng(19)
+    g = inputs.mixture_anisotropic(rng, 2500, 20.0, scale_mu=np.log(2.5))
+    v = inputs.views(rng, 3, 96, 1.0, shift_px_sd=2.0)
+    opt = binding.Options(tile=16, halo=2)
+    announce("wide path: bitwise repeatability")
+    a = host(gpu_lib.render(**mixture_args(g), **view_args(v), ctf=ctf_arg(v), options=opt))
+    for _ in range(3):
+        b = host(gpu_lib.render(**mixture_args(g), **view_args(v), ctf=ctf_arg(v), options=opt))
+        assert np.array_equal(a, b)
+    Q = host(gpu_lib.render(**mixture_args(g), **view_args(v), options=opt))
+    assert per_image_normwise(Q, _oracle_Q(g, v)) <= IMG_TOL
+    dX = dev(rng.standard_normal((3, 96, 96)).astype(np.float32))
+    ga = gpu_lib.render_backward(**mixture_args(g), **view_args(v), d_images=dX, options=opt)
+    gb = gpu_lib.render_backward(**mixture_args(g), **view_args(v), d_images=dX, options=opt)
+    for k in GROUPS:
+        assert np.array_equal(host(ga[k]), host(gb[k])), k
+
+
 def test_fixed_point_with_extreme_weight_spread(gpu_lib):
     """Very narrow and very wide Gaussians share tiles: fixed-point scale stress."""
     rng = np.random.default_rng(18)
