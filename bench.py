@@ -216,11 +216,17 @@ def run(args):
 
     step_no = [0]
 
-    graph_opt = binding.Options(graph=1)
+    # launch options (tile, halo, budget) from the library's autotuner on this
+    # step's own problem; results do not depend on them
+    pr = lib.make_problem(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean")
+    lib.autotune([pr], reps=2)
+    tuned = pr.options
+    del pr
+    graph_opt = binding.Options(tile=tuned.tile, halo=tuned.halo, budget=tuned.budget, graph=1)
 
     def step(graph=False):
         lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
-                          grads=grads, loss=loss, options=graph_opt if graph else None)
+                          grads=grads, loss=loss, options=graph_opt if graph else tuned)
         step_no[0] += 1
         lib.adam_step(flat, gflat, m, vv, step_no[0], lr=1e-3)
 
@@ -263,7 +269,7 @@ def run(args):
 
     def step_pose():
         lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
-                          grads=grads_pose, loss=loss)
+                          grads=grads_pose, loss=loss, options=tuned)
         step_no[0] += 1
         lib.adam_step(flat, gflat, m, vv, step_no[0], lr=1e-3)
 
@@ -353,6 +359,8 @@ def run(args):
                                 "parameters"),
                    "N": N, "batch": B, "D": D, "pixel_A": p, "q_cut": Q_CUT,
                    "pairs_per_step": pairs_step, "pairs_per_image": pairs_step / B,
+                   "launch_options": {"tile": tuned.tile, "halo": tuned.halo,
+                                      "budget": tuned.budget, "source": "cs_autotune"},
                    "final_loss": final_loss},
         "roofline": roof,
         "step_fraction_of_splat_roofline": step_roof_s / (ms_step * 1e-3),
@@ -409,14 +417,19 @@ def run_small(workload: str, steps: int = 20, warmup: int = 3, cpu_images: int =
     m, vv = torch.zeros_like(flat), torch.zeros_like(flat)
     loss = torch.empty(B + 1, device=dev)
     k = [0]
+    pr = lib.make_problem(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
+                          want_grads=workload != "c1")
+    lib.autotune([pr], reps=2)
+    tuned = pr.options
+    del pr
 
     def step():
         if workload == "c1":
             lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
-                              want_grads=False, loss=loss)
+                              want_grads=False, loss=loss, options=tuned)
         else:
             lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
-                              grads=grads, loss=loss)
+                              grads=grads, loss=loss, options=tuned)
             k[0] += 1
             lib.adam_step(flat, gflat, m, vv, k[0], lr=1e-3)
 
@@ -458,6 +471,7 @@ def run_small(workload: str, steps: int = 20, warmup: int = 3, cpu_images: int =
                         "N=1,000 isotropic Gaussians, 16 images D=64, p=3 A, CTF; forward + "
                         "squared-error loss"),
            "images_per_s": B / dt, "ms_per_step": dt * 1e3, "pairs_per_step": pairs,
+           "launch_options": [tuned.tile, tuned.halo, tuned.budget],
            "splat": splat, "stages_ms_per_step": stages}
     if cpu_images > 0:
         out["cpu_baseline"] = cpu_baseline(min(cpu_images, B), workload)

@@ -1069,8 +1069,8 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
       // stage 1: tile x halo at the default budget; stage 2: budget
       std::vector<int> best = {kDefaultTile, kDefaultHalo, kDefaultBudget};
       double best_ms = 1e30;
-      const int tiles[] = {32, 48, 64, 96, 128};
-      const int halos[] = {8, 12, 16, 24};
+      const int tiles[] = {32, 40, 48, 56, 64, 96, 128};
+      const int halos[] = {8, 10, 12, 14, 16, 24};
       for (int T : tiles) {
         if (T > std::max(32, pr.v.d)) continue;
         for (int h : halos) {

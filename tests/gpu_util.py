@@ -43,3 +43,12 @@ def per_image_normwise(got, ref):
 
 def announce(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+def headline_options(lib, m, rot, shift, D, pixel, observed, ctf):
+    """Launch options of the headline step as the bench chooses them: the
+    library's autotuner on the step's own problem (mean reduction)."""
+    pr = lib.make_problem(m["means"], m["log_scales"], m["quats"], m["amps"], rot, shift, D, pixel,
+                          observed, ctf=ctf, reduction="mean")
+    lib.autotune([pr], reps=2)
+    return pr.options

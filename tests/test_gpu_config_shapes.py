@@ -1,7 +1,7 @@
 """Parity at the workloads' real shapes and launch configurations (GPU).
 
 - The headline training step (N = 200,000, B = 64, D = 256, 1.1 A, CTF,
-  default launch options, as the bench times it): the adjoint of the full
+  launch options from the autotuner, as the bench times it): the adjoint of the full
   64-image call with dL/dimages non-zero on four images and zero elsewhere,
   element by element against the FP64 oracle's gradient of those four
   images (App. A.2, Eq. 15-21).
@@ -26,7 +26,8 @@ from oracle import ctf as o_ctf
 from oracle import objective as o_obj
 from paper_2508_04929_amd import inputs
 
-from gpu_util import announce, ctf_arg, dev, host, mixture_args, normwise, view_args
+from gpu_util import (announce, ctf_arg, dev, headline_options, host, mixture_args, normwise,
+                      view_args)
 
 pytestmark = pytest.mark.gpu
 GROUPS = ("means", "log_scales", "quats", "amps")
@@ -73,7 +74,11 @@ def _check_images(X, loss, g, v, Y, idx, reduction_scale):
 def test_headline_step_adjoint_elementwise(gpu_lib):
     g, v, _gt, _rn = inputs.c4()
     announce("headline step N=200000 B=64 D=256: adjoint on images 3, 17, 40, 63 vs oracle")
-    _check_adjoint(gpu_lib, g, v, (3, 17, 40, 63), seed=130)
+    Y = (2e-6 * np.random.default_rng(129).standard_normal((v.b, v.D, v.D))).astype(np.float32)
+    opt = headline_options(gpu_lib, mixture_args(g), dev(v.rot), dev(v.shift), v.D, v.pixel,
+                           dev(Y), ctf_arg(v))
+    announce(f"  autotuned options tile={opt.tile} halo={opt.halo} budget={opt.budget}")
+    _check_adjoint(gpu_lib, g, v, (3, 17, 40, 63), seed=130, options=opt)
 
 
 def test_b256_forward_and_adjoint_subset(gpu_lib):

@@ -1,6 +1,6 @@
 """The training step at its full size (N = 200,000 Gaussians, 64 images of
 256^2, 1.1 A, CTF, mean reduction), in the launch configuration the bench
-times (default options): two sampled images and their losses against the
+times (options from the library's autotuner on the same problem): two sampled images and their losses against the
 FP64 oracle, computed image by image, and the full-batch gradient through
 the directional derivative of the loss (a central difference of the
 library's own loss along the gradient, a property that holds at any size).
@@ -13,7 +13,7 @@ import torch
 from oracle import objective
 from paper_2508_04929_amd import inputs
 
-from gpu_util import announce, ctf_arg, dev, host, mixture_args, normwise
+from gpu_util import announce, ctf_arg, dev, headline_options, host, mixture_args, normwise
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +34,12 @@ def test_training_step_full_size(gpu_lib):
     Y = (2e-6 * np.random.default_rng(120).standard_normal((B, D, D))).astype(np.float32)
     m = mixture_args(g)
     rot, shift, ctf, Yd = dev(v.rot), dev(v.shift), ctf_arg(v), dev(Y)
-    announce("full-size training step N=200000 B=64 D=256 (bench launch configuration)")
+    announce("full-size training step N=200000 B=64 D=256 (autotuned launch options, as the bench)")
+    opt = headline_options(gpu_lib, m, rot, shift, D, v.pixel, Yd, ctf)
+    announce(f"  options tile={opt.tile} halo={opt.halo} budget={opt.budget}")
     loss, grads, X = gpu_lib.loss_and_grad(m["means"], m["log_scales"], m["quats"], m["amps"], rot,
                                            shift, D, v.pixel, Yd, ctf=ctf, reduction="mean",
-                                           want_images=True)
+                                           want_images=True, options=opt)
     torch.cuda.synchronize()
     lo, Xh = host(loss), host(X)
     for b in (0, 41):
@@ -55,7 +57,7 @@ def test_training_step_full_size(gpu_lib):
         p = {k: (m[k] + sgn * h * grads[k] / gnorm).contiguous() for k in keys}
         l2, _, _ = gpu_lib.loss_and_grad(p["means"], p["log_scales"], p["quats"], p["amps"], rot,
                                          shift, D, v.pixel, Yd, ctf=ctf, reduction="mean",
-                                         want_grads=False)
+                                         want_grads=False, options=opt)
         vals.append(float(l2[-1]))
     fd = (vals[0] - vals[1]) / (2 * h)
     announce(f"  directional derivative {fd:.6e} vs |g| {gnorm:.6e}")
