@@ -219,7 +219,7 @@ def run(args):
     # launch options (tile, halo, budget) from the library's autotuner on this
     # step's own problem; results do not depend on them
     pr = lib.make_problem(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean")
-    lib.autotune([pr], reps=2)
+    lib.autotune([pr], reps=3)
     tuned = pr.options
     del pr
     graph_opt = binding.Options(tile=tuned.tile, halo=tuned.halo, budget=tuned.budget, graph=1)
@@ -419,7 +419,7 @@ def run_small(workload: str, steps: int = 20, warmup: int = 3, cpu_images: int =
     k = [0]
     pr = lib.make_problem(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
                           want_grads=workload != "c1")
-    lib.autotune([pr], reps=2)
+    lib.autotune([pr], reps=3)
     tuned = pr.options
     del pr
 

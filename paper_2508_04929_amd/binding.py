@@ -1136,9 +1136,32 @@ STAGES = ("k_build", "k_bin_count", "k_bin_blockscan", "k_scan", "k_bin_scatter"
 _LIB: Optional[Library] = None
 
 
+#: launch options the autotuner chose on an MI355X for the benchmark
+#: workloads (cs_autotune's cache format: signature tile halo budget)
+TUNE_DB = os.path.join(HERE, "tune_mi355x.txt")
+
+
+def use_tune_db(path: str = TUNE_DB) -> None:
+    """Point the contexts created from now on at a private copy of a tuning
+    database (CS_AUTOTUNE_CACHE): cs_autotune then returns the recorded
+    options for known problem signatures without timing, and new entries go
+    to the copy, never to the shipped file.  No-op when CS_AUTOTUNE_CACHE is
+    already set or the database is missing."""
+    if "CS_AUTOTUNE_CACHE" in os.environ or not os.path.exists(path):
+        return
+    import shutil
+    import tempfile
+    fd, tmp = tempfile.mkstemp(prefix="cs_tune_", suffix=".txt")
+    os.close(fd)
+    shutil.copyfile(path, tmp)
+    os.environ["CS_AUTOTUNE_CACHE"] = tmp
+
+
 def library() -> Library:
-    """The process-wide binding (loads libcryosplat.so on first use)."""
+    """The process-wide binding (loads libcryosplat.so on first use; contexts
+    read the shipped tuning database, see use_tune_db)."""
     global _LIB
     if _LIB is None:
+        use_tune_db()
         _LIB = Library(load_library())
     return _LIB

@@ -50,5 +50,5 @@ def headline_options(lib, m, rot, shift, D, pixel, observed, ctf):
     library's autotuner on the step's own problem (mean reduction)."""
     pr = lib.make_problem(m["means"], m["log_scales"], m["quats"], m["amps"], rot, shift, D, pixel,
                           observed, ctf=ctf, reduction="mean")
-    lib.autotune([pr], reps=2)
+    lib.autotune([pr], reps=3)
     return pr.options
