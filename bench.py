@@ -222,7 +222,8 @@ def run(args):
     lib.autotune([pr], reps=3)
     tuned = pr.options
     del pr
-    graph_opt = binding.Options(tile=tuned.tile, halo=tuned.halo, budget=tuned.budget, graph=1)
+    graph_opt = binding.Options(tile=tuned.tile, halo=tuned.halo, budget=tuned.budget, graph=1,
+                                lane_order=tuned.lane_order)
 
     def step(graph=False):
         lib.loss_and_grad(*params, rot, shift, D, p, Y, ctf=ctf, reduction="mean",
@@ -360,7 +361,8 @@ def run(args):
                    "N": N, "batch": B, "D": D, "pixel_A": p, "q_cut": Q_CUT,
                    "pairs_per_step": pairs_step, "pairs_per_image": pairs_step / B,
                    "launch_options": {"tile": tuned.tile, "halo": tuned.halo,
-                                      "budget": tuned.budget, "source": "cs_autotune"},
+                                      "budget": tuned.budget, "lane_order": tuned.lane_order,
+                                      "source": "cs_autotune"},
                    "final_loss": final_loss},
         "roofline": roof,
         "step_fraction_of_splat_roofline": step_roof_s / (ms_step * 1e-3),
@@ -471,7 +473,7 @@ def run_small(workload: str, steps: int = 20, warmup: int = 3, cpu_images: int =
                         "N=1,000 isotropic Gaussians, 16 images D=64, p=3 A, CTF; forward + "
                         "squared-error loss"),
            "images_per_s": B / dt, "ms_per_step": dt * 1e3, "pairs_per_step": pairs,
-           "launch_options": [tuned.tile, tuned.halo, tuned.budget],
+           "launch_options": [tuned.tile, tuned.halo, tuned.budget, tuned.lane_order],
            "splat": splat, "stages_ms_per_step": stages}
     if cpu_images > 0:
         out["cpu_baseline"] = cpu_baseline(min(cpu_images, B), workload)
@@ -737,7 +739,8 @@ def run_batched(reps: int = 10, autotune: bool = True):
                        "{128,192,256}, CTF, fwd + adjoint, autotuned tile/halo/budget")
     out["images"] = n_img
     out["pairs"] = pairs
-    out["options"] = [[pr.options.tile, pr.options.halo, pr.options.budget] for pr in probs]
+    out["options"] = [[pr.options.tile, pr.options.halo, pr.options.budget, pr.options.lane_order]
+                      for pr in probs]
     return out
 
 

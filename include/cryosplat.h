@@ -141,6 +141,10 @@ typedef struct {
                      argument signature (shapes, pointers, scalars) as a HIP
                      graph and replay it; the first call with a signature
                      must not itself be inside a caller's stream capture */
+  int32_t lane_order; /* 0 = each work item's Gaussians go to lanes in list
+                         order; 1 = dealt so that the lanes of a wave start on
+                         distinct LDS banks (pays for wide footprints).  The
+                         results are identical either way. */
 } cs_options;
 
 /* Create a context on HIP device `device`.  *out receives the handle. */

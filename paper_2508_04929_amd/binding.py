@@ -68,7 +68,8 @@ def _grads_struct(grads, dev, n, b):
 
 class CsOptions(ctypes.Structure):
     _fields_ = [("q_cut", ctypes.c_float), ("tile", ctypes.c_int32), ("halo", ctypes.c_int32),
-                ("budget", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("budget", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("lane_order", ctypes.c_int32)]
 
 
 class CsProblem(ctypes.Structure):
@@ -230,6 +231,7 @@ class Options:
     halo: int = 0
     budget: int = 0
     graph: int = 0       # 1: capture/replay the call as a HIP graph
+    lane_order: int = 0  # 1: records dealt to lanes by LDS bank (same results)
 
 
 @dataclasses.dataclass
@@ -318,7 +320,7 @@ class Library:
         o = None
         if options is not None:
             o = CsOptions(float(options.q_cut), int(options.tile), int(options.halo),
-                          int(options.budget), int(options.graph))
+                          int(options.budget), int(options.graph), int(options.lane_order))
         return dev, n, b, g, v, c, o
 
     @staticmethod
@@ -456,7 +458,7 @@ class Library:
         o = None
         if options is not None:
             o = CsOptions(float(options.q_cut), int(options.tile), int(options.halo),
-                          int(options.budget), int(options.graph))
+                          int(options.budget), int(options.graph), int(options.lane_order))
         if loss is not None:
             _ptr(loss, "loss", dev, (len(order),))
         ctx = self.ctx(dev)
@@ -600,7 +602,8 @@ class Library:
         for pr, s in zip(problems, arr):
             base = pr.options or Options()
             pr.options = Options(q_cut=base.q_cut, tile=s.opt.tile, halo=s.opt.halo,
-                                 budget=s.opt.budget, graph=base.graph)
+                                 budget=s.opt.budget, graph=base.graph,
+                                 lane_order=s.opt.lane_order)
         del keep
         return problems
 

@@ -286,6 +286,8 @@ int validate(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf
     if (opt->halo < 0 || opt->halo > T) return fail(ctx, CS_ERR_INVALID_ARG, "halo must be in [0, tile]");
     if (opt->budget != 0 && opt->budget < 64) return fail(ctx, CS_ERR_INVALID_ARG, "budget must be 0 or >= 64");
     if (!std::isfinite(opt->q_cut)) return fail(ctx, CS_ERR_INVALID_ARG, "q_cut must be finite");
+    if (opt->lane_order != 0 && opt->lane_order != 1)
+      return fail(ctx, CS_ERR_INVALID_ARG, "lane_order must be 0 or 1");
   }
   return CS_OK;
 }
@@ -309,6 +311,7 @@ Geom make_geom(const cs_gaussians *g, const cs_views *v, const cs_options *opt) 
   G.budget = (opt && opt->budget) ? opt->budget : auto_budget(G.N, G.B);
   G.scale_act = g->scale_act;
   G.amp_act = g->amp_act;
+  G.deal = opt ? opt->lane_order : 0;
   return G;
 }
 
@@ -816,9 +819,11 @@ void load_tune_file(cs_ctx *ctx) {
   while (std::getline(f, line)) {
     std::istringstream is(line);
     std::string key;
-    int t, h, b;
-    if (is >> key >> t >> h >> b && t >= 16 && t <= 128 && h >= 0 && h <= t && b >= 64)
-      ctx->tuned[key] = {t, h, b};
+    int t, h, b, d = 0;
+    if (is >> key >> t >> h >> b && t >= 16 && t <= 128 && h >= 0 && h <= t && b >= 64) {
+      if (!(is >> d) || (d != 0 && d != 1)) d = 0;  // lane order: optional fourth field
+      ctx->tuned[key] = {t, h, b, d};
+    }
   }
 }
 
@@ -826,7 +831,8 @@ void save_tune_file(cs_ctx *ctx) {
   if (ctx->tune_file.empty()) return;
   std::ofstream f(ctx->tune_file, std::ios::trunc);
   for (auto &kv : ctx->tuned)
-    f << kv.first << " " << kv.second[0] << " " << kv.second[1] << " " << kv.second[2] << "\n";
+    f << kv.first << " " << kv.second[0] << " " << kv.second[1] << " " << kv.second[2] << " "
+      << kv.second[3] << "\n";
 }
 
 int time_problem(cs_ctx *ctx, const cs_problem &pr, int reps, hipStream_t st, double *ms_out) {
@@ -1071,7 +1077,7 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
       // candidate order (the smaller canvas first, then the default budget),
       // so that near-equal candidates do not flip between runs.
       constexpr double kTuneSlack = 1.02;
-      std::vector<int> best = {kDefaultTile, kDefaultHalo, kDefaultBudget};
+      std::vector<int> best = {kDefaultTile, kDefaultHalo, kDefaultBudget, 0};
       const int tiles[] = {32, 40, 48, 56, 64, 96, 128};
       const int halos[] = {8, 10, 12, 14, 16, 24};
       std::vector<std::pair<double, std::vector<int>>> cand;
@@ -1082,10 +1088,11 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
           pr.opt.tile = T;
           pr.opt.halo = h;
           pr.opt.budget = kDefaultBudget;
+          pr.opt.lane_order = 0;
           double ms = 0;
           rc = time_problem(ctx, pr, reps, st, &ms);
           if (rc) break;
-          cand.push_back({ms, {T, h, kDefaultBudget}});
+          cand.push_back({ms, {T, h, kDefaultBudget, 0}});
         }
         if (rc) break;
       }
@@ -1111,6 +1118,16 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
         if (rc) break;
         if (ms * kTuneSlack < bud_ms) { bud_ms = ms; best[2] = bgt; }
       }
+      // stage 3: lane order at the chosen tile, halo and budget
+      if (rc == CS_OK) {
+        pr.opt.tile = best[0];
+        pr.opt.halo = best[1];
+        pr.opt.budget = best[2];
+        pr.opt.lane_order = 1;
+        double ms = 0;
+        rc = time_problem(ctx, pr, reps, st, &ms);
+        if (rc == CS_OK && ms * kTuneSlack < bud_ms) best[3] = 1;
+      }
       if (rc) break;
       hit = ctx->tuned.emplace(key, best).first;
       save_tune_file(ctx);
@@ -1118,6 +1135,7 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
     problems[i].opt.tile = hit->second[0];
     problems[i].opt.halo = hit->second[1];
     problems[i].opt.budget = hit->second[2];
+    problems[i].opt.lane_order = hit->second.size() > 3 ? hit->second[3] : 0;
   }
   ctx->timing = was_timing;
   if (rc == CS_OK) HIPCHK(hipStreamSynchronize(st));

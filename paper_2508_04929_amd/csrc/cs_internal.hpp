@@ -49,6 +49,7 @@ struct Geom {
   int budget;     // Gaussians per work item
   int scale_act;  // 0 exp, 1 softplus
   int amp_act;    // 0 identity, 1 softplus
+  int deal;       // 1: splat lanes take records in bank-dealt order
 };
 
 // One problem (mixture + its images) as seen by the persistent splat

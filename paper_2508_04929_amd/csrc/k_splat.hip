@@ -57,6 +57,93 @@ __device__ __forceinline__ int next_item(int *queue, int *slot) {
 }
 
 // ---------------------------------------------------------------------------
+// Dealing records to lanes.  Every lane walks its own Gaussian, so at a step
+// the lanes of a wave touch canvas words around their own centres; words of
+// equal address mod 64 fall into one LDS bank and serialise.  With rows of
+// S words, a lane's word at row i, column j sits in bank (S i + j) mod 64;
+// as all lanes step rows and columns together, the bank of lane l is
+// key_l + w_l + (a common offset), where key_l = (S i0_l + floor(u_l)) mod 64
+// (its first row and centre column) and w_l in {0, 1} the rounding of its
+// span start.  A chunk of kDealChunk records is therefore put in an order in
+// which every 64 consecutive records carry distinct keys, the first 32 even
+// keys and the last 32 odd keys: records are grouped by key, and round r
+// takes the r-th record of every group in the order 0, 2, ..., 62, 1, 3,
+// ..., 63 (a record's place is the size of the earlier rounds plus the
+// non-empty groups before its own in its round).  Within a half-wave the keys
+// then differ by at least 2, so the span-start rounding cannot make two lanes
+// meet.  The order only changes which lane takes which record: every result
+// is the same.  Groups of more than kDealRounds records keep the list order.
+// Dealing costs a pass over the chunk's records and pays where footprints
+// are wide (many steps per record); it is the launch option lane_order = 1,
+// chosen per problem by the autotuner.
+// ---------------------------------------------------------------------------
+constexpr int kDealChunk = 512;
+constexpr int kDealRounds = 32;
+
+struct DealLds {
+  unsigned long long M[kDealRounds];  // round r: groups with more than r records
+  int R[kDealRounds];                 // records in rounds before r
+  int cnt[64];
+  unsigned short perm[kDealChunk];    // place -> record (within the chunk)
+  int ok;
+};
+
+__device__ __forceinline__ void deal(const float4 *list, size_t base, int n, int S, int R0, int C0,
+                                     DealLds &d) {
+  const int t = threadIdx.x;
+  if (t < 64) d.cnt[t] = 0;
+  __syncthreads();
+  constexpr int kPer = kDealChunk / kBlock;
+  int key[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int g = t + j * kBlock;
+    key[j] = -1;
+    if (g < n) {
+      const float4 r0 = list[2 * (base + g)];
+      const int rows = __float_as_int(list[2 * (base + g) + 1].w);
+      const int k = (S * ((rows & 0xffff) - R0) + (int)floorf(r0.x) - C0) & 63;
+      const int grp = (k >> 1) | ((k & 1) << 5);  // even keys first, then odd
+      key[j] = (atomicAdd(&d.cnt[grp], 1) << 6) | grp;
+    }
+  }
+  __syncthreads();
+  if (t < 64) {  // one wave lays out the rounds
+    const int c = d.cnt[t];
+    int mx = c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    const bool ok = mx <= kDealRounds;
+    if (ok) {
+      int run = 0;
+      for (int r = 0; r < mx; ++r) {
+        const unsigned long long m = __ballot(c > r);
+        if (t == 0) {
+          d.M[r] = m;
+          d.R[r] = run;
+        }
+        run += __popcll(m);
+      }
+    }
+    if (t == 0) d.ok = ok;
+  }
+  __syncthreads();
+  const bool ok = d.ok;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (key[j] < 0) continue;
+    const int g = t + j * kBlock;
+    int pos = g;
+    if (ok) {
+      const int r = key[j] >> 6, grp = key[j] & 63;
+      pos = d.R[r] + __popcll(d.M[r] & ((1ull << grp) - 1ull));
+    }
+    d.perm[pos] = (unsigned short)g;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Forward: partial canvas of one work item.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
@@ -64,6 +151,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
   int *icanvas = (int *)smem4;        // C rows of stride S (fixed point)
   __shared__ int slot;
   __shared__ float wsum[kBlock / 64];
+  __shared__ DealLds dl;
   // drain the problems' queues in order: blocks that find one exhausted move on
   for (int p = 0; p < MP.count; ++p) {
   const Geom G = MP.p[p].G;
@@ -100,8 +188,12 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
     const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
     const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
     __syncthreads();  // canvas cleared
-    for (int g = threadIdx.x; g < itm.w; g += kBlock) {
-      const size_t rec = 2 * (size_t)(itm.z + g);
+    const int chunk = G.deal ? kDealChunk : itm.w;
+    for (int c0 = 0; c0 < itm.w; c0 += chunk) {
+    const int nc = min(chunk, itm.w - c0);
+    if (G.deal) deal(list, (size_t)itm.z + c0, nc, G.S, R0, C0, dl);
+    for (int s = threadIdx.x; s < nc; s += kBlock) {
+      const size_t rec = 2 * ((size_t)itm.z + c0 + (G.deal ? dl.perm[s] : s));
       const float4 r0 = list[rec], r1 = list[rec + 1];
       const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x, w = r1.y * scale;
       const int rows = __float_as_int(r1.w);
@@ -142,7 +234,8 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
         }
       }
     }
-    __syncthreads();
+    __syncthreads();  // the next chunk rewrites the order
+    }
     float *out = partials + (size_t)it * G.C * G.C;
     const float inv_c = 1.f / (float)G.C;
     for (int i = threadIdx.x; i < G.C * G.C; i += kBlock) {
@@ -317,6 +410,7 @@ k_big_add(const int *count, Geom G, const double *wscale, const long long *wq, f
 __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
   extern __shared__ float gq[];  // C rows of stride S
   __shared__ int slot;
+  __shared__ DealLds dl;
   for (int p = 0; p < MP.count; ++p) {
   const Geom G = MP.p[p].G;
   const float4 *list = MP.p[p].list;
@@ -342,8 +436,12 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
       gq[q] = (c < G.C && i >= 0 && i < G.D && j >= 0 && j < G.D) ? src[(size_t)i * G.D + j] : 0.f;
     }
     __syncthreads();
-    for (int g = threadIdx.x; g < itm.w; g += kBlock) {
-      const size_t rec = 2 * (size_t)(itm.z + g);
+    const int chunk = G.deal ? kDealChunk : itm.w;
+    for (int c0 = 0; c0 < itm.w; c0 += chunk) {
+    const int nc = min(chunk, itm.w - c0);
+    if (G.deal) deal(list, (size_t)itm.z + c0, nc, G.S, R0, C0, dl);
+    for (int s = threadIdx.x; s < nc; s += kBlock) {
+      const size_t rec = 2 * ((size_t)itm.z + c0 + (G.deal ? dl.perm[s] : s));
       const float4 r0 = list[rec], r1 = list[rec + 1];
       const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x;
       const int n = __float_as_int(r1.z);
@@ -411,7 +509,8 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
       float *o = mom + ((size_t)b * G.N + n) * 6;
       o[0] = m0; o[1] = m1; o[2] = m2; o[3] = m3; o[4] = m4; o[5] = m5;
     }
-    __syncthreads();
+    __syncthreads();  // the next chunk rewrites the order
+    }
   }
   }
 }

@@ -45,7 +45,7 @@ def main(out: str, reps: int = 5) -> None:
     for pr in probs:
         lib.autotune([pr], reps=reps)
         print(f"D={pr.D} N={pr.means.shape[0]} B={pr.rot.shape[0]}: tile {pr.options.tile} "
-              f"halo {pr.options.halo} budget {pr.options.budget}", flush=True)
+              f"halo {pr.options.halo} budget {pr.options.budget} lane order {pr.options.lane_order}", flush=True)
 
 
 if __name__ == "__main__":

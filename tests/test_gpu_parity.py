@@ -204,9 +204,11 @@ def test_mean_reduction_scales_gradients(gpu_lib):
 
 # ------------------------------------------------------------- invariances
 
-@pytest.mark.parametrize("tile,halo,budget", [(16, 8, 64), (32, 16, 256), (64, 8, 4096),
-                                              (128, 24, 512), (16, 1, 100)])
-def test_results_independent_of_launch_options(gpu_lib, tile, halo, budget):
+@pytest.mark.parametrize("tile,halo,budget,lane_order", [(16, 8, 64, 0), (32, 16, 256, 0),
+                                                         (64, 8, 4096, 0), (128, 24, 512, 0),
+                                                         (16, 1, 100, 0), (40, 12, 1024, 1),
+                                                         (64, 16, 2048, 1)])
+def test_results_independent_of_launch_options(gpu_lib, tile, halo, budget, lane_order):
     rng = np.random.default_rng(14)
     g = inputs.mixture_anisotropic(rng, 6000, 40.0)
     v = inputs.views(rng, 3, 128, 1.5, shift_px_sd=2.0)
@@ -214,9 +216,17 @@ def test_results_independent_of_launch_options(gpu_lib, tile, halo, budget):
     announce(f"options tile={tile} halo={halo} budget={budget}")
     base = gpu_lib.loss_and_grad(**mixture_args(g), **view_args(v), observed=dev(Y),
                                  ctf=ctf_arg(v), want_images=True)
-    opt = binding.Options(tile=tile, halo=halo, budget=budget)
+    opt = binding.Options(tile=tile, halo=halo, budget=budget, lane_order=lane_order)
     alt = gpu_lib.loss_and_grad(**mixture_args(g), **view_args(v), observed=dev(Y),
                                 ctf=ctf_arg(v), want_images=True, options=opt)
+    if lane_order:
+        # the lane order changes no arithmetic: identical bits to list order
+        ref = gpu_lib.loss_and_grad(**mixture_args(g), **view_args(v), observed=dev(Y),
+                                    ctf=ctf_arg(v), want_images=True,
+                                    options=binding.Options(tile=tile, halo=halo, budget=budget))
+        assert torch.equal(ref[2], alt[2]) and torch.equal(ref[0], alt[0])
+        for k in GROUPS:
+            assert torch.equal(ref[1][k], alt[1][k]), k
     assert per_image_normwise(host(alt[2]), host(base[2])) <= 1e-5
     for k in GROUPS:
         assert normwise(host(alt[1][k]), host(base[1][k])) <= 1e-4, k
