@@ -1072,7 +1072,7 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
     const std::string key = tune_key(pr);
     auto hit = ctx->tuned.find(key);
     if (hit == ctx->tuned.end()) {
-      // stage 1: tile x halo at the default budget; stage 2: budget.  Timings
+      // stage 1: tile x halo at the default budget in list order.  Timings
       // within kTuneSlack of the fastest count as ties, resolved by the fixed
       // candidate order (the smaller canvas first, then the default budget),
       // so that near-equal candidates do not flip between runs.
@@ -1097,15 +1097,35 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
         if (rc) break;
       }
       if (rc) break;
-      // smaller canvas (T + 2h) first, then the smaller tile
+      // stage 2: the dealt lane order for the four fastest tile x halo
+      // candidates (it shifts the balance towards larger canvases)
+      {
+        std::vector<std::pair<double, std::vector<int>>> fast = cand;
+        std::stable_sort(fast.begin(), fast.end(),
+                         [](const auto &a, const auto &b) { return a.first < b.first; });
+        for (size_t k = 0; k < fast.size() && k < 4 && rc == CS_OK; ++k) {
+          pr.opt.tile = fast[k].second[0];
+          pr.opt.halo = fast[k].second[1];
+          pr.opt.budget = kDefaultBudget;
+          pr.opt.lane_order = 1;
+          double ms = 0;
+          rc = time_problem(ctx, pr, reps, st, &ms);
+          cand.push_back({ms, {pr.opt.tile, pr.opt.halo, kDefaultBudget, 1}});
+        }
+      }
+      if (rc) break;
+      // ties: smaller canvas (T + 2h) first, then the smaller tile, list order first
       std::stable_sort(cand.begin(), cand.end(), [](const auto &a, const auto &b) {
         const int ca = a.second[0] + 2 * a.second[1], cb = b.second[0] + 2 * b.second[1];
-        return ca != cb ? ca < cb : a.second[0] < b.second[0];
+        if (ca != cb) return ca < cb;
+        if (a.second[0] != b.second[0]) return a.second[0] < b.second[0];
+        return a.second[3] < b.second[3];
       });
       double best_ms = 1e30;
       for (const auto &c : cand) best_ms = std::min(best_ms, c.first);
       for (const auto &c : cand)
         if (c.first <= kTuneSlack * best_ms) { best = c.second; best_ms = c.first; break; }
+      // stage 3: budget for the chosen tile, halo and lane order
       const int budgets[] = {256, 512, 1024, 4096, 8192};
       double bud_ms = best_ms;
       for (int bgt : budgets) {
@@ -1113,20 +1133,11 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
         pr.opt.tile = best[0];
         pr.opt.halo = best[1];
         pr.opt.budget = bgt;
+        pr.opt.lane_order = best[3];
         double ms = 0;
         rc = time_problem(ctx, pr, reps, st, &ms);
         if (rc) break;
         if (ms * kTuneSlack < bud_ms) { bud_ms = ms; best[2] = bgt; }
-      }
-      // stage 3: lane order at the chosen tile, halo and budget
-      if (rc == CS_OK) {
-        pr.opt.tile = best[0];
-        pr.opt.halo = best[1];
-        pr.opt.budget = best[2];
-        pr.opt.lane_order = 1;
-        double ms = 0;
-        rc = time_problem(ctx, pr, reps, st, &ms);
-        if (rc == CS_OK && ms * kTuneSlack < bud_ms) best[3] = 1;
       }
       if (rc) break;
       hit = ctx->tuned.emplace(key, best).first;

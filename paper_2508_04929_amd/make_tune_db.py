@@ -13,7 +13,7 @@ import os
 import sys
 
 
-def main(out: str, reps: int = 5) -> None:
+def main(out: str, reps: int = 3) -> None:
     if os.path.exists(out):
         os.remove(out)
     os.environ["CS_AUTOTUNE_CACHE"] = out   # fresh database, written by the library
