@@ -8,8 +8,9 @@
 // (iz - c0) p) and holds sum_n A_n (2 pi)^-3/2 det(Sigma_n)^-1/2
 // exp(-q_n / 2) over the Gaussians with q_n <= q_cut.  Bricks of 8^3 voxels:
 // every Gaussian is listed under the bricks its q <= q_cut box touches
-// (counting sort); a block evaluates one brick against its list, two voxels
-// per thread.  Each voxel's sum is kept as a 64-bit fixed-point integer
+// (counting sort); a block evaluates one brick against its list, one wave
+// per 4^3 sub-cube, each Gaussian only where a conservative bound of its
+// form over the sub-cube is within the cut.  Each voxel's sum is kept as a 64-bit fixed-point integer
 // (scale 2^e with the bound sum_n |w_n| < 2^61 / scale), so the result does
 // not depend on the order of the list: it is reproducible bit for bit.
 //
@@ -159,65 +160,119 @@ k_vox_fill(const int4 *box, VoxGeom V, const int *off, int *cursor, int *list) {
   }
 }
 
-// w 2^k as a 64-bit integer, truncated toward zero, read off the float's
-// bits (kb = k - 150 folds in the exponent bias and the mantissa width);
-// zero and subnormal w give 0.  Exact up to the truncation, and a function
-// of w alone, so the voxel sums do not depend on the order of their terms.
-__device__ __forceinline__ long long fixed_point(float w, int kb) {
+// w 2^k as a 64-bit integer, truncated toward zero (|w| 2^k < 2^61); zero
+// and subnormal w give 0.  Branch-free: y = |w| 2^k is exact (ldexp), its
+// part above 2^32 is trunc(y 2^-32) and the rest, y - hi 2^32, is exact too
+// (the bits of y below 2^32), so both convert exactly.  A function of w
+// alone, so the voxel sums do not depend on the order of their terms.
+__device__ __forceinline__ long long fixed_point(float w, int k) {
   const unsigned u = __float_as_uint(w);
-  const int e = (int)((u >> 23) & 255u);
-  const unsigned m = (u & 0x7fffffu) | 0x800000u;
-  const int sh = e + kb;
-  unsigned long long mag = sh >= 0 ? (unsigned long long)m << sh : (sh > -24 ? (unsigned long long)(m >> -sh) : 0ull);
-  mag = e ? mag : 0ull;
-  return (u >> 31) ? -(long long)mag : (long long)mag;
+  const float y = ldexpf(fabsf(w), k);
+  const float hi = truncf(y * 0x1p-32f);
+  const float lo = fmaf(hi, -0x1p32f, y);
+  unsigned long long mag = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
+  mag = (u & 0x7f800000u) ? mag : 0ull;
+  const long long sgn = (long long)((int)u >> 31);  // 0 or -1
+  return ((long long)mag ^ sgn) - sgn;
 }
 
-// One brick of 8^3 voxels per block, two voxels per thread (same x and y,
-// z two voxels apart, so the x-y part of the quadratic form is shared); its
-// Gaussians staged through LDS 256 at a time.
-__global__ void __launch_bounds__(256)
+// Lower bound of the scaled form over the voxel centres of a 4^3 sub-cube,
+// minus a rounding margin: with c the centre of the sub-cube, h = 1.5 p the
+// largest offset of a voxel centre from it along each axis and P the
+// (positive semi-definite) form, q(c + d) = q(c) + 2 d.P(c - mu) + d.P d
+// >= q(c) - h sum_k |2 (P(c - mu))_k|.  The margin T / 1024, with
+// T = sum_ij |P_ij| (|c_i - mu_i| + h)(|c_j - mu_j| + h) bounding every term
+// of q over the sub-cube, exceeds by far the rounding of both this bound and
+// the per-voxel evaluation (positions included), so a sub-cube whose bound
+// exceeds the cut holds no voxel that the per-voxel test would keep.
+__device__ __forceinline__ float subcube_bound(float4 a, float4 B, float4 C, float cx, float cy,
+                                               float cz, float h) {
+  const float dx = cx - a.x, dy = cy - a.y, dz = cz - a.z;
+  const float q = fmaf(dz, fmaf(C.y, dz, fmaf(B.z, dx, C.x * dy)),
+                       fmaf(fmaf(B.x, dx, B.y * dy), dx, B.w * dy * dy));
+  const float gx = fmaf(2.f * B.x, dx, fmaf(B.y, dy, B.z * dz));
+  const float gy = fmaf(B.y, dx, fmaf(2.f * B.w, dy, C.x * dz));
+  const float gz = fmaf(B.z, dx, fmaf(C.x, dy, 2.f * C.y * dz));
+  const float ax = fabsf(dx) + h, ay = fabsf(dy) + h, az = fabsf(dz) + h;
+  const float T = fabsf(B.x) * ax * ax + fabsf(B.w) * ay * ay + fabsf(C.y) * az * az +
+                  ax * (fabsf(B.y) * ay + fabsf(B.z) * az) + fabsf(C.x) * ay * az;
+  return q - h * (fabsf(gx) + fabsf(gy) + fabsf(gz)) - T * (1.f / 1024.f);
+}
+
+// One Gaussian's term at one voxel: the scaled form (mean, weight in a;
+// form in B, C), the cut and the fixed-point value of w 2^-q.
+__device__ __forceinline__ long long vox_term(float4 a, float4 B, float4 C, float px, float py,
+                                              float pz, float qc, int k) {
+  const float dx = px - a.x, dy = py - a.y;
+  const float cxy = fmaf(fmaf(B.x, dx, B.y * dy), dx, B.w * dy * dy);
+  const float fz = fmaf(B.z, dx, C.x * dy);
+  const float dz = pz - a.z;
+  const float q = fmaf(dz, fmaf(C.y, dz, fz), cxy);
+  const long long v = fixed_point(a.w * __builtin_amdgcn_exp2f(-q), k);
+  return q <= qc ? v : 0ll;
+}
+
+// One 4^3 sub-cube of a brick per wave (a workgroup of 64), one voxel per
+// lane.  The eight sub-cubes of brick k are the workgroups
+// 64 (k / 8) + 8 s + k % 8, s = 0 .. 7: workgroups are dealt to the eight
+// XCDs in turn, so all eight land on the XCD of k % 8 and share its L2 for
+// the brick's list and records.  The wave takes the list 64 Gaussians at a
+// time: each lane loads one record and tests it against the sub-cube, the
+// kept ones are staged in LDS, and the wave evaluates them one ballot bit
+// at a time (two per pass).  The per-voxel arithmetic (form, cut, exp2,
+// fixed point) is the same for every kept Gaussian whatever the order, and
+// the sums are integers, so the result is that of evaluating every listed
+// Gaussian at every voxel of the brick.
+__global__ void __launch_bounds__(64)
 k_vox_eval(const float4 *rec, const int *list, const int *off, VoxGeom V, const double *scale,
            float *vol) {
-  __shared__ float4 sr[3][256];
-  const int k = blockIdx.x;
+  __shared__ float4 sr[3][64];
+  const int b = blockIdx.x;
+  const int k = (b >> 6) * 8 + (b & 7), s = (b >> 3) & 7;
+  if (k >= V.nb * V.nb * V.nb) return;
   const int bx = k % V.nb, by = (k / V.nb) % V.nb, bz = k / (V.nb * V.nb);
-  const int t = threadIdx.x;
-  const int ix = bx * kBrick + (t & 7), iy = by * kBrick + ((t >> 3) & 7);
-  const int iz0 = bz * kBrick + (t >> 6), iz1 = iz0 + 4;
+  const int lane = threadIdx.x;
+  const int sx = bx * kBrick + 4 * (s & 1), sy = by * kBrick + 4 * ((s >> 1) & 1),
+            sz = bz * kBrick + 4 * (s >> 2);
+  const int ix = sx + (lane & 3), iy = sy + ((lane >> 2) & 3), iz = sz + (lane >> 4);
   const float px = (float)(ix - V.c0) * V.pixel, py = (float)(iy - V.c0) * V.pixel;
-  const float pz0 = (float)(iz0 - V.c0) * V.pixel, pz1 = (float)(iz1 - V.c0) * V.pixel;
+  const float pz = (float)(iz - V.c0) * V.pixel;
+  const float h = 1.5f * V.pixel;
+  const float cx = ((float)(sx - V.c0) + 1.5f) * V.pixel, cy = ((float)(sy - V.c0) + 1.5f) * V.pixel,
+              cz = ((float)(sz - V.c0) + 1.5f) * V.pixel;
   const double S = *scale;
   int k2;
   frexp(S, &k2);
-  const int kb = (k2 - 1) - 150;            // S = 2^(k2 - 1)
+  const int kk = k2 - 1;                    // S = 2^(k2 - 1)
   const float qc = V.q_cut * 0.72134752f;   // the cut in the scaled form
   long long acc0 = 0, acc1 = 0;
   const int b0 = off[k], cnt = off[k + 1] - b0;
-  for (int c = 0; c < cnt; c += 256) {
-    if (c + t < cnt) {
-      const int n = list[b0 + c + t];
-      sr[0][t] = rec[3 * n];
-      sr[1][t] = rec[3 * n + 1];
-      sr[2][t] = rec[3 * n + 2];
+  for (int c = 0; c < cnt; c += 64) {
+    bool keep = false;
+    if (c + lane < cnt) {
+      const int n = list[b0 + c + lane];
+      const float4 a = rec[3 * n], B = rec[3 * n + 1], C = rec[3 * n + 2];
+      keep = subcube_bound(a, B, C, cx, cy, cz, h) <= qc;
+      sr[0][lane] = a;
+      sr[1][lane] = B;
+      sr[2][lane] = C;
     }
     __syncthreads();
-    const int m = min(256, cnt - c);
-    for (int j = 0; j < m; ++j) {
-      const float4 a = sr[0][j], B = sr[1][j], C = sr[2][j];
-      const float dx = px - a.x, dy = py - a.y;
-      const float cxy = fmaf(fmaf(B.x, dx, B.y * dy), dx, B.w * dy * dy);
-      const float cz = fmaf(B.z, dx, C.x * dy);
-      const float dz0 = pz0 - a.z, dz1 = pz1 - a.z;
-      const float q0 = fmaf(dz0, fmaf(C.y, dz0, cz), cxy);
-      const float q1 = fmaf(dz1, fmaf(C.y, dz1, cz), cxy);
-      if (q0 <= qc) acc0 += fixed_point(a.w * __builtin_amdgcn_exp2f(-q0), kb);
-      if (q1 <= qc) acc1 += fixed_point(a.w * __builtin_amdgcn_exp2f(-q1), kb);
+    unsigned long long bits = __ballot(keep);
+    while (bits) {  // two kept Gaussians per pass: independent chains
+      const int j0 = __builtin_ctzll(bits);
+      bits &= bits - 1ull;
+      const bool two = bits != 0ull;
+      const int j1 = two ? __builtin_ctzll(bits) : j0;
+      bits &= bits - 1ull;
+      const long long t0 = vox_term(sr[0][j0], sr[1][j0], sr[2][j0], px, py, pz, qc, kk);
+      const long long t1 = vox_term(sr[0][j1], sr[1][j1], sr[2][j1], px, py, pz, qc, kk);
+      acc0 += t0;
+      acc1 += two ? t1 : 0ll;
     }
     __syncthreads();
   }
-  vol[((int64_t)iz0 * V.D + iy) * V.D + ix] = (float)((double)acc0 / S);
-  vol[((int64_t)iz1 * V.D + iy) * V.D + ix] = (float)((double)acc1 / S);
+  vol[((int64_t)iz * V.D + iy) * V.D + ix] = (float)((double)(acc0 + acc1) / S);
 }
 
 // ---------------------------------------------------------------------------

@@ -92,7 +92,9 @@ int cs_voxelize(cs_ctx *ctx, const cs_gaussians *g, int32_t D, float pixel, floa
   if (N > 0 && total > 0)
     TLAUNCH(k_vox_fill, dim3(cdivv(N, 4)), dim3(256), 0, st, (const int4 *)(w + o_box), V, off,
             (int *)(w + o_cur), list);
-  TLAUNCH(k_vox_eval, dim3(nbr), dim3(256), 0, st, rec, (const int *)list, off, V, scale, vol);
+  // one 64-lane workgroup per 4^3 sub-cube, eight per brick (XCD-aware order)
+  TLAUNCH(k_vox_eval, dim3(cdivv(nbr, 8) * 64), dim3(64), 0, st, rec, (const int *)list, off, V,
+          scale, vol);
   return CS_OK;
 }
 

@@ -61,6 +61,55 @@ def test_voxelize_signed_amplitudes(gpu_lib):
     assert normwise(V, ref) <= 1e-4
 
 
+@pytest.mark.parametrize("D,p,seed", [(96, 1.0, 61), (64, 0.7, 62)])
+def test_voxelize_cut_per_voxel(gpu_lib, D, p, seed):
+    """The truncation q <= q_cut voxel by voxel.  Isolated Gaussians (one
+    per cell of a lattice wider than twice the largest cut radius), so that
+    every voxel holds at most one term; anisotropic (axis ratios up to ~11),
+    randomly oriented, signed, placed at random offsets so that their
+    ellipsoids cross brick and sub-brick faces at every angle, plus
+    sub-voxel ones.  A dropped term inside the cut (its value there is down
+    to 1e-6 of the peak, invisible to a normwise bar) or a kept one beyond
+    it fails: each voxel must lie between the oracle's densities cut at
+    q_cut (1 - 1e-3) and at q_cut (1 + 1e-3), to 1e-3 relative."""
+    rng = np.random.default_rng(seed)
+    cell = 24 if D == 96 else 16
+    r_max = 0.35 * cell * p / np.sqrt(Q_MATCHED)     # largest scale: cut radius 0.35 cell
+    k = D // cell
+    ax = (np.arange(k) + 0.5) * cell - D // 2
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    centres = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1) * p
+    n = len(centres)
+    means = centres + rng.uniform(-0.05, 0.05, (n, 3)) * cell * p
+    log_scales = rng.uniform(np.log(0.2 * r_max), np.log(r_max), (n, 3))
+    tiny = rng.random(n) < 0.15
+    log_scales[tiny] = rng.uniform(np.log(0.02 * p), np.log(0.3 * p), (int(tiny.sum()), 3))
+    amps = np.exp(0.5 * rng.standard_normal(n)) * np.where(rng.random(n) < 0.3, -1.0, 1.0)
+    g = inputs.Mixture(means.astype(np.float32), log_scales.astype(np.float32),
+                       inputs.haar_quaternions(rng, n).astype(np.float32), amps.astype(np.float32))
+    announce(f"voxelise {n} isolated Gaussians, D={D}, p={p}: the cut per voxel")
+    V = host(_vox(gpu_lib, g, D, p)).astype(np.float64)
+    covered = np.zeros((D, D, D), dtype=bool)
+    half = cell // 2
+    for i in range(n):
+        c = np.rint(centres[i] / p).astype(int) + D // 2     # lattice cell centre (x, y, z)
+        lo, hi = c - half, c + half
+        idx = np.stack(np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]),
+                                   np.arange(lo[0], hi[0]), indexing="ij"), -1).reshape(-1, 3)
+        pts = o_vol.voxel_points(D, p, idx)
+        one = inputs.Mixture(g.means[i:i + 1], g.log_scales[i:i + 1], g.quats[i:i + 1],
+                             g.amps[i:i + 1])
+        inner = o_vol.density_at(one, pts, q_cut=Q_MATCHED * (1 - 1e-3))
+        outer = o_vol.density_at(one, pts, q_cut=Q_MATCHED * (1 + 1e-3))
+        got = V[idx[:, 0], idx[:, 1], idx[:, 2]]
+        lo_b = np.minimum(inner, outer) - 1e-3 * np.abs(outer)
+        hi_b = np.maximum(inner, outer) + 1e-3 * np.abs(outer)
+        bad = (got < lo_b) | (got > hi_b)
+        assert not bad.any(), (i, int(bad.sum()), idx[bad][:3], got[bad][:3], inner[bad][:3], outer[bad][:3])
+        covered[idx[:, 0], idx[:, 1], idx[:, 2]] = True
+    assert np.all(V[~covered] == 0.0)
+
+
 def test_voxelize_is_exact_and_order_free(gpu_lib):
     rng = np.random.default_rng(54)
     g = inputs.mixture_anisotropic(rng, 3000, 20.0)
