@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import objective, trainer as o_tr, volume as o_vol
+from oracle import adam as o_adam, objective, trainer as o_tr, volume as o_vol
 from paper_2508_04929_amd import binding, inputs, trainer
 
 from gpu_util import announce, ctf_arg, dev, host, normwise
@@ -113,6 +113,74 @@ def test_training_steps_match_oracle(gpu_lib):
     announce(f"  max |param - oracle| = {diff.max():.2e}; outside 1e-3 lr steps: {np.sum(~close)} of {diff.size}")
     assert np.all(diff <= 2.0 * lr0 * steps)
     assert np.mean(close) >= 0.98
+
+
+def _adam_dir(g, m, v, t, b1=0.9, b2=0.999, eps=1e-8):
+    """m_hat / (sqrt(v_hat) + eps) of one Adam step from moments (m, v) with
+    gradient g (broadcast over a trailing axis of candidate gradients)."""
+    mm = b1 * m[..., None] + (1 - b1) * g
+    vv = b2 * v[..., None] + (1 - b2) * g * g
+    return (mm / (1 - b1 ** t)) / (np.sqrt(vv / (1 - b2 ** t)) + eps)
+
+
+def test_training_steps_teacher_forced(gpu_lib):
+    """Every one of 12 batch-1 steps against one oracle step taken from the
+    GPU's own state (parameters and Adam moments read back before the step),
+    so errors cannot accumulate and every step is bounded.  The bound per
+    parameter follows from the gradient bar: with the GPU gradient within
+    1e-3 of the oracle's, normwise per parameter group, each component may
+    differ by up to delta = 1e-3 ||g_group||, and Adam then moves it by
+    lr (u(g') - u(g)) for some g' in [g - delta, g + delta], u(g) =
+    m_hat / (sqrt(v_hat) + eps); the test takes the largest such change over
+    that interval (densely sampled, plus the stationary point of u), plus
+    FP32 rounding of the parameter.  Where the gradient is far above delta
+    this is a small fraction of lr; only components with |g| of order delta
+    (Adam's sign decided by rounding) get up to ~2 lr."""
+    rng, g, v, Y = _problem(75)
+    orders = [rng.permutation(6), rng.permutation(6)]
+    lr0, gamma = 1e-3, 0.5
+    n = g.n
+    groups = [slice(0, 3 * n), slice(3 * n, 6 * n), slice(6 * n, 10 * n), slice(10 * n, 11 * n)]
+    p = dev(_flat(g))
+    m, vv = torch.zeros_like(p), torch.zeros_like(p)
+    Yd, rot = dev(Y), dev(v.rot)
+    ctf = ctf_arg(v)
+    announce("12 batch-1 training steps, each against an oracle step from the GPU state")
+    k, worst = 0, 0.0
+    for e, order in enumerate(orders):
+        lr = o_tr.learning_rate(lr0, gamma, e)
+        for i in order:
+            th = host(p).astype(np.float64)
+            m0, v0 = host(m).astype(np.float64), host(vv).astype(np.float64)
+            gpu_lib.train_sequential(p, m, vv, Yd, rot, v.pixel, np.array([i]), k, lr, ctf=ctf,
+                                     options=binding.Options(graph=0))
+            got = host(p).astype(np.float64)
+            st = o_tr.State(th[:3 * n].reshape(n, 3), th[3 * n:6 * n].reshape(n, 3),
+                            th[6 * n:10 * n].reshape(n, 4), th[10 * n:])
+            f = objective.loss_and_grad(st.mixture(), _one(v, int(i)), Y[int(i)][None],
+                                        q_cut=Q_MATCHED, reduction="sum", scale_act="softplus",
+                                        amp_act="softplus", use_ctf=True)
+            gr = np.concatenate([np.asarray(f["grads"][c], dtype=np.float64).ravel()
+                                 for c in ("means", "log_scales", "quats", "amps")])
+            t = k + 1
+            ref, _, _ = o_adam.adam_step(th, gr, m0, v0, t, lr=lr)
+            delta = np.empty_like(gr)
+            for sl in groups:
+                delta[sl] = 1e-3 * np.linalg.norm(gr[sl])
+            cand = gr[:, None] + delta[:, None] * np.linspace(-1.0, 1.0, 65)[None, :]
+            b1, b2 = 0.9, 0.999
+            with np.errstate(divide="ignore", invalid="ignore"):
+                gs = (1 - b1) * b2 * v0 / (b1 * m0 * (1 - b2))  # stationary point of u
+            gs = np.where(np.isfinite(gs) & (np.abs(gs - gr) <= delta), gs, gr)
+            cand = np.concatenate([cand, gs[:, None]], axis=1)
+            u0 = _adam_dir(gr[:, None], m0, v0, t)[:, 0]
+            spread = np.abs(_adam_dir(cand, m0, v0, t) - u0[:, None]).max(axis=1)
+            bound = lr * spread * 1.01 + 4 * np.finfo(np.float32).eps * (np.abs(ref) + lr)
+            err = np.abs(got - ref)
+            assert np.all(err <= bound), (k, int(np.argmax(err - bound)), float(err.max()))
+            worst = max(worst, float((err / lr).max()))
+            k += 1
+    announce(f"  largest step deviation {worst:.2e} lr")
 
 
 def test_graph_eager_and_stepwise_are_bitwise_equal(gpu_lib):
