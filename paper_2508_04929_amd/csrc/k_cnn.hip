@@ -1,6 +1,7 @@
 // Pose-proposal network kernels: BF16 MFMA GEMMs for 3x3 stride-2 convs
-// (forward, data gradient, weight gradient) and linear layers, a VALU kernel
-// for the single-channel first conv, the 6-D -> SO(3) head and its loss.
+// (forward, data gradient, weight gradient) and linear layers, a
+// 16x16x16 MFMA kernel for the single-channel first conv (its 9 taps padded
+// to K = 16), the 6-D -> SO(3) head and its loss.
 //
 // Activations are NHWC BF16 ([B][H][W][C]); weights are [Cout][ky][kx][Cin]
 // BF16 with FP32 masters.  Every GEMM accumulates in FP32 with
@@ -12,6 +13,7 @@
 namespace cs {
 
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 __device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float((unsigned)v << 16); }
@@ -484,39 +486,67 @@ __global__ void k_sum_into(const float *part, int n, float *out) {
 }
 
 // ---------------------------------------------------------------------------
-// First conv (Cin = 1): VALU.  One thread per (output pixel, 32 channels).
+// First conv (Cin = 1) on MFMA (v_mfma_f32_16x16x16_bf16): output rows = 16
+// channels, columns = 16 output pixels, K = the 9 taps padded with zeros to
+// 16.  Lane l holds taps 4 (l >> 4) .. 4 (l >> 4) + 3 of channel (A) or
+// pixel (B) l & 15; its result rows are the four consecutive channels
+// 4 (l >> 4) .. + 3 of pixel l & 15.  The accumulator starts at the bias.
+// The inference kernel below computes the first layer with these same
+// fragments, so both produce the same bits.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bf16x4 conv1_wfrag(const bf16 *w, int Cout, int c0, int lane) {
+  const int c = c0 + (lane & 15), kq = 4 * (lane >> 4);
+  bf16x4 f;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) f[e] = (c < Cout && kq + e < 9) ? (short)w[c * 9 + kq + e] : (short)0;
+  return f;
+}
+
+__device__ __forceinline__ f32x4 conv1_bias(const float *bias, int Cout, int c0, int lane) {
+  f32x4 b;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int c = c0 + 4 * (lane >> 4) + r;
+    b[r] = (bias && c < Cout) ? bias[c] : 0.f;
+  }
+  return b;
+}
+
+// One wave per 16 output pixels, all channel tiles; Cout a multiple of 8.
 __global__ void __launch_bounds__(256)
 k_conv1_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int Hi, int Wi, int Cout,
             int relu, bf16 *out, float *out32) {
-  __shared__ float ws[256 * 9 + 256];  // weights [Cout][9] and biases (Cout <= 256)
-  for (int q = threadIdx.x; q < Cout * 9; q += 256) ws[q] = bf2f(w[q]);
-  for (int q = threadIdx.x; q < Cout; q += 256) ws[Cout * 9 + q] = bias ? bias[q] : 0.f;
-  __syncthreads();
+  const int lane = threadIdx.x & 63;
   const int Ho = Hi / 2, Wo = Wi / 2;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= (int64_t)B * Ho * Wo) return;
-  const int ox = (int)(p % Wo), t = (int)(p / Wo), oy = t % Ho, b = t / Ho;
-  float x[9];
+  const int64_t np = (int64_t)B * Ho * Wo;
+  const int64_t p = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + (lane & 15);
+  const bool live = p < np;
+  const int kq = 4 * (lane >> 4);
+  bf16x4 x;
+  {
+    const int64_t pc = live ? p : 0;
+    const int ox = (int)(pc % Wo), t = (int)(pc / Wo), oy = t % Ho, b = t / Ho;
 #pragma unroll
-  for (int tap = 0; tap < 9; ++tap) {
-    const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
-    x[tap] = (iy >= 0 && iy < Hi && ix >= 0 && ix < Wi) ? bf2f(in[((size_t)b * Hi + iy) * Wi + ix]) : 0.f;
-  }
-  // 8 channels per 16-byte store (Cout is a multiple of 8)
-  for (int c0 = 0; c0 < Cout; c0 += 8) {
-    Vec8 o;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int co = c0 + e;
-      float s = ws[Cout * 9 + co];
-#pragma unroll
-      for (int tap = 0; tap < 9; ++tap) s = __fmaf_rn(ws[co * 9 + tap], x[tap], s);
-      if (relu) s = fmaxf(s, 0.f);
-      if (out32) out32[p * Cout + co] = s;
-      o.h[e] = f2bf(s);
+    for (int e = 0; e < 4; ++e) {
+      const int tap = kq + e;
+      const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+      x[e] = (tap < 9 && iy >= 0 && iy < Hi && ix >= 0 && ix < Wi)
+                 ? (short)in[((size_t)b * Hi + iy) * Wi + ix] : (short)0;
     }
-    *(uint4 *)&out[p * Cout + c0] = o.u;
+  }
+  for (int c0 = 0; c0 < Cout; c0 += 16) {
+    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(conv1_wfrag(w, Cout, c0, lane), x,
+                                                          conv1_bias(bias, Cout, c0, lane), 0, 0, 0);
+    const int c = c0 + kq;  // four consecutive channels of pixel p
+    if (!live || c >= Cout) continue;
+    bf16x4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float v = relu ? fmaxf(acc[r], 0.f) : acc[r];
+      if (out32) out32[p * Cout + c + r] = v;
+      o[r] = (short)f2bf(v);
+    }
+    *(bf16x4 *)&out[p * Cout + c] = o;
   }
 }
 
@@ -554,8 +584,8 @@ k_conv1_wgrad(const bf16 *in, const bf16 *dpre, int B, int Hi, int Wi, int Cout,
 // Inference: the first two convolutions fused (C1 = 32 first-layer channels,
 // C2 = 64 second-layer channels).  A block owns 8 x 16 second-layer output
 // pixels of one image: it stages the 35 x 67 input patch, computes the
-// 17 x 33 x 32 first-layer patch once into LDS (same fma order and bfloat16
-// rounding as k_conv1_fwd, so the values are identical), then runs the second
+// 17 x 33 x 32 first-layer patch once into LDS (the MFMA fragments of
+// k_conv1_fwd, so the values are identical), then runs the second
 // layer on MFMA with A fragments read from the LDS patch (im2col addressing,
 // one tap per K slice of 32 channels) and B fragments (weights) loaded from
 // global memory straight into registers.  The first layer's activation never
@@ -583,16 +613,9 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
 #pragma unroll
   for (int t = 0; t < 9; ++t)
     bw[t] = *(const bf16x8 *)&w2[(size_t)(wv * 16 + (lane & 15)) * 288 + t * 32 + cq];
-  // a thread always computes first-layer channels [c0, c0 + 8): their
-  // weights and biases stay in registers
-  const int c0 = (tid & 3) * 8;
-  float wr[8][9], br[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    br[e] = b1 ? b1[c0 + e] : 0.f;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) wr[e][t] = bf2f(w1[(c0 + e) * 9 + t]);  // w1 [c][tap]
-  }
+  // first-layer weight fragments and biases of the two channel tiles
+  const bf16x4 wf0 = conv1_wfrag(w1, 32, 0, lane), wf1 = conv1_wfrag(w1, 32, 16, lane);
+  const f32x4 bf0 = conv1_bias(b1, 32, 0, lane), bf1 = conv1_bias(b1, 32, 16, lane);
   // input patch rows 4 oy0 - 3 .., columns 4 ox0 - 3 .. 4 ox0 + 63: 16-byte
   // loads of the aligned columns 4 ox0 - 8 .. 4 ox0 + 63 (9 per row)
   const int iy0 = 4 * oy0 - 3, cx0 = 4 * ox0 - 8;
@@ -609,30 +632,37 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
     }
   }
   __syncthreads();
-  // first layer at patch positions (y, x) = first-layer rows 2 oy0 - 1 + y, columns 2 ox0 - 1 + x
-  for (int pos = tid >> 2; pos < C12_PY * C12_PX; pos += 64) {
-    const int y = pos / C12_PX, x = pos - y * C12_PX;
-    const int y1 = 2 * oy0 - 1 + y, x1 = 2 * ox0 - 1 + x;
-    Vec8 o;
-    if (y1 < 0 || y1 >= H1 || x1 < 0 || x1 >= H1) {
-      o.u = make_uint4(0, 0, 0, 0);
-    } else {
-      float xv[9];
+  // first layer at patch positions (y, x) = first-layer rows 2 oy0 - 1 + y,
+  // columns 2 ox0 - 1 + x: 16 positions per MFMA column tile, wave wv takes
+  // tiles wv, wv + 4, ...; positions outside the first-layer image are 0
+  {
+    const int kq = 4 * (lane >> 4);
+    for (int tile = wv; tile * 16 < C12_PY * C12_PX; tile += 4) {
+      const int pos = tile * 16 + (lane & 15);
+      const int pc = min(pos, C12_PY * C12_PX - 1);
+      const int y = pc / C12_PX, x = pc - y * C12_PX;
+      bf16x4 xf;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) xv[t] = xin[(2 * y + t / 3) * C12_IX + 2 * x + t % 3];
+      for (int e = 0; e < 4; ++e) {
+        const int tap = kq + e;
+        xf[e] = tap < 9 ? (short)f2bf(xin[(2 * y + tap / 3) * C12_IX + 2 * x + tap % 3]) : (short)0;
+      }
+      const f32x4 r0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf0, xf, bf0, 0, 0, 0);
+      const f32x4 r1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf1, xf, bf1, 0, 0, 0);
+      if (pos < C12_PY * C12_PX) {
+        const int y1 = 2 * oy0 - 1 + y, x1 = 2 * ox0 - 1 + x;
+        const bool in_img = y1 >= 0 && y1 < H1 && x1 >= 0 && x1 < H1;
+        bf16x4 o0, o1;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        float acc = br[e];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc = __fmaf_rn(wr[e][t], xv[t], acc);
-        o.h[e] = f2bf(fmaxf(acc, 0.f));
+        for (int r = 0; r < 4; ++r) {
+          o0[r] = in_img ? (short)f2bf(fmaxf(r0[r], 0.f)) : (short)0;
+          o1[r] = in_img ? (short)f2bf(fmaxf(r1[r], 0.f)) : (short)0;
+        }
+        *(bf16x4 *)&a1[pos * C12_PS + kq] = o0;
+        *(bf16x4 *)&a1[pos * C12_PS + 16 + kq] = o1;
       }
     }
-    uint2 *dst = (uint2 *)&a1[pos * C12_PS + c0];
-    dst[0] = make_uint2(o.u.x, o.u.y);
-    dst[1] = make_uint2(o.u.z, o.u.w);
   }
-  __syncthreads();
   // second layer: MFMA row tiles i = pixels [16 i, 16 i + 16) of the 8 x 16
   // tile (one output row each), columns = this wave's 16 channels
   f32x4 acc[8];
@@ -873,7 +903,7 @@ hipError_t conv_fwd(const bf16 *in, const bf16 *w, const float *bias, int B, int
                     int Cin, int Cout, int relu, bf16 *out, float *out32, hipStream_t st) {
   if (Cin == 1) {
     const int64_t np = (int64_t)B * (Hi / 2) * (Wi / 2);
-    hipLaunchKernelGGL(k_conv1_fwd, dim3(cdiv_(np, 256)), dim3(256), 0, st, in, w, bias, B, Hi, Wi,
+    hipLaunchKernelGGL(k_conv1_fwd, dim3(cdiv_(np, 64)), dim3(256), 0, st, in, w, bias, B, Hi, Wi,
                        Cout, relu, out, out32);
     return hipGetLastError();
   }

@@ -39,20 +39,25 @@ def hb(t):
 def check_bf16_rounding(got_bf16, ref64, max_frac=1e-3):
     """Stored bfloat16 values vs the FP64 value rounded to bfloat16.
 
-    A mismatch is allowed on a small fraction of elements, by at most one
-    bfloat16 ulp plus the FP32 accumulation error (1e-5 of the tensor's
-    largest magnitude, the normwise bar of the FP32 outputs): near-zero
-    results of cancelling sums carry that absolute error, however small
-    their own ulp."""
+    Every mismatch must be by at most one bfloat16 ulp plus the FP32
+    accumulation error (1e-5 of the tensor's largest magnitude, the normwise
+    bar of the FP32 outputs): near-zero results of cancelling sums carry that
+    absolute error, however small their own ulp.  A mismatch whose FP64
+    value lies within that error (or 1e-5 of itself) of the rounding boundary
+    between the two bfloat16 neighbours is a rounding decided by the FP32
+    error and always allowed; the others may be at most a max_frac fraction
+    of the elements."""
     ref64 = np.asarray(ref64, dtype=np.float64)
     ref = cnn.round_bf16(ref64)
     got = hb(got_bf16)
     diff = got != ref
-    assert diff.mean() <= max_frac, diff.mean()
     if diff.any():
         ulp = np.abs(ref[diff]) * 2.0 ** -7
         acc = 1e-5 * np.abs(ref64).max()
         assert np.all(np.abs(got[diff] - ref64[diff]) <= 1.01 * ulp + acc)
+        mid = 0.5 * (got[diff] + ref[diff])
+        tie = np.abs(ref64[diff] - mid) <= acc + 1e-5 * np.abs(ref64[diff])
+        assert (~tie).sum() <= max_frac * diff.size, ((~tie).sum(), diff.size)
 
 
 @pytest.mark.parametrize("B,H,W,Cin,Cout", [(3, 34, 34, 40, 72), (2, 66, 66, 1, 32),
