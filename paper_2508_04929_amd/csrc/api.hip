@@ -371,7 +371,7 @@ int launch_binning(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   TLAUNCH(k_scan, dim3(1), dim3(1024), 0, st, count, G, (int *)(ws + L.off),
           (int4 *)(ws + L.items), (int *)(ws + L.item_off), (int *)(ws + L.n_items),
           (int *)(ws + L.queues), fuse ? (int *)(ws + L.blk) : (int *)nullptr, L.nbx);
-  TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), (size_t)(kBlock / 64) * G.K * 4, st, gc, P.v.rot,
+  TLAUNCH(k_bin_scatter, bgrid, dim3(kBlock), (size_t)(kBlock / 64) * G.K * 8, st, gc, P.v.rot,
           P.v.shift, G, (const int *)(ws + L.key), (const int *)(ws + L.off),
           (const int *)(ws + L.blk), L.nbx, (float4 *)(ws + L.list), (float *)(ws + L.wabs));
   return CS_OK;

@@ -247,12 +247,14 @@ k_scan(int *count, Geom G, int *off, int4 *items, int *item_off, int *n_items,
 // row range of the q_cut ellipse.  The position is the bin offset plus the
 // block's scanned offset plus the stable rank inside the block, so every
 // bin lists its Gaussians in increasing index (a deterministic counting
-// sort; no device atomics).
+// sort; the rank inside the block comes from per-wave LDS bitmasks of the
+// lanes holding each bin, and no device-memory atomics are used).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
 k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, const int *key,
               const int *off, const int *blk, int nbx, float4 *list, float *wabs) {
-  extern __shared__ int wcnt[];  // [kBlock/64][K] per-wave bin counts
+  // [kBlock/64][K]: per wave and bin, the lanes holding that bin
+  extern __shared__ unsigned long long wmask[];
   const int n = blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int b0 = blockIdx.y * kImgPerBinBlock;
@@ -266,23 +268,16 @@ k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, co
   for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
     const int b = b0 + bi;
     if (b >= G.B) break;
-    for (int i = threadIdx.x; i < (kBlock / 64) * G.K; i += kBlock) wcnt[i] = 0;
+    for (int i = threadIdx.x; i < (kBlock / 64) * G.K; i += kBlock) wmask[i] = 0ull;
     __syncthreads();
     const int k = (n < G.N) ? key[(size_t)b * G.N + n] : -1;
-    // stable rank among the lanes of this wave with the same bin
-    int rank = 0;
-    unsigned long long active = __ballot(k >= 0);
-    while (active) {
-      const int leader = __ffsll((long long)active) - 1;
-      const int kk = __shfl(k, leader, 64);
-      const unsigned long long m = __ballot(k == kk) & active;
-      if (k == kk) rank = __popcll(m & below);
-      if (lane == leader) wcnt[wid * G.K + kk] = __popcll(m);
-      active &= ~m;
-    }
+    if (k >= 0) atomicOr(&wmask[wid * G.K + k], 1ull << lane);
     __syncthreads();
     if (k >= 0) {
-      for (int w = 0; w < wid; ++w) rank += wcnt[w * G.K + k];
+      // stable rank: same-bin lanes below this one in its wave, then the
+      // same-bin lanes of the earlier waves
+      int rank = __popcll(wmask[wid * G.K + k] & below);
+      for (int w = 0; w < wid; ++w) rank += __popcll(wmask[w * G.K + k]);
       const int e = b * G.K + k;
       const int pos = off[e] + blk[(size_t)e * nbx + blockIdx.x] + rank;
       float p0[3], p1[3], tx, ty;
