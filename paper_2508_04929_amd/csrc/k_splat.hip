@@ -467,8 +467,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
         //   a0 = sum t_k, a1 = sum t_k (M-k), a2 = sum t_k (M-k)(M-k+1)/2
         float a0 = 0.f, a1 = 0.f, a2 = 0.f;
         const int L4 = L & ~3;
-        int k = 0;
-        for (; k < L4; k += 4) {
+        for (int k = 0; k < L4; k += 4) {
           const float g0 = px[k], g1 = px[k + 1], g2 = px[k + 2], g3 = px[k + 3];
           float t = g0 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
@@ -480,13 +479,14 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
           a0 += t; a1 += a0; a2 += a1;
         }
         int M = L4;
-        if (k < L) {
-          // 1 to 3 trailing pixels as three steps with G_Q = 0 past the span
-          // (the reads stay inside the row: spans end at column C - 1 of a
-          // row of stride C + 4)
-          const float g0 = px[k];
-          const float g1 = k + 1 < L ? px[k + 1] : 0.f;
-          const float g2 = k + 2 < L ? px[k + 2] : 0.f;
+        if (L4 < L) {
+          // 1 to 3 trailing pixels as three steps with G_Q = 0 past the span.
+          // The three reads are unconditional: the span ends at column C - 1
+          // at most, so they reach column C + 1 at most, inside the row of
+          // stride C + 4.
+          const float g0 = px[L4], h1 = px[L4 + 1], h2 = px[L4 + 2];
+          const float g1 = L4 + 1 < L ? h1 : 0.f;
+          const float g2 = L4 + 2 < L ? h2 : 0.f;
           float t = g0 * e; e *= r; r *= K;
           a0 += t; a1 += a0; a2 += a1;
           t = g1 * e; e *= r;
