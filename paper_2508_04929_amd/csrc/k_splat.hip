@@ -213,8 +213,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
         float r = hexp2(-(al * (2.f * dj + 1.f) + 2.f * be * di));
         int *px = icanvas + rowo + j0;
         const int L4 = L & ~3;
-        int k = 0;
-        for (; k < L4; k += 4) {
+        for (int k = 0; k < L4; k += 4) {
           const int v0 = __float2int_rn(e); e *= r; r *= K;
           const int v1 = __float2int_rn(e); e *= r; r *= K;
           const int v2 = __float2int_rn(e); e *= r; r *= K;
@@ -224,13 +223,13 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
           atomicAdd(px + k + 2, v2);
           atomicAdd(px + k + 3, v3);
         }
-        if (k < L) {  // 1 to 3 trailing pixels
+        if (L4 < L) {  // 1 to 3 trailing pixels
           const int v0 = __float2int_rn(e); e *= r; r *= K;
           const int v1 = __float2int_rn(e); e *= r;
           const int v2 = __float2int_rn(e);
-          atomicAdd(px + k, v0);
-          if (k + 1 < L) atomicAdd(px + k + 1, v1);
-          if (k + 2 < L) atomicAdd(px + k + 2, v2);
+          atomicAdd(px + L4, v0);
+          if (L4 + 1 < L) atomicAdd(px + L4 + 1, v1);
+          if (L4 + 2 < L) atomicAdd(px + L4 + 2, v2);
         }
       }
     }
