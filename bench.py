@@ -350,6 +350,33 @@ def run(args):
                                "nominal_budget": {"peak": pair_peak(other) / 1e9,
                                                   "frac": ach_o / pair_peak(other)}}
     step_roof_s = pairs_step * (1 / pair_peak("k_splat_fwd") + 1 / pair_peak("k_splat_bwd"))
+
+    # Whole-step roofline: T_roof = sum over the step's kernels of the time
+    # at the bound that limits each, T_roof / T_measured.  The splat kernels
+    # at their hardware ceilings (the lower of VALU issue and LDS, from the
+    # committed counters); every other kernel at its HBM bytes per launch
+    # (FETCH_SIZE + WRITE_SIZE, committed counters) over the 8 TB/s peak,
+    # times its launches per step.  None when a summary is missing or stale.
+    def step_roofline():
+        terms, unpriced = {}, []
+        for name, st in stages.items():
+            per_step = st["launches"] / timing_steps
+            if name in ("k_splat_fwd", "k_splat_bwd"):
+                pk, _ = ceilings(name, pairs_step / (st["ms_per_launch"] * 1e-3))
+                if pk is None:
+                    return None
+                terms[name] = per_step * pairs_step / pk * 1e3
+            else:
+                bts = measured_traffic(name)
+                if bts is None:
+                    unpriced.append(name)  # left out: T_roof only shrinks
+                    continue
+                terms[name] = per_step * bts / 8e12 * 1e3
+        t_roof = sum(terms.values())
+        return {"t_roof_ms": t_roof, "t_measured_ms": ms_step, "frac": t_roof / ms_step,
+                "terms_ms": terms, "unpriced": unpriced,
+                "note": "splat kernels at their VALU-issue / LDS ceilings (counters), other "
+                        "kernels at measured HBM bytes / 8 TB/s; measured step from wall time"}
     result = {
         "metric": METRIC, "value": value, "unit": "images/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -366,6 +393,7 @@ def run(args):
                    "final_loss": final_loss},
         "roofline": roof,
         "step_fraction_of_splat_roofline": step_roof_s / (ms_step * 1e-3),
+        "step_roofline": step_roofline(),
         "stages_ms_per_step": {k: s["ms_total"] / timing_steps for k, s in stages.items()},
         "graph_replay": bool(args.graph),
         "pose_gradients": pose_grad,
