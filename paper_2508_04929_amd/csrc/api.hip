@@ -183,7 +183,7 @@ Layout make_layout(const Geom &G, bool need_partials, bool need_mom, bool need_f
     L.ctf = take((size_t)G.B * G.D * (G.D / 2 + 1) * 4);
   }
   if (need_mom) {
-    L.mom = take(BN * 4 * kMomStride + 32);
+    L.mom = take(BN * 24 + 32);
     L.pose_part = take((size_t)G.B * std::max(L.nbx, 1) * 32);
   }
   L.loss_part = take((size_t)G.B * G.D * 4);

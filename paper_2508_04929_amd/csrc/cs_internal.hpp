@@ -28,10 +28,6 @@
 namespace cs {
 
 constexpr int kBlock = 256;                  // threads per block of every splat kernel
-// Six pixel moments per (image, Gaussian), stored in rows of 8 floats
-// (32 bytes, aligned): one row is one 32-byte memory sector, where rows of 6
-// floats straddle sector boundaries and cost 1.5 sectors per access.
-constexpr int kMomStride = 8;
 constexpr float kHalfLog2e = 0.72134752044448170368f;  // 0.5 * log2(e)
 constexpr int kImgPerBinBlock = 8;           // images per block in the binning kernels
 

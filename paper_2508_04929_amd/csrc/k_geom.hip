@@ -320,9 +320,7 @@ struct ScreenGrad {
 
 __device__ __forceinline__ ScreenGrad screen_grad(const Proj &P, const float *m, float pixel) {
   const float p2 = pixel * pixel, ip = 1.f / pixel;
-  // one aligned 32-byte row: two 16-byte loads
-  const float4 ma = ((const float4 *)m)[0], mb = ((const float4 *)m)[1];
-  const float m0 = ma.x, m1 = ma.y, m2 = ma.z, m3 = ma.w, m4 = mb.x, m5 = mb.y;
+  const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4], m5 = m[5];
   const float inv_det = 1.f / P.det;
   const float Cxx = P.syy * inv_det, Cxy = -P.sxy * inv_det, Cyy = P.sxx * inv_det;
   const float a = p2 * Cxx, bb = -p2 * Cxy, c = p2 * Cyy;
@@ -372,7 +370,7 @@ k_chain(const float4 *gc, const float *log_scales, const float *quats, const flo
     load_pose(rot, shift, b, p0, p1, tx, ty);
     Proj P;
     project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
-    const float *m = mom + ((size_t)b * G.N + n) * kMomStride;
+    const float *m = mom + ((size_t)b * G.N + n) * 6;
     const ScreenGrad sg = screen_grad(P, m, G.pixel);
     const float dmx = sg.dmx, dmy = sg.dmy, Sxx = sg.Sxx, Sxy = sg.Sxy, Syy = sg.Syy;
     const float m0 = m[0];
@@ -507,7 +505,7 @@ k_pose_grad_part(const float4 *gc, const float *rot, const float *shift, Geom G,
       if (n < G.N && key[(size_t)b * G.N + n] >= 0) {
         Proj P;
         project_one(g0[j], g1[j], make_float2(g2[j].x, g2[j].y), p0, p1, tx, ty, G, P);
-        const ScreenGrad sg = screen_grad(P, mom + ((size_t)b * G.N + n) * kMomStride, G.pixel);
+        const ScreenGrad sg = screen_grad(P, mom + ((size_t)b * G.N + n) * 6, G.pixel);
         // Sigma p0, Sigma p1 (Sigma symmetric: the rows of P Sigma)
         const float4 a = g1[j], c = g2[j];
         const float sp0[3] = {a.x * p0[0] + a.y * p0[1] + a.z * p0[2],

@@ -404,7 +404,7 @@ k_big_add(const int *count, Geom G, const double *wscale, const long long *wq, f
 // ---------------------------------------------------------------------------
 // Backward: six pixel moments per (image, Gaussian) of one work item,
 //   m = sum G_Q e (1, dj, di, dj^2, dj di, di^2),  e = exp(-q/2),
-// with dj = j - u, di = i - v (pixels).  Written to mom[(b N + n) kMomStride + k].
+// with dj = j - u, di = i - v (pixels).  Written to mom[(b N + n) 6 + k].
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
   extern __shared__ float gq[];  // C rows of stride S
@@ -505,9 +505,8 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
         m4 += sdj * di;
         m5 += a0 * di * di;
       }
-      float4 *o = (float4 *)(mom + ((size_t)b * G.N + n) * kMomStride);
-      o[0] = make_float4(m0, m1, m2, m3);
-      o[1] = make_float4(m4, m5, 0.f, 0.f);  // the whole 32-byte row
+      float *o = mom + ((size_t)b * G.N + n) * 6;
+      o[0] = m0; o[1] = m1; o[2] = m2; o[3] = m3; o[4] = m4; o[5] = m5;
     }
     __syncthreads();  // the next chunk rewrites the order
     }
@@ -554,7 +553,7 @@ k_big_bwd(const float4 *list, const int *off, const int *count, const int *n_wid
         float x = 0.f;
         for (int wv = 0; wv < kBlock / 64; ++wv) x += red[threadIdx.x][wv];
         const int n = __float_as_int(r1.z);
-        mom[((size_t)b * G.N + n) * kMomStride + threadIdx.x] = x;
+        mom[((size_t)b * G.N + n) * 6 + threadIdx.x] = x;
       }
       __syncthreads();
     }
