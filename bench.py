@@ -805,8 +805,8 @@ def main():
     ap.add_argument("--pose-test", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU data parallelism is described, not built)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
+                          "(multi-GPU data parallelism is a design, not implemented)"}))
         sys.exit(2)
     if args.only_small:
         print(json.dumps({k: run_small(k, args.steps, args.warmup, args.cpu_images)
