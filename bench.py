@@ -357,26 +357,45 @@ def run(args):
     # committed counters); every other kernel at its HBM bytes per launch
     # (FETCH_SIZE + WRITE_SIZE, committed counters) over the 8 TB/s peak,
     # times its launches per step.  None when a summary is missing or stale.
-    def step_roofline():
+    def step_roofline(rates=None):
+        """With rates (the chip-rate probes of this GPU), every term at the
+        measured rate instead: VALU issue slots at the FP32 probe's wave64
+        instructions per second, LDS busy cycles at its clock, HBM bytes at
+        the copy probe's rate."""
         terms, unpriced = {}, []
         for name, st in stages.items():
             per_step = st["launches"] / timing_steps
             if name in ("k_splat_fwd", "k_splat_bwd"):
-                pk, _ = ceilings(name, pairs_step / (st["ms_per_launch"] * 1e-3))
-                if pk is None:
+                c = issue_ceiling(name)
+                if c is None:
                     return None
-                terms[name] = per_step * pairs_step / pk * 1e3
+                if rates is None:
+                    t = c["valu_issue_slots_per_pair"] / VALU_INSTR_RATE
+                    if "lds_cycles_per_pair" in c:
+                        t = max(t, c["lds_cycles_per_pair"] / LDS_CYCLE_RATE)
+                else:
+                    t = c["valu_issue_slots_per_pair"] / rates["fma"]["wave_instr_per_s"]
+                    if "lds_cycles_per_pair" in c:
+                        t = max(t, c["lds_cycles_per_pair"]
+                                / (256 * rates["fma"]["clock_ghz"] * 1e9))
+                terms[name] = per_step * pairs_step * t * 1e3
             else:
                 bts = measured_traffic(name)
                 if bts is None:
                     unpriced.append(name)  # left out: T_roof only shrinks
                     continue
-                terms[name] = per_step * bts / 8e12 * 1e3
+                bw = 8e12 if rates is None else rates["copy"]["gb_per_s"] * 1e9
+                terms[name] = per_step * bts / bw * 1e3
         t_roof = sum(terms.values())
         return {"t_roof_ms": t_roof, "t_measured_ms": ms_step, "frac": t_roof / ms_step,
                 "terms_ms": terms, "unpriced": unpriced,
-                "note": "splat kernels at their VALU-issue / LDS ceilings (counters), other "
-                        "kernels at measured HBM bytes / 8 TB/s; measured step from wall time"}
+                "note": ("splat kernels at their VALU-issue / LDS ceilings (counters), other "
+                         "kernels at measured HBM bytes / 8 TB/s; measured step from wall time"
+                         if rates is None else
+                         "as above, at the rates the chip-rate probes measured on this GPU "
+                         "(FP32 VALU issue and its clock, simple-copy bandwidth); the FP32 "
+                         "probe's all-FMA load runs at a lower clock than the splat kernels, "
+                         "so their terms here can exceed their measured times")}
     result = {
         "metric": METRIC, "value": value, "unit": "images/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -394,6 +413,8 @@ def run(args):
         "roofline": roof,
         "step_fraction_of_splat_roofline": step_roof_s / (ms_step * 1e-3),
         "step_roofline": step_roofline(),
+        "step_roofline_at_measured_rates": (step_roofline(getattr(args, "rates", None))
+                                            if getattr(args, "rates", None) else None),
         "stages_ms_per_step": {k: s["ms_total"] / timing_steps for k, s in stages.items()},
         "graph_replay": bool(args.graph),
         "pose_gradients": pose_grad,
@@ -798,6 +819,8 @@ def main():
                     help="skip the extra refinement configurations of the pose leg")
     ap.add_argument("--no-small", dest="small", action="store_false",
                     help="skip the N=20,000 (256 x 128^2) and N=1,000 (16 x 64^2) workloads")
+    ap.add_argument("--no-probe", dest="probe", action="store_false",
+                    help="skip the chip-rate probes (VALU, exp, LDS, BF16 MFMA, copy; ~0.2 s)")
     ap.add_argument("--only-small", action="store_true",
                     help="run only the N=20,000 and N=1,000 workloads (counter profiling)")
     ap.add_argument("--pose-train", type=int, default=200000)
@@ -817,8 +840,20 @@ def main():
         cpu = cpu_baseline(args.cpu_images)
         print(f"[bench] cpu oracle: {cpu['value']:.4f} images/s on {cpu['cores']} cores",
               file=sys.stderr, flush=True)
+    args.rates = None
+    if args.probe:
+        # the chip's rates measured on this GPU, beside the published peaks
+        # the rooflines use (FP32 VALU issue, v_exp_f32, LDS, BF16 MFMA, copy)
+        from paper_2508_04929_amd import probe
+        args.rates = probe.measure()
     res = run(args)
     res["cpu_baseline"] = cpu
+    if args.rates:
+        res["measured_rates"] = r = args.rates
+        print(f"[bench] measured: VALU {r['fma']['per_cu_per_cycle']:.2f} wave64 instr/CU/cycle "
+              f"at {r['fma']['clock_ghz']:.2f} GHz, LDS {r['lds']['bytes_per_cu_per_cycle']:.0f} "
+              f"B/CU/cycle, BF16 MFMA {r['mfma']['tflops_bf16']:.0f} TFLOP/s, copy "
+              f"{r['copy']['gb_per_s']:.0f} GB/s", file=sys.stderr, flush=True)
     if args.small:
         for k in ("c2", "c1"):
             res[k] = run_small(k, cpu_images=args.cpu_images)

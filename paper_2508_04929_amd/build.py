@@ -2,7 +2,8 @@
 
 Every HIP translation unit under ``csrc/`` is compiled for gfx950 into an
 object file, in parallel, and linked into ``libcryosplat.so`` next to this
-file.  Packed FP32 instructions are disabled for all device code.
+file; the chip-rate probes of the benchmark (``probe/probe.hip``) become
+``libcsprobe.so``.  Packed FP32 instructions are disabled for all device code.
 """
 from __future__ import annotations
 
@@ -62,7 +63,24 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probe(hipcc)
     return LIB
+
+
+PROBE_SRC = os.path.join(HERE, "probe", "probe.hip")
+PROBE_LIB = os.path.join(HERE, "libcsprobe.so")
+
+
+def build_probe(hipcc=None) -> str:
+    """Compile the chip-rate probes (probe/probe.hip) into libcsprobe.so."""
+    hipcc = hipcc or _hipcc()
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc, *FLAGS, "-shared", "-o", tmp, PROBE_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":

@@ -48,3 +48,14 @@ def test_binding_fails_loudly_without_library(tmp_path):
     from paper_2508_04929_amd import binding
     with pytest.raises(binding.CryoSplatError):
         binding.load_library(str(tmp_path / "missing.so"))
+
+
+PROBE = os.path.join(ROOT, "paper_2508_04929_amd", "libcsprobe.so")
+
+
+@pytest.mark.skipif(not os.path.exists(PROBE), reason="libcsprobe.so not built")
+def test_probe_library_loads_and_exports_its_probes():
+    from paper_2508_04929_amd import probe
+    lib = probe.load()
+    for name in ("csp_fma", "csp_exp", "csp_lds", "csp_mfma", "csp_copy", "csp_wall_clock_khz"):
+        assert hasattr(lib, name)
