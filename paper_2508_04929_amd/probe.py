@@ -68,7 +68,7 @@ def measure(device: int = 0, blocks: int = 8 * N_CU, copy_mib: int = 1024) -> di
     dst = torch.empty_like(src)
     times = []
     for _ in range(6):
-        ms = lib.csp_copy(src.data_ptr(), dst.data_ptr(), n4, 4 * 1024 * N_CU // 256)
+        ms = lib.csp_copy(src.data_ptr(), dst.data_ptr(), n4, 65536)
         if ms <= 0:
             raise RuntimeError("probe copy failed")
         times.append(ms)
