@@ -94,6 +94,18 @@ struct FftPlan {
 // Device helpers
 // ----------------------------------------------------------------------------
 
+// Work index of block k of a grid of `total` blocks such that each XCD runs
+// one contiguous run of work indices: the dispatcher deals workgroups to the
+// eight XCDs in turn (block k to XCD k mod 8), so XCD x takes indices
+// [start_x, start_x + count_x) in order, count_x = the number of k < total
+// with k mod 8 = x.  Neighbouring work (sharing cache lines) then meets in
+// one XCD's L2.  A bijection of [0, total) for any total.
+__device__ __forceinline__ int xcd_work(int k, int total) {
+  const int per = (total + 7) / 8, r = total % 8 == 0 ? 8 : total % 8;
+  const int x = k % 8;
+  return x * (per - 1) + min(x, r) + k / 8;
+}
+
 __device__ __forceinline__ float softplusf(float x) {
   return x > 20.f ? x : log1pf(__expf(x));
 }

@@ -154,13 +154,21 @@ k_ctf_table(int L, float pixel, CtfDev ctf, int B, float *table) {
 // rows, times a multiplier mul(ky, kx, z) of image blockIdx.y, inverse FFT
 // over rows, in place.
 // ---------------------------------------------------------------------------
+// Image and column group of this block: the grid is (column groups, images)
+// and the XCD-aware order keeps an image's adjacent column groups (whose
+// rows share cache lines) on one XCD.
+__device__ __forceinline__ void cols_block(int &b, int &group) {
+  const int j = xcd_work(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  b = j / gridDim.x;
+  group = j % gridDim.x;
+}
+
 template <class Mul>
 __device__ __forceinline__ void fft_cols_apply(float2 *spec, const FftPlan &P, const float2 *tw,
-                                               int cpw, const Mul &mul) {
+                                               int cpw, int b, int group, const Mul &mul) {
   extern __shared__ float2 lds[];
   const int L = P.L, Dh = L / 2 + 1;
-  const int b = blockIdx.y;
-  const int kx0 = blockIdx.x * cpw;
+  const int kx0 = group * cpw;
   const int ts = 256 / cpw;
   const int team = threadIdx.x / ts, t = threadIdx.x % ts;
   float2 *img = spec + (size_t)b * L * Dh;
@@ -193,8 +201,10 @@ __device__ __forceinline__ void fft_cols_apply(float2 *spec, const FftPlan &P, c
 __global__ void __launch_bounds__(256)
 k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, const float *table) {
   const int L = P.L, Dh = L / 2 + 1;
-  const float *hcol = table + (size_t)blockIdx.y * L * Dh;
-  fft_cols_apply(spec, P, tw, cpw, [&](int ky, int kx, float2 z) {
+  int b, group;
+  cols_block(b, group);
+  const float *hcol = table + (size_t)b * L * Dh;
+  fft_cols_apply(spec, P, tw, cpw, b, group, [&](int ky, int kx, float2 z) {
     const float h = hcol[(size_t)ky * Dh + kx];
     return make_float2(z.x * h, z.y * h);
   });
@@ -209,13 +219,15 @@ k_fft_cols_ctf(float2 *spec, FftPlan P, const float2 *tw, int B, int cpw, const 
 __global__ void __launch_bounds__(256)
 k_fft_cols_shift(float2 *spec, FftPlan P, const float2 *tw, int cpw, const float *shift,
                  float inv_pixel, float sign) {
-  const int L = P.L, b = blockIdx.y;
+  const int L = P.L;
+  int b, group;
+  cols_block(b, group);
   const double ac = (double)(sign * shift[2 * b] * inv_pixel);
   const double ar = -(double)(sign * shift[2 * b + 1] * inv_pixel);
   const bool even = (L % 2) == 0;
   const int half = L / 2;
   const float norm = 1.f / ((float)L * (float)L);
-  fft_cols_apply(spec, P, tw, cpw, [&](int ky, int kx, float2 z) {
+  fft_cols_apply(spec, P, tw, cpw, b, group, [&](int ky, int kx, float2 z) {
     const bool nx = even && kx == half, ny = even && ky == half;
     const int fy = ky < (L + 1) / 2 ? ky : ky - L;
     double turns;

@@ -260,7 +260,13 @@ __device__ __forceinline__ float4 f4add(float4 a, float4 b) {
 __global__ void __launch_bounds__(kBlock)
 k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, Geom G,
                 float *Q) {
-  const int t = blockIdx.x, b = blockIdx.y;
+  // XCD-aware order: a work index runs over the z-split parts of a tile,
+  // then the tiles of an image, so the blocks that read one canvas (its own
+  // and its neighbours' halos) meet in one XCD's L2
+  const int zsplit = gridDim.z;
+  const int j = xcd_work(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                         gridDim.x * gridDim.y * zsplit);
+  const int zz = j % zsplit, t = (j / zsplit) % gridDim.x, b = j / (zsplit * gridDim.x);
   const int ty = t / G.ntx, tx = t % G.ntx;
   const int r_lo = ty * G.T, r_hi = min(r_lo + G.T, G.D);
   const int c_lo = tx * G.T, c_hi = min(c_lo + G.T, G.D);
@@ -271,7 +277,7 @@ k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, G
   const int px_per = vec ? 4 : 1;
   const int wq = wdt / px_per;
   const int nq = (r_hi - r_lo) * wq;
-  for (int q = threadIdx.x + blockIdx.z * kBlock; q < nq; q += kBlock * gridDim.z) {
+  for (int q = threadIdx.x + zz * kBlock; q < nq; q += kBlock * zsplit) {
     const int i = r_lo + q / wq, j = c_lo + px_per * (q % wq);
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int dy = -1; dy <= 1; ++dy) {
