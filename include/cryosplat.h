@@ -143,8 +143,11 @@ typedef struct {
                      must not itself be inside a caller's stream capture */
   int32_t lane_order; /* 0 = each work item's Gaussians go to lanes in list
                          order; 1 = dealt so that the lanes of a wave start on
-                         distinct LDS banks (pays for wide footprints).  The
-                         results are identical either way. */
+                         distinct LDS banks (pays for wide footprints);
+                         2 = sorted by footprint shape (row count, then
+                         widest span) so that the lanes of a wave walk
+                         similar footprints (pays where sizes spread).  The
+                         results are identical in every order. */
 } cs_options;
 
 /* Create a context on HIP device `device`.  *out receives the handle. */

@@ -231,7 +231,7 @@ class Options:
     halo: int = 0
     budget: int = 0
     graph: int = 0       # 1: capture/replay the call as a HIP graph
-    lane_order: int = 0  # 1: records dealt to lanes by LDS bank (same results)
+    lane_order: int = 0  # 1: dealt by LDS bank, 2: sorted by footprint shape (same results)
 
 
 @dataclasses.dataclass

@@ -286,8 +286,8 @@ int validate(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf
     if (opt->halo < 0 || opt->halo > T) return fail(ctx, CS_ERR_INVALID_ARG, "halo must be in [0, tile]");
     if (opt->budget != 0 && opt->budget < 64) return fail(ctx, CS_ERR_INVALID_ARG, "budget must be 0 or >= 64");
     if (!std::isfinite(opt->q_cut)) return fail(ctx, CS_ERR_INVALID_ARG, "q_cut must be finite");
-    if (opt->lane_order != 0 && opt->lane_order != 1)
-      return fail(ctx, CS_ERR_INVALID_ARG, "lane_order must be 0 or 1");
+    if (opt->lane_order < 0 || opt->lane_order > 2)
+      return fail(ctx, CS_ERR_INVALID_ARG, "lane_order must be 0, 1 or 2");
   }
   return CS_OK;
 }
@@ -821,7 +821,7 @@ void load_tune_file(cs_ctx *ctx) {
     std::string key;
     int t, h, b, d = 0;
     if (is >> key >> t >> h >> b && t >= 16 && t <= 128 && h >= 0 && h <= t && b >= 64) {
-      if (!(is >> d) || (d != 0 && d != 1)) d = 0;  // lane order: optional fourth field
+      if (!(is >> d) || d < 0 || d > 2) d = 0;  // lane order: optional fourth field
       ctx->tuned[key] = {t, h, b, d};
     }
   }
@@ -1097,20 +1097,23 @@ int cs_autotune(cs_ctx *ctx, cs_problem *problems, int32_t count, int32_t reps, 
         if (rc) break;
       }
       if (rc) break;
-      // stage 2: the dealt lane order for the four fastest tile x halo
-      // candidates (it shifts the balance towards larger canvases)
+      // stage 2: the dealt and the size-sorted lane orders for the four
+      // fastest tile x halo candidates (they shift the balance towards
+      // larger canvases)
       {
         std::vector<std::pair<double, std::vector<int>>> fast = cand;
         std::stable_sort(fast.begin(), fast.end(),
                          [](const auto &a, const auto &b) { return a.first < b.first; });
         for (size_t k = 0; k < fast.size() && k < 4 && rc == CS_OK; ++k) {
-          pr.opt.tile = fast[k].second[0];
-          pr.opt.halo = fast[k].second[1];
-          pr.opt.budget = kDefaultBudget;
-          pr.opt.lane_order = 1;
-          double ms = 0;
-          rc = time_problem(ctx, pr, reps, st, &ms);
-          cand.push_back({ms, {pr.opt.tile, pr.opt.halo, kDefaultBudget, 1}});
+          for (int lo = 1; lo <= 2 && rc == CS_OK; ++lo) {
+            pr.opt.tile = fast[k].second[0];
+            pr.opt.halo = fast[k].second[1];
+            pr.opt.budget = kDefaultBudget;
+            pr.opt.lane_order = lo;
+            double ms = 0;
+            rc = time_problem(ctx, pr, reps, st, &ms);
+            cand.push_back({ms, {pr.opt.tile, pr.opt.halo, kDefaultBudget, lo}});
+          }
         }
       }
       if (rc) break;

@@ -144,6 +144,98 @@ __device__ __forceinline__ void deal(const float4 *list, size_t base, int n, int
 }
 
 // ---------------------------------------------------------------------------
+// Sorting records by footprint shape.  A wave steps as many rows as its
+// tallest footprint and, per row, as many pixel groups as its widest active
+// span, so where footprint sizes spread (anisotropic Gaussians with
+// log-normal scales) most lanes idle for most steps.  Launch option
+// lane_order = 2 orders each chunk of kSortChunk records by (row count,
+// width class) with a counting sort in LDS: the row count is the record's
+// row range clipped to the canvas (capped at 31), the width class the
+// widest span, 2 sqrt(qk / a) at the centre row, in steps of four pixels
+// (capped at 7).  The order among equal keys follows the LDS atomics and
+// is not fixed, which is harmless: as with the dealt order, only the lane
+// that walks a record changes, never its arithmetic, and the forward sums
+// are order-free integers, so every result is the same.
+// ---------------------------------------------------------------------------
+constexpr int kSortChunk = 1024;
+constexpr int kSortKeys = 256;  // 32 row counts x 8 width classes
+static_assert(kSortKeys == kBlock, "one key counter per thread");
+
+struct SortLds {
+  int start[kSortKeys];
+  int wsum[kBlock / 64];
+  unsigned short perm[kSortChunk];  // place -> record (within the chunk)
+};
+
+union OrderLds {
+  DealLds deal;
+  SortLds sort;
+};
+
+__device__ __forceinline__ void size_sort(const float4 *list, size_t base, int n, int rlo, int rhi,
+                                          float qk, SortLds &d) {
+  const int t = threadIdx.x;
+  d.start[t] = 0;
+  __syncthreads();
+  constexpr int kPer = kSortChunk / kBlock;
+  int key[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int g = t + j * kBlock;
+    key[j] = -1;
+    if (g < n) {
+      const float al = list[2 * (base + g)].z;
+      const int rows = __float_as_int(list[2 * (base + g) + 1].w);
+      const int nr = min(rows >> 16, rhi) - max(rows & 0xffff, rlo) + 1;
+      const int wc = (int)fminf(2.f * hsqrt(qk / al), 64.f) >> 2;
+      const int k = min(max(nr, 0), 31) * 8 + min(wc, 7);
+      key[j] = (atomicAdd(&d.start[k], 1) << 8) | k;
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the key counts: wave scans, then the wave totals
+  const int c = d.start[t];
+  int x = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if ((t & 63) >= o) x += y;
+  }
+  if ((t & 63) == 63) d.wsum[t >> 6] = x;
+  __syncthreads();
+  int off = x - c;
+  for (int w = 0; w < (t >> 6); ++w) off += d.wsum[w];
+  d.start[t] = off;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kPer; ++j)
+    if (key[j] >= 0) d.perm[d.start[key[j] & 255] + (key[j] >> 8)] = (unsigned short)(t + j * kBlock);
+  __syncthreads();
+}
+
+// Records per ordered chunk for an item of w records, by lane_order.
+__device__ __forceinline__ int chunk_len(const Geom &G, int w) {
+  return G.deal == 1 ? kDealChunk : G.deal == 2 ? kSortChunk : w;
+}
+
+// Orders one chunk of records as the launch option lane_order asks and
+// returns the place -> record map (null: list order).  Block-wide: every
+// thread of the block calls it.
+__device__ __forceinline__ const unsigned short *order_records(const float4 *list, size_t base,
+                                                               int n, const Geom &G, int R0, int C0,
+                                                               int rlo, int rhi, OrderLds &o) {
+  if (G.deal == 1) {
+    deal(list, base, n, G.S, R0, C0, o.deal);
+    return o.deal.perm;
+  }
+  if (G.deal == 2) {
+    size_sort(list, base, n, rlo, rhi, G.qk, o.sort);
+    return o.sort.perm;
+  }
+  return nullptr;
+}
+
+// ---------------------------------------------------------------------------
 // Forward: partial canvas of one work item.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
@@ -151,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
   int *icanvas = (int *)smem4;        // C rows of stride S (fixed point)
   __shared__ int slot;
   __shared__ float wsum[kBlock / 64];
-  __shared__ DealLds dl;
+  __shared__ OrderLds ol;
   // drain the problems' queues in order: blocks that find one exhausted move on
   for (int p = 0; p < MP.count; ++p) {
   const Geom G = MP.p[p].G;
@@ -188,12 +280,13 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
     const int rlo = max(R0, 0), rhi = min(R0 + G.C - 1, G.D - 1);
     const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
     __syncthreads();  // canvas cleared
-    const int chunk = G.deal ? kDealChunk : itm.w;
+    const int chunk = chunk_len(G, itm.w);
     for (int c0 = 0; c0 < itm.w; c0 += chunk) {
     const int nc = min(chunk, itm.w - c0);
-    if (G.deal) deal(list, (size_t)itm.z + c0, nc, G.S, R0, C0, dl);
+    const unsigned short *perm =
+        order_records(list, (size_t)itm.z + c0, nc, G, R0, C0, rlo, rhi, ol);
     for (int s = threadIdx.x; s < nc; s += kBlock) {
-      const size_t rec = 2 * ((size_t)itm.z + c0 + (G.deal ? dl.perm[s] : s));
+      const size_t rec = 2 * ((size_t)itm.z + c0 + (perm ? perm[s] : s));
       const float4 r0 = list[rec], r1 = list[rec + 1];
       const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x, w = r1.y * scale;
       const int rows = __float_as_int(r1.w);
@@ -415,7 +508,7 @@ k_big_add(const int *count, Geom G, const double *wscale, const long long *wq, f
 __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
   extern __shared__ float gq[];  // C rows of stride S
   __shared__ int slot;
-  __shared__ DealLds dl;
+  __shared__ OrderLds ol;
   for (int p = 0; p < MP.count; ++p) {
   const Geom G = MP.p[p].G;
   const float4 *list = MP.p[p].list;
@@ -441,12 +534,13 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
       gq[q] = (c < G.C && i >= 0 && i < G.D && j >= 0 && j < G.D) ? src[(size_t)i * G.D + j] : 0.f;
     }
     __syncthreads();
-    const int chunk = G.deal ? kDealChunk : itm.w;
+    const int chunk = chunk_len(G, itm.w);
     for (int c0 = 0; c0 < itm.w; c0 += chunk) {
     const int nc = min(chunk, itm.w - c0);
-    if (G.deal) deal(list, (size_t)itm.z + c0, nc, G.S, R0, C0, dl);
+    const unsigned short *perm =
+        order_records(list, (size_t)itm.z + c0, nc, G, R0, C0, rlo, rhi, ol);
     for (int s = threadIdx.x; s < nc; s += kBlock) {
-      const size_t rec = 2 * ((size_t)itm.z + c0 + (G.deal ? dl.perm[s] : s));
+      const size_t rec = 2 * ((size_t)itm.z + c0 + (perm ? perm[s] : s));
       const float4 r0 = list[rec], r1 = list[rec + 1];
       const float u = r0.x, v = r0.y, al = r0.z, be = r0.w, ga = r1.x;
       const int n = __float_as_int(r1.z);

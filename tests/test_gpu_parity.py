@@ -207,7 +207,8 @@ def test_mean_reduction_scales_gradients(gpu_lib):
 @pytest.mark.parametrize("tile,halo,budget,lane_order", [(16, 8, 64, 0), (32, 16, 256, 0),
                                                          (64, 8, 4096, 0), (128, 24, 512, 0),
                                                          (16, 1, 100, 0), (40, 12, 1024, 1),
-                                                         (64, 16, 2048, 1)])
+                                                         (64, 16, 2048, 1), (32, 24, 3000, 2),
+                                                         (16, 8, 64, 2)])
 def test_results_independent_of_launch_options(gpu_lib, tile, halo, budget, lane_order):
     rng = np.random.default_rng(14)
     g = inputs.mixture_anisotropic(rng, 6000, 40.0)
