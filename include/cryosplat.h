@@ -89,7 +89,7 @@ typedef struct {
 typedef struct {
   const float *rot;   /* [B][3][3] world-to-view rotations W, row-major */
   const float *shift; /* [B][2] in-plane shifts t in Angstrom, or NULL for 0 */
-  int64_t b;          /* B >= 1 images */
+  int64_t b;          /* B images, 1 <= B <= 65535 */
   int32_t d;          /* image side D, 1 <= D <= 512 */
   float pixel;        /* pixel size p in Angstrom, > 0 */
 } cs_views;

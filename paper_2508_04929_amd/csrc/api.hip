@@ -37,6 +37,7 @@ int auto_budget(int64_t N, int64_t B) {
   return b;
 }
 constexpr int kMaxD = 512;
+constexpr int kMaxImages = 65535;  // launches put the image index in grid y
 
 inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
@@ -262,6 +263,9 @@ int validate(cs_ctx *ctx, const cs_gaussians *g, const cs_views *v, const cs_ctf
   if (g->amp_act != 0 && g->amp_act != 1) return fail(ctx, CS_ERR_INVALID_ARG, "bad amp_act");
   if (!v->rot) return fail(ctx, CS_ERR_INVALID_ARG, "null rotations");
   if (v->b < 1) return fail(ctx, CS_ERR_INVALID_ARG, "image count must be >= 1");
+  if (v->b > kMaxImages)
+    return fail(ctx, CS_ERR_UNSUPPORTED, "image count %lld > %d (one grid row per image)",
+                (long long)v->b, kMaxImages);
   if (v->d < 1) return fail(ctx, CS_ERR_INVALID_ARG, "image side must be >= 1");
   if (v->d > kMaxD) return fail(ctx, CS_ERR_UNSUPPORTED, "image side %d > %d", v->d, kMaxD);
   if (!(v->pixel > 0.f) || !std::isfinite(v->pixel))
@@ -445,6 +449,10 @@ int launch_persistent(cs_ctx *ctx, bool forward, const Plan *const *all, int n, 
 }
 
 // After the forward splat: Q of one problem (reduce + wide Gaussians).
+// Blocks per image of the wide-record kernels (grid rows are images): about
+// 512 blocks in all, at least 4 per image.
+int big_blocks(int B) { return std::max(4, (512 + B - 1) / B); }
+
 int launch_forward_finish(cs_ctx *ctx, const Plan &P, float *Q, hipStream_t st) {
   const Geom &G = P.G;
   char *ws = P.ws;
@@ -460,7 +468,7 @@ int launch_forward_finish(cs_ctx *ctx, const Plan &P, float *Q, hipStream_t st) 
   long long *wq = (long long *)(ws + P.L.wideq);
   TLAUNCH(k_big_prep, dim3(G.B), dim3(kBlock), 0, st, (const int *)(ws + P.L.off),
           (const int *)(ws + P.L.count), (const float *)(ws + P.L.wabs), G, wscale, wq);
-  TLAUNCH(k_big_fwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
+  TLAUNCH(k_big_fwd, dim3(big_blocks(G.B), G.B), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
           (const int *)(ws + P.L.off), (const int *)(ws + P.L.count),
           (const int *)(ws + P.L.n_items) + 1, G, (const double *)wscale, wq);
   TLAUNCH(k_big_add, dim3(cdiv((size_t)G.D * G.D, 4 * kBlock), G.B), dim3(kBlock), 0, st,
@@ -472,7 +480,7 @@ int launch_backward_finish(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   const Geom &G = P.G;
   char *ws = P.ws;
   float *mom = (float *)(ws + P.L.mom);
-  TLAUNCH(k_big_bwd, dim3(256), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
+  TLAUNCH(k_big_bwd, dim3(big_blocks(G.B), G.B), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.list),
           (const int *)(ws + P.L.off), (const int *)(ws + P.L.count),
           (const int *)(ws + P.L.n_items) + 1, G, P.GQ(), mom);
   TLAUNCH(k_chain, dim3(cdiv(G.N, 64)), dim3(kBlock), 0, st, (const float4 *)(ws + P.L.gc),

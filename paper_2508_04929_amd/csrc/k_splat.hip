@@ -455,33 +455,33 @@ k_big_prep(const int *off, const int *count, const float *wabs, Geom G, double *
   }
 }
 
-// k_big_fwd: one block per wide record, threads over its pixel box, exp per
-// pixel, 64-bit integer atomics into the image's integer sum.
+// k_big_fwd: grid row b takes image b's wide records, one block per record
+// at a time, threads over its pixel box, exp per pixel, 64-bit integer
+// atomics into the image's integer sum.
 __global__ void __launch_bounds__(kBlock)
 k_big_fwd(const float4 *list, const int *off, const int *count, const int *n_wide, Geom G,
           const double *wscale, long long *wq) {
   if (*n_wide == 0) return;
-  for (int b = 0; b < G.B; ++b) {
-    const int e = b * G.K + G.ntiles;
-    const int cnt = count[e], start = off[e];
-    if (cnt == 0) continue;
-    const double S = wscale[b];
-    unsigned long long *img = (unsigned long long *)(wq + (size_t)b * G.D * G.D);
-    for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
-      const float4 r0 = list[2 * (size_t)(start + k)], r1 = list[2 * (size_t)(start + k) + 1];
-      int i0, i1, j0, j1;
-      wide_box(r0, r1, G, i0, i1, j0, j1);
-      if (i1 < i0 || j1 < j0) continue;
-      const int wdt = j1 - j0 + 1;
-      const long npx = (long)(i1 - i0 + 1) * wdt;
-      for (long q = threadIdx.x; q < npx; q += kBlock) {
-        const int i = i0 + (int)(q / wdt), j = j0 + (int)(q % wdt);
-        const float dj = (float)j - r0.x, di = (float)i - r0.y;
-        const float qq = r0.z * dj * dj + 2.f * r0.w * dj * di + r1.x * di * di;
-        if (qq <= G.qk) {
-          const long long v = __double2ll_rn((double)(r1.y * exp2f(-qq)) * S);
-          atomicAdd(&img[(size_t)i * G.D + j], (unsigned long long)v);
-        }
+  const int b = blockIdx.y;
+  const int e = b * G.K + G.ntiles;
+  const int cnt = count[e], start = off[e];
+  if (cnt == 0) return;
+  const double S = wscale[b];
+  unsigned long long *img = (unsigned long long *)(wq + (size_t)b * G.D * G.D);
+  for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+    const float4 r0 = list[2 * (size_t)(start + k)], r1 = list[2 * (size_t)(start + k) + 1];
+    int i0, i1, j0, j1;
+    wide_box(r0, r1, G, i0, i1, j0, j1);
+    if (i1 < i0 || j1 < j0) continue;
+    const int wdt = j1 - j0 + 1;
+    const long npx = (long)(i1 - i0 + 1) * wdt;
+    for (long q = threadIdx.x; q < npx; q += kBlock) {
+      const int i = i0 + (int)(q / wdt), j = j0 + (int)(q % wdt);
+      const float dj = (float)j - r0.x, di = (float)i - r0.y;
+      const float qq = r0.z * dj * dj + 2.f * r0.w * dj * di + r1.x * di * di;
+      if (qq <= G.qk) {
+        const long long v = __double2ll_rn((double)(r1.y * exp2f(-qq)) * S);
+        atomicAdd(&img[(size_t)i * G.D + j], (unsigned long long)v);
       }
     }
   }
@@ -614,49 +614,50 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
   }
 }
 
+// Grid row b takes image b's wide records, one block per record at a time:
+// per-thread moments over the pixel box, then a fixed-order block sum.
 __global__ void __launch_bounds__(kBlock)
 k_big_bwd(const float4 *list, const int *off, const int *count, const int *n_wide, Geom G,
           const float *GQ, float *mom) {
   __shared__ float red[6][kBlock / 64];
   if (*n_wide == 0) return;
-  for (int b = 0; b < G.B; ++b) {
-    const int e = b * G.K + G.ntiles;
-    const int cnt = count[e], start = off[e];
-    for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
-      const float4 r0 = list[2 * (size_t)(start + k)], r1 = list[2 * (size_t)(start + k) + 1];
-      int i0, i1, j0, j1;
-      wide_box(r0, r1, G, i0, i1, j0, j1);
-      float m[6] = {0, 0, 0, 0, 0, 0};
-      if (i1 >= i0 && j1 >= j0) {
-        const int wdt = j1 - j0 + 1;
-        const long npx = (long)(i1 - i0 + 1) * wdt;
-        for (long q = threadIdx.x; q < npx; q += kBlock) {
-          const int i = i0 + (int)(q / wdt), j = j0 + (int)(q % wdt);
-          const float dj = (float)j - r0.x, di = (float)i - r0.y;
-          const float qq = r0.z * dj * dj + 2.f * r0.w * dj * di + r1.x * di * di;
-          if (qq <= G.qk) {
-            const float t = GQ[((size_t)b * G.D + i) * G.D + j] * exp2f(-qq);
-            m[0] += t; m[1] += t * dj; m[2] += t * di;
-            m[3] += t * dj * dj; m[4] += t * dj * di; m[5] += t * di * di;
-          }
+  const int b = blockIdx.y;
+  const int e = b * G.K + G.ntiles;
+  const int cnt = count[e], start = off[e];
+  for (int k = blockIdx.x; k < cnt; k += gridDim.x) {
+    const float4 r0 = list[2 * (size_t)(start + k)], r1 = list[2 * (size_t)(start + k) + 1];
+    int i0, i1, j0, j1;
+    wide_box(r0, r1, G, i0, i1, j0, j1);
+    float m[6] = {0, 0, 0, 0, 0, 0};
+    if (i1 >= i0 && j1 >= j0) {
+      const int wdt = j1 - j0 + 1;
+      const long npx = (long)(i1 - i0 + 1) * wdt;
+      for (long q = threadIdx.x; q < npx; q += kBlock) {
+        const int i = i0 + (int)(q / wdt), j = j0 + (int)(q % wdt);
+        const float dj = (float)j - r0.x, di = (float)i - r0.y;
+        const float qq = r0.z * dj * dj + 2.f * r0.w * dj * di + r1.x * di * di;
+        if (qq <= G.qk) {
+          const float t = GQ[((size_t)b * G.D + i) * G.D + j] * exp2f(-qq);
+          m[0] += t; m[1] += t * dj; m[2] += t * di;
+          m[3] += t * dj * dj; m[4] += t * dj * di; m[5] += t * di * di;
         }
       }
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        float x = m[c];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = x;
-      }
-      __syncthreads();
-      if (threadIdx.x < 6) {
-        float x = 0.f;
-        for (int wv = 0; wv < kBlock / 64; ++wv) x += red[threadIdx.x][wv];
-        const int n = __float_as_int(r1.z);
-        mom[((size_t)b * G.N + n) * 6 + threadIdx.x] = x;
-      }
-      __syncthreads();
     }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      float x = m[c];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      float x = 0.f;
+      for (int wv = 0; wv < kBlock / 64; ++wv) x += red[threadIdx.x][wv];
+      const int n = __float_as_int(r1.z);
+      mom[((size_t)b * G.N + n) * 6 + threadIdx.x] = x;
+    }
+    __syncthreads();
   }
 }
 
