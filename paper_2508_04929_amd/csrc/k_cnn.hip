@@ -34,7 +34,14 @@ union Vec8 {
 // Generic split-K GEMM: C[m][n] = sum_k A[m][k] B[n][k] over k in this
 // block's K range.  Op supplies the gathers and the epilogue:
 //   Op::kATrans / kBTrans: false = 8 consecutive k of one row per 16-byte
-//   load (a_vec / b_vec); true = 8 consecutive rows of one k (a_vecT / b_vecT).
+//   load (ptr_a / ptr_b); true = 8 consecutive rows of one k (ptr_aT / ptr_bT).
+// A gather returns the address of its 16 bytes and whether they are real
+// operand values; outside the operand (image padding, past M, N or the K
+// range) it returns an address that is still valid to read (the tensor's
+// first element) with ok = false, and the value read is replaced by zeros
+// when it is staged into LDS.  Every load is thus unconditional, so the
+// compiler can count the loads in flight exactly and wait only for the one
+// step being staged, keeping the prefetched steps in flight.
 // ---------------------------------------------------------------------------
 // One K step of an operand tile: each thread fetches 16 bytes into a
 // register (prefetched while the previous step computes), then stores them
@@ -42,23 +49,25 @@ union Vec8 {
 // 8 consecutive rows of one k, scattered into 8 rows).  A non-transposed
 // operand keeps the same rows for the whole K loop, so each thread decodes
 // its rows once (Op::row_a / row_b) and gathers with the step's base k
-// (uniform across the block) plus its own offset (Op::vec_a / vec_b).
+// (uniform across the block) plus its own offset (Op::ptr_a / ptr_b).
 template <class Op, bool IS_A>
 struct Gather {
   typedef typename Op::Row Row;
   __device__ static Row row(const Op &op, int r) { return IS_A ? op.row_a(r) : op.row_b(r); }
-  __device__ static uint4 vec(const Op &op, const Row &w, int k0, int koff) {
-    return IS_A ? op.vec_a(w, k0, koff) : op.vec_b(w, k0, koff);
+  __device__ static const uint4 *ptr(const Op &op, const Row &w, int k0, int koff, bool &ok) {
+    return IS_A ? op.ptr_a(w, k0, koff, ok) : op.ptr_b(w, k0, koff, ok);
   }
 };
 
 template <class Op, int TB>
 __device__ __forceinline__ uint4 fetch_trans(const Op &op, bool isA, int idx, int r0, int k0, int R,
-                                             int Kend) {
-  uint4 v = make_uint4(0, 0, 0, 0);
+                                             int Kend, bool &ok) {
   const int r = r0 + (idx % (TB / 8)) * 8, k = k0 + idx / (TB / 8);
-  if (r < R && k < Kend) v = isA ? op.a_vecT(r, k) : op.b_vecT(r, k);
-  return v;
+  const bool in = r < R && k < Kend;
+  bool okp;
+  const uint4 *p = isA ? op.ptr_aT(in ? r : 0, in ? k : 0, okp) : op.ptr_bT(in ? r : 0, in ? k : 0, okp);
+  ok = in && okp;
+  return *p;
 }
 
 template <class Op, int TB>
@@ -93,15 +102,29 @@ struct Side {
       }
     }
   }
-  __device__ uint4 fetch(const Op &op, int q, int tid, int r0, int k0, int R, int Kend) const {
+  // the 16 bytes of gather q at step base k0 (always read) and whether
+  // they are operand values (false: to be replaced by zeros)
+  __device__ uint4 fetch(const Op &op, int q, int tid, int r0, int k0, int R, int Kend,
+                         bool &valid) const {
     if constexpr (kTrans) {
-      return fetch_trans<Op, TB>(op, IS_A, tid + 256 * q, r0, k0, R, Kend);
+      return fetch_trans<Op, TB>(op, IS_A, tid + 256 * q, r0, k0, R, Kend, valid);
     } else {
-      if (!ok[q] || k0 + koff[q] >= Kend) return make_uint4(0, 0, 0, 0);
-      return Gather<Op, IS_A>::vec(op, row[q], k0, koff[q]);
+      // beyond the K range the read goes to the range's last 8 columns
+      // (Kend is a multiple of 8): an in-bounds address from the step base,
+      // which stays uniform across the block
+      const bool in = ok[q] && k0 + koff[q] < Kend;
+      const int kc = k0 < Kend ? k0 : Kend - 8;
+      bool okp;
+      const uint4 *p = Gather<Op, IS_A>::ptr(op, row[q], kc, in ? koff[q] : 0, okp);
+      valid = in && okp;
+      return *p;
     }
   }
 };
+
+__device__ __forceinline__ uint4 keep_if(bool valid, uint4 v) {
+  return valid ? v : make_uint4(0, 0, 0, 0);
+}
 
 // TBM x TBN block tile, four waves in 2 x 2, each wave (TBM/2) x (TBN/2) as
 // 16 x 16 MFMA tiles; K steps of 32 double-buffered through LDS (operands
@@ -134,35 +157,36 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
   sb.init(op, tid, n0, N);
   // operand registers of S consecutive K steps: a step's global loads are
   // issued S - 1 steps before it is staged into LDS, so their latency hides
-  // behind that many steps of MFMA work
+  // behind that many steps of MFMA work (va / vb: validity of each gather)
   constexpr int S = 3;
   uint4 ra[S][NA], rb[S][NB];
+  bool va[S][NA], vb[S][NB];
   const int nsteps = (ke - kb + BK - 1) / BK;
 #pragma unroll
   for (int u = 0; u < S; ++u) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) ra[u][q] = sa.fetch(op, q, tid, m0, kb + u * BK, M, ke);
+    for (int q = 0; q < NA; ++q) ra[u][q] = sa.fetch(op, q, tid, m0, kb + u * BK, M, ke, va[u][q]);
 #pragma unroll
-    for (int q = 0; q < NB; ++q) rb[u][q] = sb.fetch(op, q, tid, n0, kb + u * BK, N, ke);
+    for (int q = 0; q < NB; ++q) rb[u][q] = sb.fetch(op, q, tid, n0, kb + u * BK, N, ke, vb[u][q]);
   }
 #pragma unroll
-  for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[0], tid + 256 * q, ra[0][q]);
+  for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[0], tid + 256 * q, keep_if(va[0][q], ra[0][q]));
 #pragma unroll
-  for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[0], tid + 256 * q, rb[0][q]);
+  for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[0], tid + 256 * q, keep_if(vb[0][q], rb[0][q]));
   __syncthreads();
   for (int t0 = 0; t0 < nsteps; t0 += S) {
 #pragma unroll
     for (int u = 0; u < S; ++u) {
       const int t = t0 + u;
+      const int cur = t & 1, k0 = kb + t * BK;
+      // register slot u held step t (already in LDS): refill it with t + S,
+      // past the last step too (those gathers come back invalid), so that
+      // the loads issued per step never depend on a branch
+#pragma unroll
+      for (int q = 0; q < NA; ++q) ra[u][q] = sa.fetch(op, q, tid, m0, k0 + S * BK, M, ke, va[u][q]);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rb[u][q] = sb.fetch(op, q, tid, n0, k0 + S * BK, N, ke, vb[u][q]);
       if (t < nsteps) {
-        const int cur = t & 1, k0 = kb + t * BK;
-        // register slot u held step t (already in LDS): refill it with t + S
-        if (t + S < nsteps) {
-#pragma unroll
-          for (int q = 0; q < NA; ++q) ra[u][q] = sa.fetch(op, q, tid, m0, k0 + S * BK, M, ke);
-#pragma unroll
-          for (int q = 0; q < NB; ++q) rb[u][q] = sb.fetch(op, q, tid, n0, k0 + S * BK, N, ke);
-        }
 #pragma unroll
         for (int ks = 0; ks < BK / MK; ++ks) {
           if (k0 + ks * MK >= ke) break;  // past the end of this K range: nothing to add
@@ -182,12 +206,14 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
         if (t + 1 < nsteps) {
           const int un = (u + 1) % S;  // a constant once the loop is unrolled
 #pragma unroll
-          for (int q = 0; q < NA; ++q) put_tile<Op, TBM>(true, sA[cur ^ 1], tid + 256 * q, ra[un][q]);
+          for (int q = 0; q < NA; ++q)
+            put_tile<Op, TBM>(true, sA[cur ^ 1], tid + 256 * q, keep_if(va[un][q], ra[un][q]));
 #pragma unroll
-          for (int q = 0; q < NB; ++q) put_tile<Op, TBN>(false, sB[cur ^ 1], tid + 256 * q, rb[un][q]);
+          for (int q = 0; q < NB; ++q)
+            put_tile<Op, TBN>(false, sB[cur ^ 1], tid + 256 * q, keep_if(vb[un][q], rb[un][q]));
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
   }
   if constexpr (Op::kStaged) {
@@ -265,7 +291,7 @@ struct ConvFwdOp {
     r.off = (((int64_t)b * g.Hi + r.y) * g.Wi + r.x) * g.Cin;
     return r;
   }
-  __device__ uint4 vec_a(const Row &r, int k0, int koff) const {
+  __device__ const uint4 *ptr_a(const Row &r, int k0, int koff, bool &ok) const {
     int tap, ci;
     if (tap_uniform) {
       tap = k0 / g.Cin;
@@ -277,12 +303,13 @@ struct ConvFwdOp {
     }
     const int dy = tap / 3, dx = tap - 3 * dy;
     const int iy = r.y + dy, ix = r.x + dx;
-    if ((unsigned)iy >= (unsigned)g.Hi || (unsigned)ix >= (unsigned)g.Wi) return make_uint4(0, 0, 0, 0);
-    return *(const uint4 *)&in[r.off + ((int64_t)dy * g.Wi + dx) * g.Cin + ci];
+    ok = (unsigned)iy < (unsigned)g.Hi && (unsigned)ix < (unsigned)g.Wi;
+    return (const uint4 *)(ok ? &in[r.off + ((int64_t)dy * g.Wi + dx) * g.Cin + ci] : in);
   }
   __device__ Row row_b(int n) const { return Row{(int64_t)n * 9 * g.Cin, 0, 0}; }
-  __device__ uint4 vec_b(const Row &r, int k0, int koff) const {
-    return *(const uint4 *)&w[r.off + k0 + koff];
+  __device__ const uint4 *ptr_b(const Row &r, int k0, int koff, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&w[r.off + k0 + koff];
   }
   static constexpr bool kStaged = true;
   __device__ float col(int n) const { return bias ? bias[n] : 0.f; }
@@ -314,7 +341,7 @@ struct ConvDgradOp {
     const int ix = m % g.Wi, t = m / g.Wi, iy = t % g.Hi, b = t / g.Hi;
     return Row{(int64_t)b * g.Ho * g.Wo * g.Cout, iy, ix};
   }
-  __device__ uint4 vec_a(const Row &r, int k0, int koff) const {
+  __device__ const uint4 *ptr_a(const Row &r, int k0, int koff, bool &ok) const {
     int tap, co;
     if (tap_uniform) {
       tap = k0 / g.Cout;
@@ -326,14 +353,14 @@ struct ConvDgradOp {
     }
     const int dy = tap / 3, dx = tap - 3 * dy;
     const int oy2 = r.y + 1 - dy, ox2 = r.x + 1 - dx;
-    if (oy2 < 0 || ox2 < 0 || (oy2 & 1) || (ox2 & 1)) return make_uint4(0, 0, 0, 0);
     const int oy = oy2 >> 1, ox = ox2 >> 1;
-    if (oy >= g.Ho || ox >= g.Wo) return make_uint4(0, 0, 0, 0);
-    return *(const uint4 *)&dout[r.off + ((int64_t)oy * g.Wo + ox) * g.Cout + co];
+    ok = oy2 >= 0 && ox2 >= 0 && !(oy2 & 1) && !(ox2 & 1) && oy < g.Ho && ox < g.Wo;
+    return (const uint4 *)(ok ? &dout[r.off + ((int64_t)oy * g.Wo + ox) * g.Cout + co] : dout);
   }
   __device__ Row row_b(int n) const { return Row{(int64_t)n * 9 * g.Cout, 0, 0}; }
-  __device__ uint4 vec_b(const Row &r, int k0, int koff) const {
-    return *(const uint4 *)&wt[r.off + k0 + koff];
+  __device__ const uint4 *ptr_b(const Row &r, int k0, int koff, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&wt[r.off + k0 + koff];
   }
   static constexpr bool kStaged = true;
   __device__ float col(int) const { return 0.f; }
@@ -354,14 +381,17 @@ struct ConvWgradOp {
   float *part;
   struct Row {};
   // 8 consecutive output channels of pixel p
-  __device__ uint4 a_vecT(int m, int p) const { return *(const uint4 *)&dout[(size_t)p * g.Cout + m]; }
+  __device__ const uint4 *ptr_aT(int m, int p, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&dout[(size_t)p * g.Cout + m];
+  }
   // 8 consecutive (tap, ci) columns of the im2col row of pixel p
-  __device__ uint4 b_vecT(int n, int p) const {
+  __device__ const uint4 *ptr_bT(int n, int p, bool &ok) const {
     const int ox = p % g.Wo, t = p / g.Wo, oy = t % g.Ho, b = t / g.Ho;
     const int tap = n / g.Cin, ci = n - tap * g.Cin;
     const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
-    if (iy < 0 || iy >= g.Hi || ix < 0 || ix >= g.Wi) return make_uint4(0, 0, 0, 0);
-    return *(const uint4 *)&in[(((size_t)b * g.Hi + iy) * g.Wi + ix) * g.Cin + ci];
+    ok = iy >= 0 && iy < g.Hi && ix >= 0 && ix < g.Wi;
+    return (const uint4 *)(ok ? &in[(((size_t)b * g.Hi + iy) * g.Wi + ix) * g.Cin + ci] : in);
   }
   static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int z) const {
@@ -391,8 +421,14 @@ struct LinFwdOp {  // M = B, N = Out, K = In
   typedef LinRow Row;
   __device__ Row row_a(int m) const { return Row{(int64_t)m * g.In}; }
   __device__ Row row_b(int n) const { return Row{(int64_t)n * g.In}; }
-  __device__ uint4 vec_a(const Row &r, int k0, int koff) const { return *(const uint4 *)&x[r.off + k0 + koff]; }
-  __device__ uint4 vec_b(const Row &r, int k0, int koff) const { return *(const uint4 *)&w[r.off + k0 + koff]; }
+  __device__ const uint4 *ptr_a(const Row &r, int k0, int koff, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&x[r.off + k0 + koff];
+  }
+  __device__ const uint4 *ptr_b(const Row &r, int k0, int koff, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&w[r.off + k0 + koff];
+  }
   static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int) const {
     v += bias ? bias[n] : 0.f;
@@ -412,8 +448,14 @@ struct LinDgradOp {  // M = B, N = In, K = Out; wt = W^T [In][Out]
   typedef LinRow Row;
   __device__ Row row_a(int m) const { return Row{(int64_t)m * g.Out}; }
   __device__ Row row_b(int n) const { return Row{(int64_t)n * g.Out}; }
-  __device__ uint4 vec_a(const Row &r, int k0, int koff) const { return *(const uint4 *)&dy[r.off + k0 + koff]; }
-  __device__ uint4 vec_b(const Row &r, int k0, int koff) const { return *(const uint4 *)&wt[r.off + k0 + koff]; }
+  __device__ const uint4 *ptr_a(const Row &r, int k0, int koff, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&dy[r.off + k0 + koff];
+  }
+  __device__ const uint4 *ptr_b(const Row &r, int k0, int koff, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&wt[r.off + k0 + koff];
+  }
   static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int) const {
     const size_t o = (size_t)m * g.In + n;
@@ -429,8 +471,14 @@ struct LinWgradOp {  // M = Out, N = In, K = B; split-K partials
   const bf16 *dy, *x;
   float *part;
   struct Row {};
-  __device__ uint4 a_vecT(int m, int b) const { return *(const uint4 *)&dy[(size_t)b * g.Out + m]; }
-  __device__ uint4 b_vecT(int n, int b) const { return *(const uint4 *)&x[(size_t)b * g.In + n]; }
+  __device__ const uint4 *ptr_aT(int m, int b, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&dy[(size_t)b * g.Out + m];
+  }
+  __device__ const uint4 *ptr_bT(int n, int b, bool &ok) const {
+    ok = true;
+    return (const uint4 *)&x[(size_t)b * g.In + n];
+  }
   static constexpr bool kStaged = false;
   __device__ void store(int m, int n, float v, int z) const {
     part[((size_t)z * g.Out + m) * g.In + n] = v;
@@ -663,6 +711,7 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
       }
     }
   }
+  __syncthreads();  // the whole first-layer patch is in LDS (every wave reads all of it)
   // second layer: MFMA row tiles i = pixels [16 i, 16 i + 16) of the 8 x 16
   // tile (one output row each), columns = this wave's 16 channels
   f32x4 acc[8];
