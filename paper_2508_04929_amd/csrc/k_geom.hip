@@ -265,12 +265,31 @@ k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, co
     g2 = gc[3 * n + 2];
   }
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // the bins of all the block's images, then their list bases (segment
+  // offset plus this block's count of earlier records), requested before
+  // the per-image loop so the loads overlap instead of costing two
+  // round trips per image
+  int kk[kImgPerBinBlock], base[kImgPerBinBlock];
+#pragma unroll
+  for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
+    const int b = b0 + bi;
+    kk[bi] = (n < G.N && b < G.B) ? key[(size_t)b * G.N + n] : -1;
+  }
+#pragma unroll
+  for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
+    // every load is issued (index 0 for an absent record), so none waits
+    // behind a branch
+    const int e = kk[bi] >= 0 ? (b0 + bi) * G.K + kk[bi] : 0;
+    const int o = off[e], c = blk[(size_t)e * nbx + blockIdx.x];
+    base[bi] = o + c;
+  }
+#pragma unroll
   for (int bi = 0; bi < kImgPerBinBlock; ++bi) {
     const int b = b0 + bi;
     if (b >= G.B) break;
     for (int i = threadIdx.x; i < (kBlock / 64) * G.K; i += kBlock) wmask[i] = 0ull;
     __syncthreads();
-    const int k = (n < G.N) ? key[(size_t)b * G.N + n] : -1;
+    const int k = kk[bi];
     if (k >= 0) atomicOr(&wmask[wid * G.K + k], 1ull << lane);
     __syncthreads();
     if (k >= 0) {
@@ -278,8 +297,7 @@ k_bin_scatter(const float4 *gc, const float *rot, const float *shift, Geom G, co
       // same-bin lanes of the earlier waves
       int rank = __popcll(wmask[wid * G.K + k] & below);
       for (int w = 0; w < wid; ++w) rank += __popcll(wmask[w * G.K + k]);
-      const int e = b * G.K + k;
-      const int pos = off[e] + blk[(size_t)e * nbx + blockIdx.x] + rank;
+      const int pos = base[bi] + rank;
       float p0[3], p1[3], tx, ty;
       load_pose(rot, shift, b, p0, p1, tx, ty);
       Proj P;
