@@ -382,13 +382,25 @@ k_chain(const float4 *gc, const float *log_scales, const float *quats, const flo
   float dmu[3] = {0, 0, 0};
   float dS[6] = {0, 0, 0, 0, 0, 0};  // xx xy xz yy yz zz
   float dw_sum = 0.f;                // sum_b dL/dw * w / A  (= dL/dA)
-  for (int b = wv; live && b < G.B; b += 4) {
-    if (key[(size_t)b * G.N + n] < 0) continue;
+  // the image index is uniform across the wave: its pose comes through
+  // scalar loads
+  for (int b = __builtin_amdgcn_readfirstlane(wv); live && b < G.B; b += 4) {
+    // the pose, the key and the moment row are read together (the row
+    // exists for every (image, Gaussian); it holds moments only where the
+    // key is a bin), so an image costs one round trip to memory, not three
     float p0[3], p1[3], tx, ty;
     load_pose(rot, shift, b, p0, p1, tx, ty);
+    const size_t row = (size_t)b * G.N + n;
+    const int kb = key[row];
+    const float2 *m2 = (const float2 *)(mom + row * 6);
+    const float2 ma = m2[0], mb = m2[1], mc = m2[2];
+    // keeps the row's loads ahead of the branch (the compiler would sink
+    // them into it, after the key's round trip)
+    asm volatile("" ::"v"(ma), "v"(mb), "v"(mc));
+    if (kb < 0) continue;
+    const float m[6] = {ma.x, ma.y, mb.x, mb.y, mc.x, mc.y};
     Proj P;
     project_one(g0, g1, make_float2(g2.x, g2.y), p0, p1, tx, ty, G, P);
-    const float *m = mom + ((size_t)b * G.N + n) * 6;
     const ScreenGrad sg = screen_grad(P, m, G.pixel);
     const float dmx = sg.dmx, dmy = sg.dmy, Sxx = sg.Sxx, Sxy = sg.Sxy, Syy = sg.Syy;
     const float m0 = m[0];
