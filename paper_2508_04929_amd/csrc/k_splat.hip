@@ -361,6 +361,19 @@ k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, G
                          gridDim.x * gridDim.y * zsplit);
   const int zz = j % zsplit, t = (j / zsplit) % gridDim.x, b = j / (zsplit * gridDim.x);
   const int ty = t / G.ntx, tx = t % G.ntx;
+  // item ranges of the 3 x 3 owner tiles around this one (empty outside the
+  // image), read once per block rather than per pixel and neighbour
+  __shared__ int2 range[9];
+  if (threadIdx.x < 9) {
+    const int sy = ty + threadIdx.x / 3 - 1, sx = tx + threadIdx.x % 3 - 1;
+    int2 r = make_int2(0, 0);
+    if (sy >= 0 && sy < G.ntx && sx >= 0 && sx < G.ntx) {
+      const int e = b * G.K + sy * G.ntx + sx;
+      r = make_int2(item_off[e], item_off[e + 1]);
+    }
+    range[threadIdx.x] = r;
+  }
+  __syncthreads();
   const int r_lo = ty * G.T, r_hi = min(r_lo + G.T, G.D);
   const int c_lo = tx * G.T, c_hi = min(c_lo + G.T, G.D);
   const int wdt = c_hi - c_lo;
@@ -383,8 +396,8 @@ k_canvas_reduce(const float *partials, const int *item_off, const int4 *items, G
         if (sx < 0 || sx >= G.ntx) continue;
         const int cj = j - (sx * G.T - G.halo);
         if (cj < 0 || cj >= G.C) continue;
-        const int e = b * G.K + sy * G.ntx + sx;
-        const int it0 = item_off[e], it1 = item_off[e + 1];
+        const int2 r = range[3 * (dy + 1) + dx + 1];
+        const int it0 = r.x, it1 = r.y;
         const float *base = partials + (size_t)ri * G.C + cj;
         if (vec) {
           int it = it0;
