@@ -263,7 +263,16 @@ __global__ void __launch_bounds__(kBlock) k_splat_fwd(MultiProb MP) {
     // contiguous beside the list, summed in a fixed order)
     const float *wa = MP.p[p].wabs + itm.z;
     float aw = 0.f;
-    for (int g = threadIdx.x; g < itm.w; g += kBlock) aw += wa[g];
+    // four loads in flight per thread, added in the same order as one at a time
+    int g = threadIdx.x;
+    for (; g + 3 * kBlock < itm.w; g += 4 * kBlock) {
+      const float a0 = wa[g], a1 = wa[g + kBlock], a2 = wa[g + 2 * kBlock], a3 = wa[g + 3 * kBlock];
+      aw += a0;
+      aw += a1;
+      aw += a2;
+      aw += a3;
+    }
+    for (; g < itm.w; g += kBlock) aw += wa[g];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) aw += __shfl_xor(aw, o, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = aw;
@@ -541,10 +550,26 @@ __global__ void __launch_bounds__(kBlock) k_splat_bwd(MultiProb MP) {
     const int clo = max(C0, 0), chi = min(C0 + G.C - 1, G.D - 1);
     const float *src = GQ + (size_t)b * G.D * G.D;
     const float inv_s = 1.f / (float)G.S;
-    for (int q = threadIdx.x; q < G.C * G.S; q += kBlock) {
-      const int r = row_of(q, inv_s), c = q - r * G.S;
-      const int i = R0 + r, j = C0 + c;
-      gq[q] = (c < G.C && i >= 0 && i < G.D && j >= 0 && j < G.D) ? src[(size_t)i * G.D + j] : 0.f;
+    // G_Q of the canvas region into LDS (zero outside the image and in the
+    // row padding): four unconditional loads in flight per thread (outside
+    // the image they read the image's first value, then dropped)
+    const int CS = G.C * G.S;
+    for (int q0 = threadIdx.x; q0 < CS; q0 += 4 * kBlock) {
+      float v[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * kBlock;
+        const int r = row_of(q, inv_s), c = q - r * G.S;
+        const int i = R0 + r, j = C0 + c;
+        ok[u] = q < CS && c < G.C && i >= 0 && i < G.D && j >= 0 && j < G.D;
+        v[u] = src[ok[u] ? (size_t)i * G.D + j : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * kBlock;
+        if (q < CS) gq[q] = ok[u] ? v[u] : 0.f;
+      }
     }
     __syncthreads();
     const int chunk = chunk_len(G, itm.w);
