@@ -23,7 +23,9 @@ __global__ void k_init_attributes(const float *z, int64_t n, float scale_pre, fl
 __global__ void k_train_gather(const float *images, const float *rot, TrainCtfSrc src, int64_t idx,
                                int npix, TrainStage stage, const float *rec_src, float *rec_dst);
 __global__ void k_train_record(const float *src, float *dst);
-__global__ void k_split_gaussians(const float *p, const float *m, const float *v, int64_t n,
-                                  int scale_act, int amp_act, float *q, float *qm, float *qv);
+__global__ void k_split_gaussians(const float *__restrict__ p, const float *__restrict__ m,
+                                  const float *__restrict__ v, int64_t n, int scale_act, int amp_act,
+                                  float *__restrict__ q, float *__restrict__ qm,
+                                  float *__restrict__ qv);
 
 }  // namespace cs

@@ -55,13 +55,38 @@ k_train_gather(const float *images, const float *rot, TrainCtfSrc src, int64_t i
 __device__ __forceinline__ double softplus_d(double x) { return x > 30.0 ? x : log1p(exp(x)); }
 
 __global__ void __launch_bounds__(256)
-k_split_gaussians(const float *p, const float *m, const float *v, int64_t n, int scale_act,
-                  int amp_act, float *q, float *qm, float *qv) {
+k_split_gaussians(const float *__restrict__ p, const float *__restrict__ m,
+                  const float *__restrict__ v, int64_t n, int scale_act, int amp_act,
+                  float *__restrict__ q, float *__restrict__ qm, float *__restrict__ qv) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const int64_t n2 = 2 * n;
-  const float *mu = p + 3 * i, *ls = p + 3 * n + 3 * i, *qt = p + 6 * n + 4 * i;
+  // every input value of this Gaussian is read before anything is written
+  // (the outputs never overlap the inputs: restrict), so the loads are in
+  // flight together
+  float mu[3], ls[3], qt[4], mv[2][11];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    mu[c] = p[3 * i + c];
+    ls[c] = p[3 * n + 3 * i + c];
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) qt[c] = p[6 * n + 4 * i + c];
   const float a = p[10 * n + i];
+  if (qm) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const float *src = t ? v : m;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        mv[t][c] = src[3 * i + c];
+        mv[t][3 + c] = src[3 * n + 3 * i + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) mv[t][6 + c] = src[6 * n + 4 * i + c];
+      mv[t][10] = src[10 * n + i];
+    }
+  }
   int k = 0;
   float lk = ls[0];
   if (ls[1] > lk) { k = 1; lk = ls[1]; }
@@ -98,19 +123,17 @@ k_split_gaussians(const float *p, const float *m, const float *v, int64_t n, int
     q[10 * n2 + j] = a_new;
     if (qm) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        qm[3 * j + c] = m[3 * i + c];
-        qv[3 * j + c] = v[3 * i + c];
-        qm[3 * n2 + 3 * j + c] = m[3 * n + 3 * i + c];
-        qv[3 * n2 + 3 * j + c] = v[3 * n + 3 * i + c];
-      }
+      for (int t = 0; t < 2; ++t) {
+        float *dst = t ? qv : qm;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        qm[6 * n2 + 4 * j + c] = m[6 * n + 4 * i + c];
-        qv[6 * n2 + 4 * j + c] = v[6 * n + 4 * i + c];
+        for (int c = 0; c < 3; ++c) {
+          dst[3 * j + c] = mv[t][c];
+          dst[3 * n2 + 3 * j + c] = mv[t][3 + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dst[6 * n2 + 4 * j + c] = mv[t][6 + c];
+        dst[10 * n2 + j] = mv[t][10];
       }
-      qm[10 * n2 + j] = m[10 * n + i];
-      qv[10 * n2 + j] = v[10 * n + i];
     }
   }
 }

@@ -179,11 +179,16 @@ int cs_split_gaussians(cs_ctx *ctx, const float *params, const float *adam_m, co
     const char *x = (const char *)a, *y = (const char *)b;
     return a && b && x < y + nb && y < x + na;
   };
-  if (overlap(params, in_b, out_params, out_b) ||
-      (mom && (overlap(adam_m, in_b, out_m, out_b) || overlap(adam_v, in_b, out_v, out_b) ||
-               overlap(out_params, out_b, out_m, out_b) || overlap(out_params, out_b, out_v, out_b) ||
-               overlap(out_m, out_b, out_v, out_b))))
-    return fail(ctx, CS_ERR_INVALID_ARG, "outputs must not overlap the inputs or each other");
+  // no output may overlap an input or another output (the kernel reads its
+  // inputs through restrict pointers)
+  const void *ins[3] = {params, adam_m, adam_v};
+  const void *outs[3] = {out_params, out_m, out_v};
+  bool bad = false;
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b) bad = bad || overlap(ins[a], in_b, outs[b], out_b);
+    for (int b = a + 1; b < 3; ++b) bad = bad || overlap(outs[a], out_b, outs[b], out_b);
+  }
+  if (bad) return fail(ctx, CS_ERR_INVALID_ARG, "outputs must not overlap the inputs or each other");
   HIPCHK(hipSetDevice(ctx->device));
   TLAUNCH(k_split_gaussians, dim3(cdivt(n, 256)), dim3(256), 0, (hipStream_t)stream, params,
           adam_m, adam_v, n, scale_act, amp_act, out_params, mom ? out_m : nullptr,

@@ -80,6 +80,12 @@ def test_split_rejects_overlap_and_partial_moments(gpu_lib):
     q = torch.zeros(11 * 8 * 2, device="cuda")
     assert L.cs_split_gaussians(ctx, base, base, None, 8, 1, 1, q.data_ptr(), None, None,
                                 None) == -1
+    # an output moment array overlapping an input of another kind (the
+    # parameters): every input is read through a restrict pointer
+    mo = torch.zeros(11 * 8 * 2 * 3, device="cuda")
+    m_in, v_in = mo.data_ptr(), mo.data_ptr() + 4 * 88
+    assert L.cs_split_gaussians(ctx, base, m_in, v_in, 8, 1, 1, q.data_ptr(), base,
+                                mo.data_ptr() + 4 * 176, None) == -1
 
 
 def test_training_continues_across_a_split(gpu_lib):
