@@ -529,13 +529,40 @@ k_pose_grad_part(const float4 *gc, const float *rot, const float *shift, Geom G,
     float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // t_x, t_y, P_0 (3), P_1 (3)
     float p0[3], p1[3], tx, ty;
     load_pose(rot, shift, b, p0, p1, tx, ty);
+    // the keys and moment rows of the thread's Gaussians, all requested
+    // before the first branch (indices past N read row 0 and are dropped)
+    int kb[kPoseGauss];
+    float2 mv[kPoseGauss][3];
 #pragma unroll
     for (int j = 0; j < kPoseGauss; ++j) {
       const int n = nbase + j * kBlock;
-      if (n < G.N && key[(size_t)b * G.N + n] >= 0) {
+      const size_t row = (size_t)b * G.N + (n < G.N ? n : 0);
+      kb[j] = key[row];
+      const float2 *m2 = (const float2 *)(mom + row * 6);
+      mv[j][0] = m2[0];
+      mv[j][1] = m2[1];
+      mv[j][2] = m2[2];
+    }
+    bool use[kPoseGauss];
+    float mrow[kPoseGauss][6];
+#pragma unroll
+    for (int j = 0; j < kPoseGauss; ++j) {
+      // keeps the loads ahead of the branches below (the compiler would
+      // sink each into its branch, one round trip per Gaussian)
+      asm volatile("" ::"v"(mv[j][0]), "v"(mv[j][1]), "v"(mv[j][2]));
+      use[j] = nbase + j * kBlock < G.N && kb[j] >= 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        mrow[j][2 * c] = mv[j][c].x;
+        mrow[j][2 * c + 1] = mv[j][c].y;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPoseGauss; ++j) {
+      if (use[j]) {
         Proj P;
         project_one(g0[j], g1[j], make_float2(g2[j].x, g2[j].y), p0, p1, tx, ty, G, P);
-        const ScreenGrad sg = screen_grad(P, mom + ((size_t)b * G.N + n) * 6, G.pixel);
+        const ScreenGrad sg = screen_grad(P, mrow[j], G.pixel);
         // Sigma p0, Sigma p1 (Sigma symmetric: the rows of P Sigma)
         const float4 a = g1[j], c = g2[j];
         const float sp0[3] = {a.x * p0[0] + a.y * p0[1] + a.z * p0[2],
