@@ -117,3 +117,24 @@ def test_split_of_a_single_gaussian(gpu_lib):
     out, _, _ = gpu_lib.split_gaussians(dev(theta), scale_act="exp", amp_act="identity")
     ref = o_den.split_flat(theta, 1)
     np.testing.assert_allclose(host(out), ref, rtol=3e-7, atol=1e-7)
+
+
+def test_image_count_limit_is_reported(gpu_lib):
+    """Launches put the image index in the grid's y dimension: more than
+    65,535 images in one call is refused with an error before any work, and
+    65,535 itself is accepted."""
+    announce("image count limit (65,535 per call)")
+    rng = np.random.default_rng(31)
+    g = inputs.mixture_anisotropic(rng, 4, 5.0)
+    for B, ok in ((65536, False), (65535, True)):
+        rot = torch.eye(3, device="cuda").expand(B, 3, 3).contiguous()
+        shift = torch.zeros(B, 2, device="cuda")
+        if ok:
+            out = gpu_lib.render(**mixture_args(g), rot=rot, shift=shift, D=8, pixel=2.0)
+            torch.cuda.synchronize()
+            assert torch.isfinite(out).all()
+            # every image has the same pose: all equal the first
+            assert torch.equal(out, out[:1].expand_as(out))
+        else:
+            with pytest.raises(binding.CryoSplatError, match="65535"):
+                gpu_lib.render(**mixture_args(g), rot=rot, shift=shift, D=8, pixel=2.0)
