@@ -666,13 +666,27 @@ k_conv12_fwd(const bf16 *in0, const bf16 *w1, const float *b1, const bf16 *w2, c
   const f32x4 bf0 = conv1_bias(b1, 32, 0, lane), bf1 = conv1_bias(b1, 32, 16, lane);
   // input patch rows 4 oy0 - 3 .., columns 4 ox0 - 3 .. 4 ox0 + 63: 16-byte
   // loads of the aligned columns 4 ox0 - 8 .. 4 ox0 + 63 (9 per row)
+  // (both loads of a thread are issued before either is used: outside the
+  // image they read the tensor's first 16 bytes, replaced by zeros)
   const int iy0 = 4 * oy0 - 3, cx0 = 4 * ox0 - 8;
-  for (int q = tid; q < C12_IY * 9; q += 256) {
+  static_assert(C12_IY * 9 <= 2 * 256, "two patch loads per thread");
+  uint4 pv[2];
+  bool pok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = tid + 256 * h;
     const int ry = q / 9, t = q - ry * 9;
     const int yy = iy0 + ry, xx = cx0 + 8 * t;
+    pok[h] = q < C12_IY * 9 && yy >= 0 && yy < H0 && xx >= 0 && xx < H0;
+    pv[h] = *(const uint4 *)(pok[h] ? &in0[((size_t)b * H0 + yy) * H0 + xx] : in0);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int q = tid + 256 * h;
+    if (q >= C12_IY * 9) continue;
+    const int ry = q / 9, t = q - ry * 9;
     Vec8 v;
-    v.u = make_uint4(0, 0, 0, 0);
-    if (yy >= 0 && yy < H0 && xx >= 0 && xx < H0) v.u = *(const uint4 *)&in0[((size_t)b * H0 + yy) * H0 + xx];
+    v.u = pok[h] ? pv[h] : make_uint4(0, 0, 0, 0);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int c = 8 * t + e - 5;  // patch column of input column xx + e
