@@ -18,6 +18,9 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 __device__ __forceinline__ float bf2f(bf16 v) { return __uint_as_float((unsigned)v << 16); }
 
+// 1.0 in bfloat16: what an absent ReLU mask reads
+__device__ const bf16 kBf16One = 0x3f80;
+
 // Round to nearest even (the hardware conversion, v_cvt_pk_bf16_f32).
 __device__ __forceinline__ bf16 f2bf(float x) { return __builtin_bit_cast(bf16, (__bf16)x); }
 
@@ -126,13 +129,23 @@ __device__ __forceinline__ uint4 keep_if(bool valid, uint4 v) {
   return valid ? v : make_uint4(0, 0, 0, 0);
 }
 
+// Keeps loaded values ahead of the branches that use them: without it the
+// compiler sinks each load into its branch, one round trip per element.
+template <int TI>
+__device__ __forceinline__ void pin_loads(const float (&v)[TI][4]) {
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) asm volatile("" ::"v"(v[i][r]));
+}
+
 // TBM x TBN block tile, four waves in 2 x 2, each wave (TBM/2) x (TBN/2) as
 // 16 x 16 MFMA tiles; K steps of 32 double-buffered through LDS (operands
 // prefetched into registers while the current step computes).  The tile
 // shape changes only the partition: every output accumulates its K steps in
 // the same order, so results do not depend on it.
 template <class Op, int TBM, int TBN>
-__global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kchunk) {
+__global__ void __launch_bounds__(256, 3) k_gemm(Op op, int M, int N, int K, int kchunk) {
   constexpr int TI = TBM / 32, TJ = TBN / 32;
   constexpr int NA = TBM * BK / 8 / 256, NB = TBN * BK / 8 / 256;
   static_assert(NA >= 1 && NB >= 1, "tile");
@@ -225,6 +238,17 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
     for (int j = 0; j < TJ; ++j) {
       const int nl = wn + j * 16 + (lane & 15), n = n0 + nl;
       const float cv = n < N ? op.col(n) : 0.f;
+      // the column's per-element epilogue inputs, requested together (at
+      // clamped indices, so no load waits behind a branch)
+      float ein[TI][4];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+          ein[i][r] = op.epi_in(min(m, M - 1), min(n, N - 1));
+        }
+      pin_loads(ein);
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -232,7 +256,7 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
           const int ml = wm + i * 16 + (lane >> 4) * 4 + r, m = m0 + ml;
           float v = 0.f;
           if (m < M && n < N) {
-            v = op.epi(m, n, acc[i][j][r], cv);
+            v = op.epi(acc[i][j][r], cv, ein[i][r]);
             if (op.f32_out()) op.f32_out()[(size_t)m * op.ldo() + n] = v;
           }
           sC[ml][nl] = f2bf(v);
@@ -248,15 +272,25 @@ __global__ void __launch_bounds__(256) k_gemm(Op op, int M, int N, int K, int kc
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
+    for (int j = 0; j < TJ; ++j) {
+      const int n = n0 + wn + j * 16 + (lane & 15);
+      float ein[TI][4];  // as in the staged epilogue
 #pragma unroll
-      for (int j = 0; j < TJ; ++j)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
-          const int n = n0 + wn + j * 16 + (lane & 15);
-          if (m < M && n < N) op.store(m, n, acc[i][j][r], blockIdx.z);
+          ein[i][r] = op.epi_in(min(m, M - 1), min(n, N - 1));
         }
+      pin_loads(ein);
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+          if (m < M && n < N) op.store(m, n, acc[i][j][r], blockIdx.z, ein[i][r]);
+        }
+    }
   }
 }
 
@@ -313,7 +347,8 @@ struct ConvFwdOp {
   }
   static constexpr bool kStaged = true;
   __device__ float col(int n) const { return bias ? bias[n] : 0.f; }
-  __device__ float epi(int, int, float v, float cv) const {
+  __device__ float epi_in(int, int) const { return 0.f; }
+  __device__ float epi(float v, float cv, float) const {
     v += cv;
     return relu ? fmaxf(v, 0.f) : v;
   }
@@ -364,9 +399,12 @@ struct ConvDgradOp {
   }
   static constexpr bool kStaged = true;
   __device__ float col(int) const { return 0.f; }
-  __device__ float epi(int m, int n, float v, float) const {
-    return (act_in && !(bf2f(act_in[(size_t)m * g.Cin + n]) > 0.f)) ? 0.f : v;
+  // the input activation (1 without a mask): the gradient passes where it
+  // is > 0; a pointer select, not a branch, so the loads need no branch
+  __device__ float epi_in(int m, int n) const {
+    return bf2f(*(act_in ? act_in + (size_t)m * g.Cin + n : &kBf16One));
   }
+  __device__ float epi(float v, float, float a) const { return a > 0.f ? v : 0.f; }
   __device__ bf16 *bf16_out() const { return din; }
   __device__ float *f32_out() const { return din32; }
   __device__ int64_t ldo() const { return g.Cin; }
@@ -394,7 +432,8 @@ struct ConvWgradOp {
     return (const uint4 *)(ok ? &in[(((size_t)b * g.Hi + iy) * g.Wi + ix) * g.Cin + ci] : in);
   }
   static constexpr bool kStaged = false;
-  __device__ void store(int m, int n, float v, int z) const {
+  __device__ float epi_in(int, int) const { return 0.f; }
+  __device__ void store(int m, int n, float v, int z, float) const {
     part[((size_t)z * g.Cout + m) * 9 * g.Cin + n] = v;
   }
 };
@@ -430,7 +469,8 @@ struct LinFwdOp {  // M = B, N = Out, K = In
     return (const uint4 *)&w[r.off + k0 + koff];
   }
   static constexpr bool kStaged = false;
-  __device__ void store(int m, int n, float v, int) const {
+  __device__ float epi_in(int, int) const { return 0.f; }
+  __device__ void store(int m, int n, float v, int, float) const {
     v += bias ? bias[n] : 0.f;
     if (relu) v = fmaxf(v, 0.f);
     const size_t o = (size_t)m * g.Out + n;
@@ -457,9 +497,14 @@ struct LinDgradOp {  // M = B, N = In, K = Out; wt = W^T [In][Out]
     return (const uint4 *)&wt[r.off + k0 + koff];
   }
   static constexpr bool kStaged = false;
-  __device__ void store(int m, int n, float v, int) const {
+  // the layer's input activation (1 without a mask): the gradient passes
+  // where it is > 0 (a pointer select, as in ConvDgradOp)
+  __device__ float epi_in(int m, int n) const {
+    return bf2f(*(x_act ? x_act + (size_t)m * g.In + n : &kBf16One));
+  }
+  __device__ void store(int m, int n, float v, int, float a) const {
     const size_t o = (size_t)m * g.In + n;
-    if (x_act && !(bf2f(x_act[o]) > 0.f)) v = 0.f;
+    if (!(a > 0.f)) v = 0.f;
     if (dx32) dx32[o] = v;
     dx[o] = f2bf(v);
   }
@@ -480,7 +525,8 @@ struct LinWgradOp {  // M = Out, N = In, K = B; split-K partials
     return (const uint4 *)&x[(size_t)b * g.In + n];
   }
   static constexpr bool kStaged = false;
-  __device__ void store(int m, int n, float v, int z) const {
+  __device__ float epi_in(int, int) const { return 0.f; }
+  __device__ void store(int m, int n, float v, int z, float) const {
     part[((size_t)z * g.Out + m) * g.In + n] = v;
   }
 };
