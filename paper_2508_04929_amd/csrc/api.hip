@@ -530,8 +530,11 @@ int fft_setup(cs_ctx *ctx, const Geom &G, const float2 *tw, FftLaunch &F) {
 
 int launch_ctf_table(cs_ctx *ctx, const Plan &P, hipStream_t st) {
   const Geom &G = P.G;
-  const size_t n = (size_t)G.B * G.D * (G.D / 2 + 1);
-  TLAUNCH(k_ctf_table, dim3(cdiv(n, 256)), dim3(256), 0, st, G.D, ctf_pixel(P.ctf, G.pixel),
+  // one grid row per image; a few entries per thread where there are
+  // enough images to fill the chip
+  const size_t per = (size_t)G.D * (G.D / 2 + 1);
+  const size_t ept = G.B >= 16 ? 8 : 1;
+  TLAUNCH(k_ctf_table, dim3(cdiv(per, 256 * ept), G.B), dim3(256), 0, st, G.D, ctf_pixel(P.ctf, G.pixel),
           make_ctf(P.ctf), G.B,
           (float *)(P.ws + P.L.ctf));
   return CS_OK;

@@ -13,7 +13,7 @@ namespace cs {
 // over the two mirror frequencies, which keeps H^ exactly even.
 // ---------------------------------------------------------------------------
 __device__ inline double ctf_at(double sx, double sy, const CtfDev &c, double du, double dv,
-                         double c2a, double s2a, double ph) {
+                         double c2a, double s2a, double ph, double amp_s) {
   const double s2 = sx * sx + sy * sy;
   double df = 0.5 * (du + dv);
   if (s2 > 0.0 && du != dv) {
@@ -27,7 +27,7 @@ __device__ inline double ctf_at(double sx, double sy, const CtfDev &c, double du
   const float red = (float)((turns - rint(turns)) * (2.0 * M_PI));
   float sn, cs;
   sincosf(red, &sn, &cs);
-  double h = -(sqrt(1.0 - c.w * c.w) * (double)sn + c.w * (double)cs);
+  double h = -(amp_s * (double)sn + c.w * (double)cs);
   if (c.bfactor != 0.0) h *= exp(-0.25 * c.bfactor * s2);
   return h;
 }
@@ -51,23 +51,28 @@ __device__ inline CtfParticle ctf_particle(const CtfDev &c, int b) {
   return q;
 }
 
-__device__ inline float ctf_value(int ky, int kx, int L, float pixel, const CtfDev &c,
-                                  const CtfParticle &q) {
-  const int half = L / 2;
-  const double inv = 1.0 / ((double)L * (double)pixel);
-  const int fkx = (kx < (L + 1) / 2) ? kx : kx - L;
-  const int fky = (ky < (L + 1) / 2) ? ky : ky - L;
-  const double sx = fkx * inv, sy = -fky * inv;
-  double h = ctf_at(sx, sy, c, q.du, q.dv, q.c2a, q.s2a, q.ph);
-  if ((L % 2 == 0) && (kx == half || ky == half)) {
-    const double mx = (kx == half) ? -sx : sx, my = (ky == half) ? -sy : sy;
-    h = 0.5 * (h + ctf_at(mx, my, c, q.du, q.dv, q.c2a, q.s2a, q.ph));
-  }
-  return (float)h;
+// Constants of a CTF grid shared by all its values: the frequency step
+// 1 / (L p) and the phase-contrast weight sqrt(1 - w^2).
+struct CtfGrid {
+  double inv, amp_s;
+};
+
+__device__ inline CtfGrid ctf_grid(int L, float pixel, const CtfDev &c) {
+  return CtfGrid{1.0 / ((double)L * (double)pixel), sqrt(1.0 - c.w * c.w)};
 }
 
-__device__ inline float ctf_grid_value(int ky, int kx, int L, float pixel, const CtfDev &c, int b) {
-  return ctf_value(ky, kx, L, pixel, c, ctf_particle(c, b));
+__device__ inline float ctf_value(int ky, int kx, int L, const CtfGrid &g, const CtfDev &c,
+                                  const CtfParticle &q) {
+  const int half = L / 2;
+  const int fkx = (kx < (L + 1) / 2) ? kx : kx - L;
+  const int fky = (ky < (L + 1) / 2) ? ky : ky - L;
+  const double sx = fkx * g.inv, sy = -fky * g.inv;
+  double h = ctf_at(sx, sy, c, q.du, q.dv, q.c2a, q.s2a, q.ph, g.amp_s);
+  if ((L % 2 == 0) && (kx == half || ky == half)) {
+    const double mx = (kx == half) ? -sx : sx, my = (ky == half) ? -sy : sy;
+    h = 0.5 * (h + ctf_at(mx, my, c, q.du, q.dv, q.c2a, q.s2a, q.ph, g.amp_s));
+  }
+  return (float)h;
 }
 
 }  // namespace cs

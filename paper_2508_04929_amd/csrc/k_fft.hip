@@ -138,15 +138,26 @@ k_fft_rows_fwd(const float *src, FftPlan P, const float2 *tw, int B, float2 *spe
 // H^ / D^2 on the half-spectrum grid [B][D][D/2+1], once per call.
 __global__ void __launch_bounds__(256)
 k_ctf_table(int L, float pixel, CtfDev ctf, int B, float *table) {
+  // grid rows walk the images (b = blockIdx.y, blockIdx.y + gridDim.y, ...);
+  // a thread fills entries blockIdx.x * 256 + threadIdx.x + k * gridDim.x *
+  // 256 of an image with its constants (defocus, astigmatism angle, phase,
+  // frequency step) evaluated once
   const int Dh = L / 2 + 1;
-  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
-  const size_t per = (size_t)L * Dh;
-  if (idx >= per * B) return;
-  const int b = (int)(idx / per);
-  const int r = (int)(idx % per);
-  const int ky = r / Dh, kx = r % Dh;
+  const int per = L * Dh;
   const float norm = 1.f / ((float)L * (float)L);
-  table[idx] = (ctf.enabled ? ctf_grid_value(ky, kx, L, pixel, ctf, b) : 1.f) * norm;
+  const CtfGrid g = ctf_grid(L, pixel, ctf);
+  for (int b = blockIdx.y; b < B; b += gridDim.y) {
+    float *row = table + (size_t)b * per;
+    if (!ctf.enabled) {
+      for (int r = blockIdx.x * 256 + threadIdx.x; r < per; r += gridDim.x * 256) row[r] = norm;
+      continue;
+    }
+    const CtfParticle q = ctf_particle(ctf, b);
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < per; r += gridDim.x * 256) {
+      const int ky = r / Dh, kx = r % Dh;
+      row[r] = ctf_value(ky, kx, L, g, ctf, q) * norm;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -124,8 +124,12 @@ int ctf_filter_into(cs_ctx *ctx, int D, float pixel, const float *Y, const cs_ct
   const float2 *tw = nullptr;
   int rc = get_twiddles(ctx, D, &tw);
   if (rc) return rc;
-  const size_t n = (size_t)P * D * Dh;
-  hipLaunchKernelGGL(k_ctf_table, dim3(cdivu(n, 256)), dim3(256), 0, st, D, ctf_pixel(ctf, pixel),
+  // one grid row per particle (the kernel strides rows beyond 65535), a few
+  // entries per thread where there are enough particles to fill the chip
+  const size_t per = (size_t)D * Dh;
+  const size_t ept = P >= 16 ? 8 : 1;
+  const unsigned rows = (unsigned)(P < 65535 ? P : 65535);
+  hipLaunchKernelGGL(k_ctf_table, dim3(cdivu(per, 256 * ept), rows), dim3(256), 0, st, D, ctf_pixel(ctf, pixel),
                      make_ctf(ctf), P,
                      table);
   LAUNCHCHK("k_ctf_table");
