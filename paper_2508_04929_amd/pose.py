@@ -249,7 +249,7 @@ def literal_grid_search(lib, gd, image, ctf_one: binding.Ctf, grid_rot: torch.Te
 def run_c5(lib, *, n_train=200000, n_test=8192, epochs=12, batch=256, lr=1e-3, gamma=0.85,
            lam=0.1, snr_db=-20.0, seed=5, coarse=(4, 24), fine=(8, 48), shift_radius=2,
            stages=((0, 6, 2), (1, 4, 2)), matched_filter=True, chunks=(2048, 4096, 8192),
-           literal_particles=2, stage_sweep=(), use_graphs=True, n_val=2048,
+           literal_particles=2, stage_sweep=(), use_graphs=True, n_val=8192,
            fallback_margin_deg=1.0, log=print):
     """The learned-pose experiment: returns angular errors and throughputs.
 
